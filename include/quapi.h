@@ -1,0 +1,177 @@
+/*
+ * quapi.h -- C ABI of the MI355X (gfx950) path-propagation library for
+ * MACGIC-iQUAPI (mask-assisted coarse-graining of influence coefficients,
+ * iterative quasi-adiabatic propagator path integral).
+ *
+ * The library propagates the augmented reduced density tensor of a quantum
+ * system bilinearly coupled to a harmonic bath (Sec. 2, eqs. tot_ham,
+ * quapi_red_rho, SysP, inf_fun).  The tensor is a sparse set of paths: each
+ * path is the sequence of forward/backward state pairs over the memory window
+ * (dk_max points) plus a complex weight.  One time step (Sec. 2.1, Sec. 3.1,
+ * Sec. 3.2.1):
+ *   1. merge the stored paths that agree on the mask positions (pre-merging on
+ *      the reduced mask {mask[i]-1 : i>=1}, or post-merging on the mask);
+ *      a group keeps the sum of the member weights and, as representative
+ *      history, the member of largest |w|;
+ *   2. extend every group by every forward/backward pair: weight times the
+ *      short-time propagator element (eq. SysP) times the influence factor of
+ *      the new point with the points of the window (eq. inf_fun, lags 0..dk_max);
+ *   3. drop children whose |w| is below theta (Sec. 2.1, path filtering);
+ *   4. add the survivors to rho(t) (Sec. 3.2.1).
+ * All device memory is owned by the library; every step runs as HIP kernels
+ * on one stream without host synchronisation.
+ *
+ * Conventions (all functions):
+ *   - return QUAPI_OK (0) or a negative QUAPI_E* code; quapi_strerror() names it;
+ *   - a context is used by one host thread at a time; there is no global state;
+ *   - complex numbers are quapi_c64 {re, im}; matrices are row-major;
+ *   - pair index p = a*M + b for forward state a and backward state b;
+ *   - hbar = 1.
+ */
+#ifndef QUAPI_H
+#define QUAPI_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { double re, im; } quapi_c64;
+
+#define QUAPI_OK            0
+#define QUAPI_EINVAL       -1   /* invalid argument                                   */
+#define QUAPI_ENOMEM       -2   /* device allocation failed or group capacity exceeded */
+#define QUAPI_EDEVICE      -3   /* HIP runtime error or kernel-reported fault          */
+#define QUAPI_ESTATE       -4   /* call not valid in the current state                 */
+#define QUAPI_EUNSUPPORTED -5   /* valid input this build does not handle              */
+
+#define QUAPI_PRE   0           /* pre-merging (Sec. 3.1): merge on {mask[i]-1 : i>=1} before extending */
+#define QUAPI_POST  1           /* post-merging (Sec. 2.1): merge the children on the mask              */
+
+typedef struct quapi_ctx quapi_ctx;
+
+/* Problem definition, copied by quapi_create (the caller keeps ownership of
+ * every pointer and may free it after the call). */
+typedef struct {
+    int M;                    /* number of system (DVR) states, 2..4                                    */
+    const quapi_c64* H;       /* M*M Hermitian system Hamiltonian H_S (eq. tot_ham), used as given;     */
+                              /* rejected if |H_ij - conj(H_ji)| > 1e-12 max(1, max|H|)                  */
+    const double* q;          /* M coupling eigenvalues q_i of the DVR states (eq. tot_ham)             */
+    double dt;                /* Trotter time step, > 0                                                 */
+    int dk_max;               /* memory length K (Sec. 2): a stored path holds K points, lags 0..K-1;   */
+                              /* the new point couples to lags 0..K                                     */
+    const quapi_c64* eta;     /* 3*(K+1) influence coefficients, three columns of K+1 lags:             */
+                              /*  eta[0*(K+1)+d]  both points interior (window dt),                     */
+                              /*  eta[1*(K+1)+d]  one point is the initial or final point (window dt/2),*/
+                              /*  eta[2*(K+1)+d]  initial x final point (d >= 1);                       */
+                              /* eta[1*(K+1)+0] is the end-point self term (eq. inf_fun)                 */
+    const int* mask;          /* MACGIC mask (Sec. 2.1): n_mask sorted lags, mask[0]=0, mask[1]=1,      */
+                              /* mask[n_mask-1] <= K-1; NULL: every lag 0..K-1                          */
+    int n_mask;
+    double theta;             /* filter: drop a child when |w|^2 < theta^2; 0 disables                  */
+    const quapi_c64* rho0;    /* M*M initial reduced density matrix                                     */
+    int mode;                 /* QUAPI_PRE or QUAPI_POST                                                */
+    int qbits;                /* representative choice compares |w|^2 = re*re + im*im (no fused         */
+                              /* multiply-add) with its low qbits mantissa bits cleared; equal values    */
+                              /* go to the history that is smaller read from the oldest point.          */
+                              /* < 0: default 32                                                        */
+    long long max_groups;     /* cap on stored groups that share their newest point; 0: 2^25          */
+    int max_steps;            /* initial capacity of the rho(t) history; grows on demand; <= 0: 1024    */
+    void* stream;             /* hipStream_t to run on (e.g. a torch stream); NULL: a library stream   */
+} quapi_params;
+
+/* Per-step counters, available for every step t >= 1 that has completed. */
+typedef struct {
+    int t;
+    long long n_groups;       /* groups extended at step t                                              */
+    long long n_children;     /* n_groups * M^2 (path-steps of step t)                                  */
+    long long n_survivors;    /* children with |w| >= theta                                             */
+    long long n_stored;       /* groups stored after step t (the groups step t+1 extends)               */
+    double dropped_abs;       /* sum of |w| over the filtered children                                  */
+} quapi_stepstat_t;
+
+/* Layout facts of a context (for accounting and tests). */
+typedef struct {
+    int M, P, K, L;           /* P = M*M pairs; L = key length in points (merge positions 0..L-1)     */
+    int bits_per_point;       /* history bits per point                                                 */
+    int record_bytes;         /* bytes of one stored group: 8 key + 8 history tail + 16 weight          */
+    long long capacity;       /* maximum number of stored groups                                        */
+    size_t device_bytes;      /* device memory held by the context                                      */
+} quapi_info_t;
+
+/* Create a context and its initial state t = 0 (one path per nonzero
+ * element of rho0, weighted by the initial point's self term).
+ * Errors: EINVAL (bad argument), EUNSUPPORTED (a mask whose merge positions
+ * are not 0..L-1 with L >= 2, or M > 4), ENOMEM, EDEVICE.  *out is NULL on error. */
+int quapi_create(const quapi_params* p, quapi_ctx** out);
+
+/* Enqueue n_steps time steps on the context's stream; returns without waiting.
+ * Errors: EINVAL (n_steps < 0), ESTATE (a previous step failed), ENOMEM
+ * (history growth), EDEVICE.  A capacity overflow inside a step is reported by
+ * the next synchronising call; the context then stays at the last complete step. */
+int quapi_step(quapi_ctx* c, int n_steps);
+
+/* Wait for the enqueued steps; returns the first error a step reported. */
+int quapi_sync(quapi_ctx* c);
+
+/* Current time step (number of completed steps; synchronises). */
+int quapi_time(quapi_ctx* c, int* t_out);
+
+/* rho(t) for 0 <= t <= current step into caller-owned rho_out[M*M] (synchronises). */
+int quapi_rho(quapi_ctx* c, int t, quapi_c64* rho_out);
+
+/* rho(t0 .. t0+n-1) into caller-owned out[n*M*M] (synchronises). */
+int quapi_rho_history(quapi_ctx* c, int t0, int n, quapi_c64* out);
+
+/* Counters of steps t0 .. t0+n-1 (t0 >= 1) into caller-owned out[n] (synchronises). */
+int quapi_step_stats(quapi_ctx* c, int t0, int n, quapi_stepstat_t* out);
+
+/* The stored groups (the groups the next step extends), sorted by merge key:
+ * hist[i*K + j] = pair index of group i at lag j (0 for lags the paths do not
+ * yet hold), w[i] = group amplitude.  Writes min(n, cap) groups; *n_out = n.
+ * hist or w may be NULL with cap = 0 to query n (synchronises). */
+int quapi_groups(quapi_ctx* c, long long cap, unsigned char* hist, quapi_c64* w,
+                 long long* n_out);
+
+/* Return to t = 0 with the initial state (tables and buffers are kept). */
+int quapi_reset(quapi_ctx* c);
+
+int quapi_info(quapi_ctx* c, quapi_info_t* out);
+
+/* The hipStream_t the context runs on. */
+void* quapi_stream(quapi_ctx* c);
+
+const char* quapi_strerror(int code);
+
+/* Free the context and its device memory (synchronises first).  NULL is a no-op. */
+void quapi_destroy(quapi_ctx* c);
+
+/* ---------------------------------------------------------------- host utilities */
+
+/* Spectral density of eq. SD as an Ohmic part plus Brownian-oscillator peaks:
+ *   J(w) = (pi/2) ohmic_alpha w exp(-w/ohmic_wc)
+ *        + sum_k 2 lam_k gam_k w0_k^2 w / ((w0_k^2 - w^2)^2 + gam_k^2 w^2),
+ * peaks[3k..3k+2] = (w0_k, gam_k, lam_k) with lam_k = (1/pi) int J_k(w)/w dw. */
+typedef struct {
+    double ohmic_alpha, ohmic_wc;
+    int n_peaks;
+    const double* peaks;
+} quapi_bath;
+
+/* eta columns (layout of quapi_params.eta) for the bath at inverse temperature
+ * beta, step dt and memory dk_max: integrals of the bath response function
+ * over the Trotter windows of the two points (interior: dt; initial/final
+ * point: dt/2), from g(t) = int_0^t int_0^t' alpha.  Host only, no GPU needed.
+ * Errors: EINVAL. */
+int quapi_eta(const quapi_bath* bath, double beta, double dt, int dk_max, quapi_c64* eta_out);
+
+/* U = exp(-i H dt) (M*M, row-major) as the library computes it, by a Jacobi
+ * eigendecomposition.  Host only.  Errors: EINVAL (M out of 1..8, non-Hermitian H). */
+int quapi_propagator(int M, const quapi_c64* H, double dt, quapi_c64* U_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QUAPI_H */

@@ -1,0 +1,518 @@
+// C ABI of the path-propagation library: context, host tables, device
+// buffers and the step loop.  See include/quapi.h for the contract.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/quapi.h"
+#include "quapi_host.h"
+
+using quapi_dev::GroupBuf;
+using quapi_dev::StepArgs;
+using quapi_dev::StepStatsDev;
+using quapi_dev::TableLayout;
+using quapi_dev::TilePartial;
+
+struct quapi_ctx {
+    int M = 0, P = 0, K = 0, L = 0, bits = 0, mode = 0, qbits = 32;
+    double dt = 0, theta = 0;
+    long long cap = 0;           // groups per run
+    int max_tiles = 0;
+    int grid = 0;
+    std::vector<double> tables;  // host copy of the device tables
+    std::vector<double> rho0;    // 2*P
+    std::vector<unsigned long long> init_key, init_tail;
+    std::vector<double2> init_w;
+    std::vector<unsigned int> init_count;
+
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    GroupBuf buf[2] = {};
+    unsigned int* counts[2] = {nullptr, nullptr};
+    double* d_tables = nullptr;
+    unsigned int* d_counters = nullptr;
+    unsigned long long* d_status = nullptr;
+    TilePartial* d_partials = nullptr;
+    double2* d_rho = nullptr;
+    StepStatsDev* d_stats = nullptr;
+    unsigned int* d_error = nullptr;
+    int hist_cap = 0;            // rho/stats history holds steps 0..hist_cap
+    int t = 0;                   // steps enqueued
+    int cur = 0;                 // buffer holding the state at time t
+    unsigned int epoch = 0;
+    int err = QUAPI_OK;          // sticky error of a failed step
+    size_t device_bytes = 0;
+    std::vector<void*> allocations;
+};
+
+namespace {
+
+int hip_to_code(hipError_t e) {
+    if (e == hipSuccess) return QUAPI_OK;
+    if (e == hipErrorOutOfMemory) return QUAPI_ENOMEM;
+    return QUAPI_EDEVICE;
+}
+
+template <class T>
+int dev_alloc(quapi_ctx* c, T** p, size_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    const size_t bytes = count * sizeof(T);
+    void* q = nullptr;
+    const hipError_t e = hipMalloc(&q, bytes);
+    if (e != hipSuccess) return hip_to_code(e);
+    c->allocations.push_back(q);
+    c->device_bytes += bytes;
+    *p = (T*)q;
+    return QUAPI_OK;
+}
+
+void dev_free(quapi_ctx* c, void* p) {
+    if (!p) return;
+    auto it = std::find(c->allocations.begin(), c->allocations.end(), p);
+    if (it != c->allocations.end()) c->allocations.erase(it);
+    (void)hipFree(p);
+}
+
+int upload_initial(quapi_ctx* c) {
+    hipError_t e = hipSuccess;
+    for (int p = 0; p < c->P && e == hipSuccess; ++p) {
+        if (!c->init_count[p]) continue;
+        const size_t o = (size_t)p * c->cap;
+        e = hipMemcpyAsync(c->buf[0].key + o, &c->init_key[p], 8, hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(c->buf[0].tail + o, &c->init_tail[p], 8, hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(c->buf[0].w + o, &c->init_w[p], 16, hipMemcpyHostToDevice, c->stream);
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->counts[0], c->init_count.data(), c->P * sizeof(unsigned int),
+                           hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c->d_error, 0, 2 * sizeof(unsigned int), c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c->d_counters, 0, 4 * sizeof(unsigned int), c->stream);
+    if (e == hipSuccess) {
+        std::vector<double2> r0(c->P);
+        for (int p = 0; p < c->P; ++p) r0[p] = make_double2(c->rho0[2 * p], c->rho0[2 * p + 1]);
+        e = hipMemcpyAsync(c->d_rho, r0.data(), c->P * sizeof(double2), hipMemcpyHostToDevice, c->stream);
+        StepStatsDev s0 = {};
+        unsigned long long n0 = 0;
+        for (unsigned int x : c->init_count) n0 += x;
+        s0.n_stored = n0;
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(c->d_stats, &s0, sizeof s0, hipMemcpyHostToDevice, c->stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    c->t = 0;
+    c->cur = 0;
+    c->err = QUAPI_OK;
+    return hip_to_code(e);
+}
+
+int grow_history(quapi_ctx* c, int need) {
+    if (need <= c->hist_cap) return QUAPI_OK;
+    int ncap = std::max(need, 2 * c->hist_cap);
+    double2* nr = nullptr;
+    StepStatsDev* ns = nullptr;
+    int rc = dev_alloc(c, &nr, (size_t)(ncap + 1) * c->P);
+    if (rc) return rc;
+    rc = dev_alloc(c, &ns, (size_t)(ncap + 1));
+    if (rc) { dev_free(c, nr); return rc; }
+    hipError_t e = hipMemcpyAsync(nr, c->d_rho, (size_t)(c->hist_cap + 1) * c->P * sizeof(double2),
+                                  hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ns, c->d_stats, (size_t)(c->hist_cap + 1) * sizeof(StepStatsDev),
+                           hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) { dev_free(c, nr); dev_free(c, ns); return hip_to_code(e); }
+    c->device_bytes -= (size_t)(c->hist_cap + 1) * (c->P * sizeof(double2) + sizeof(StepStatsDev));
+    dev_free(c, c->d_rho);
+    dev_free(c, c->d_stats);
+    c->d_rho = nr;
+    c->d_stats = ns;
+    c->hist_cap = ncap;
+    return QUAPI_OK;
+}
+
+// Reads the kernel-reported error after a synchronisation and rolls the
+// context back to the last complete step.
+int check_device_error(quapi_ctx* c) {
+    if (c->err) return c->err;
+    unsigned int h[2] = {0, 0};
+    hipError_t e = hipMemcpy(h, c->d_error, sizeof h, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) { c->err = hip_to_code(e); return c->err; }
+    if (h[0] == quapi_dev::kErrNone) return QUAPI_OK;
+    c->err = (h[0] == quapi_dev::kErrOverflow) ? QUAPI_ENOMEM : QUAPI_EDEVICE;
+    const int failed = (int)h[1];
+    if (failed >= 1 && failed <= c->t) {
+        c->t = failed - 1;
+        c->cur = c->t & 1;
+    }
+    return c->err;
+}
+
+int sync_ctx(quapi_ctx* c) {
+    const hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) { c->err = hip_to_code(e); return c->err; }
+    return check_device_error(c);
+}
+
+bool is_finite_d(double x) { return std::isfinite(x); }
+
+}  // namespace
+
+extern "C" {
+
+const char* quapi_strerror(int code) {
+    switch (code) {
+        case QUAPI_OK: return "ok";
+        case QUAPI_EINVAL: return "invalid argument";
+        case QUAPI_ENOMEM: return "out of device memory or group capacity exceeded";
+        case QUAPI_EDEVICE: return "HIP runtime error or kernel-reported fault";
+        case QUAPI_ESTATE: return "call not valid in the current state";
+        case QUAPI_EUNSUPPORTED: return "input not supported by this build";
+        default: return "unknown error";
+    }
+}
+
+int quapi_propagator(int M, const quapi_c64* H, double dt, quapi_c64* U_out) {
+    if (M < 1 || M > 8 || !H || !U_out || !is_finite_d(dt)) return QUAPI_EINVAL;
+    if (!quapi_host::hermitian_ok(M, (const double*)H)) return QUAPI_EINVAL;
+    quapi_host::propagator(M, (const double*)H, dt, (double*)U_out);
+    return QUAPI_OK;
+}
+
+int quapi_eta(const quapi_bath* bath, double beta, double dt, int dk_max, quapi_c64* eta_out) {
+    if (!bath || !eta_out || !(beta > 0) || !(dt > 0) || dk_max < 1 || dk_max > quapi_dev::kMaxK)
+        return QUAPI_EINVAL;
+    if (bath->ohmic_alpha < 0 || (bath->ohmic_alpha > 0 && !(bath->ohmic_wc > 0))) return QUAPI_EINVAL;
+    if (bath->n_peaks < 0 || (bath->n_peaks > 0 && !bath->peaks)) return QUAPI_EINVAL;
+    for (int k = 0; k < bath->n_peaks; ++k)
+        if (!(bath->peaks[3 * k] > 0) || !(bath->peaks[3 * k + 1] > 0) || bath->peaks[3 * k + 2] < 0)
+            return QUAPI_EINVAL;
+    return quapi_host::eta_columns(bath->ohmic_alpha, bath->ohmic_wc, bath->n_peaks, bath->peaks, beta,
+                                   dt, dk_max, (double*)eta_out) == 0 ? QUAPI_OK : QUAPI_EINVAL;
+}
+
+int quapi_create(const quapi_params* p, quapi_ctx** out) {
+    if (!out) return QUAPI_EINVAL;
+    *out = nullptr;
+    if (!p || !p->H || !p->q || !p->eta || !p->rho0) return QUAPI_EINVAL;
+    const int M = p->M, K = p->dk_max;
+    if (M < 2 || K < 1 || K > quapi_dev::kMaxK || !(p->dt > 0) || !is_finite_d(p->dt)) return QUAPI_EINVAL;
+    if (!(p->theta >= 0) || !is_finite_d(p->theta)) return QUAPI_EINVAL;
+    if (p->mode != QUAPI_PRE && p->mode != QUAPI_POST) return QUAPI_EINVAL;
+    if (M > 3) return QUAPI_EUNSUPPORTED;
+    if (!quapi_host::hermitian_ok(M, (const double*)p->H)) return QUAPI_EINVAL;
+    for (int i = 0; i < M; ++i)
+        if (!is_finite_d(p->q[i])) return QUAPI_EINVAL;
+    for (int i = 0; i < 3 * (K + 1); ++i)
+        if (!is_finite_d(p->eta[i].re) || !is_finite_d(p->eta[i].im)) return QUAPI_EINVAL;
+    for (int i = 0; i < M * M; ++i)
+        if (!is_finite_d(p->rho0[i].re) || !is_finite_d(p->rho0[i].im)) return QUAPI_EINVAL;
+
+    // mask: sorted, distinct, contains 0 and 1, lags < K
+    std::vector<int> mask;
+    if (p->mask && p->n_mask > 0) {
+        mask.assign(p->mask, p->mask + p->n_mask);
+    } else if (p->mask && p->n_mask < 0) {
+        return QUAPI_EINVAL;
+    } else {
+        for (int d = 0; d < K; ++d) mask.push_back(d);
+    }
+    if (mask.size() < 2 || mask[0] != 0 || mask[1] != 1) return QUAPI_EINVAL;
+    for (size_t i = 1; i < mask.size(); ++i)
+        if (mask[i] <= mask[i - 1] || mask[i] >= K) return QUAPI_EINVAL;
+    // merge positions: pre-merging {mask[i]-1 : i>=1}, post-merging the mask itself
+    std::vector<int> pos;
+    if (p->mode == QUAPI_PRE) {
+        for (size_t i = 1; i < mask.size(); ++i) pos.push_back(mask[i] - 1);
+    } else {
+        pos = mask;
+    }
+    for (size_t i = 0; i < pos.size(); ++i)
+        if (pos[i] != (int)i) return QUAPI_EUNSUPPORTED;   // merge positions must be 0..L-1
+    const int L = (int)pos.size();
+    if (L < 2) return QUAPI_EUNSUPPORTED;
+    const int P = M * M;
+    const int bits = P <= 4 ? 2 : 4;
+    if (L * bits > 62 || (K - L) * bits > 64) return QUAPI_EUNSUPPORTED;
+
+    quapi_ctx* c = new (std::nothrow) quapi_ctx();
+    if (!c) return QUAPI_ENOMEM;
+    c->M = M;
+    c->P = P;
+    c->K = K;
+    c->L = L;
+    c->bits = bits;
+    c->mode = p->mode;
+    c->qbits = p->qbits < 0 ? 32 : std::min(p->qbits, 63);
+    c->dt = p->dt;
+    c->theta = p->theta;
+
+    // capacity of one run: all keys with a fixed newest point, or the cap given
+    long long space = 1;
+    for (int i = 0; i < L - 1 && space < (1ll << 40); ++i) space *= P;
+    long long cap = std::min(space, p->max_groups > 0 ? p->max_groups : (1ll << 25));
+    cap = std::min(cap, (1ll << 30) - 1);
+    c->cap = cap;
+    c->max_tiles = quapi_dev::max_tiles_for(P, cap);
+
+    // tables: K4[pn][po] = U[an][ao] conj(U[bn][bo]); ds, ss; eta
+    std::vector<double> U(2 * M * M);
+    quapi_host::propagator(M, (const double*)p->H, p->dt, U.data());
+    c->tables.assign(TableLayout::total(P, K), 0.0);
+    for (int pn = 0; pn < P; ++pn)
+        for (int po = 0; po < P; ++po) {
+            const std::complex<double> u1(U[2 * ((pn / M) * M + po / M)], U[2 * ((pn / M) * M + po / M) + 1]);
+            const std::complex<double> u2(U[2 * ((pn % M) * M + po % M)], U[2 * ((pn % M) * M + po % M) + 1]);
+            const std::complex<double> k4 = u1 * std::conj(u2);
+            c->tables[2 * (pn * P + po)] = k4.real();
+            c->tables[2 * (pn * P + po) + 1] = k4.imag();
+        }
+    for (int pp = 0; pp < P; ++pp) {
+        c->tables[TableLayout::ds(P) + pp] = p->q[pp / M] - p->q[pp % M];
+        c->tables[TableLayout::ss(P) + pp] = p->q[pp / M] + p->q[pp % M];
+    }
+    for (int i = 0; i < 3 * (K + 1); ++i) {
+        c->tables[TableLayout::eta(P) + 2 * i] = p->eta[i].re;
+        c->tables[TableLayout::eta(P) + 2 * i + 1] = p->eta[i].im;
+    }
+
+    // t = 0: one group per nonzero element of rho0 with the initial point's self term
+    c->rho0.resize(2 * P);
+    c->init_key.assign(P, 0);
+    c->init_tail.assign(P, 0);
+    c->init_w.assign(P, make_double2(0, 0));
+    c->init_count.assign(P, 0);
+    const std::complex<double> e0(p->eta[K + 1].re, p->eta[K + 1].im);   // end-point self term
+    for (int pp = 0; pp < P; ++pp) {
+        const std::complex<double> r(p->rho0[pp].re, p->rho0[pp].im);
+        c->rho0[2 * pp] = r.real();
+        c->rho0[2 * pp + 1] = r.imag();
+        if (r == std::complex<double>(0, 0)) continue;
+        const double ds = c->tables[TableLayout::ds(P) + pp], ss = c->tables[TableLayout::ss(P) + pp];
+        const std::complex<double> w = r * std::exp(std::complex<double>(-ds * e0.real() * ds, -ds * e0.imag() * ss));
+        c->init_key[pp] = (unsigned long long)pp << (bits * (L - 1));
+        c->init_w[pp] = make_double2(w.real(), w.imag());
+        c->init_count[pp] = 1;
+    }
+
+    int rc = QUAPI_OK;
+    if (p->stream) {
+        c->stream = (hipStream_t)p->stream;
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete c;
+            return QUAPI_EDEVICE;
+        }
+        c->own_stream = true;
+    }
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        quapi_destroy(c);
+        return QUAPI_EDEVICE;
+    }
+    c->grid = std::max(1, std::min(c->max_tiles, 4 * std::max(ncu, 1)));
+
+    const size_t n = (size_t)P * (size_t)cap;
+    for (int b = 0; b < 2 && rc == QUAPI_OK; ++b) {
+        rc = dev_alloc(c, &c->buf[b].key, n);
+        if (!rc) rc = dev_alloc(c, &c->buf[b].tail, n);
+        if (!rc) rc = dev_alloc(c, &c->buf[b].w, n);
+        if (!rc) rc = dev_alloc(c, &c->counts[b], (size_t)P);
+    }
+    if (!rc) rc = dev_alloc(c, &c->d_tables, c->tables.size());
+    if (!rc) rc = dev_alloc(c, &c->d_counters, 4);
+    if (!rc) rc = dev_alloc(c, &c->d_status, (size_t)P * c->max_tiles);
+    if (!rc) rc = dev_alloc(c, &c->d_partials, (size_t)c->max_tiles);
+    if (!rc) rc = dev_alloc(c, &c->d_error, 2);
+    c->hist_cap = p->max_steps > 0 ? p->max_steps : 1024;
+    if (!rc) rc = dev_alloc(c, &c->d_rho, (size_t)(c->hist_cap + 1) * P);
+    if (!rc) rc = dev_alloc(c, &c->d_stats, (size_t)(c->hist_cap + 1));
+    if (rc) {
+        quapi_destroy(c);
+        return rc;
+    }
+    hipError_t e = hipMemcpyAsync(c->d_tables, c->tables.data(), c->tables.size() * sizeof(double),
+                                  hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c->d_counters, 0, 4 * sizeof(unsigned int), c->stream);
+    if (e == hipSuccess)
+        e = hipMemsetAsync(c->d_status, 0, (size_t)P * c->max_tiles * sizeof(unsigned long long), c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c->counts[1], 0, P * sizeof(unsigned int), c->stream);
+    if (e != hipSuccess) {
+        quapi_destroy(c);
+        return hip_to_code(e);
+    }
+    rc = upload_initial(c);
+    if (rc) {
+        quapi_destroy(c);
+        return rc;
+    }
+    *out = c;
+    return QUAPI_OK;
+}
+
+int quapi_step(quapi_ctx* c, int n_steps) {
+    if (!c || n_steps < 0) return QUAPI_EINVAL;
+    if (c->err) return QUAPI_ESTATE;
+    if (n_steps == 0) return QUAPI_OK;
+    int rc = grow_history(c, c->t + n_steps);
+    if (rc) return rc;
+    StepArgs a;
+    a.cap = c->cap;
+    a.P = c->P;
+    a.L = c->L;
+    a.K = c->K;
+    a.bits = c->bits;
+    a.max_tiles = c->max_tiles;
+    a.theta2 = c->theta * c->theta;
+    a.qmask = c->qbits >= 64 ? 0ull : ~((1ull << c->qbits) - 1ull);
+    a.tables = c->d_tables;
+    a.counters = c->d_counters;
+    a.status = c->d_status;
+    a.partials = c->d_partials;
+    a.error = c->d_error;
+    for (int k = 0; k < n_steps; ++k) {
+        const int t = c->t + 1;
+        a.in = c->buf[c->cur];
+        a.out = c->buf[1 - c->cur];
+        a.in_count = c->counts[c->cur];
+        a.out_count = c->counts[1 - c->cur];
+        a.t = t;
+        a.epoch = ++c->epoch;
+        a.rho_out = c->d_rho + (size_t)t * c->P;
+        a.stats_out = c->d_stats + t;
+        const int e = quapi_dev::launch_step(a, c->grid, c->stream);
+        if (e != (int)hipSuccess) {
+            c->err = QUAPI_EDEVICE;
+            return c->err;
+        }
+        c->t = t;
+        c->cur = 1 - c->cur;
+    }
+    return QUAPI_OK;
+}
+
+int quapi_sync(quapi_ctx* c) {
+    if (!c) return QUAPI_EINVAL;
+    return sync_ctx(c);
+}
+
+int quapi_time(quapi_ctx* c, int* t_out) {
+    if (!c || !t_out) return QUAPI_EINVAL;
+    const int rc = sync_ctx(c);
+    *t_out = c->t;
+    return rc == QUAPI_EDEVICE ? rc : QUAPI_OK;
+}
+
+int quapi_rho_history(quapi_ctx* c, int t0, int n, quapi_c64* out) {
+    if (!c || !out || t0 < 0 || n < 0) return QUAPI_EINVAL;
+    const int rc = sync_ctx(c);
+    if (rc == QUAPI_EDEVICE) return rc;
+    if (t0 + n - 1 > c->t) return QUAPI_EINVAL;
+    if (n == 0) return QUAPI_OK;
+    const hipError_t e = hipMemcpy(out, c->d_rho + (size_t)t0 * c->P, (size_t)n * c->P * sizeof(double2),
+                                   hipMemcpyDeviceToHost);
+    return hip_to_code(e);
+}
+
+int quapi_rho(quapi_ctx* c, int t, quapi_c64* rho_out) { return quapi_rho_history(c, t, 1, rho_out); }
+
+int quapi_step_stats(quapi_ctx* c, int t0, int n, quapi_stepstat_t* out) {
+    if (!c || !out || t0 < 1 || n < 0) return QUAPI_EINVAL;
+    const int rc = sync_ctx(c);
+    if (rc == QUAPI_EDEVICE) return rc;
+    if (t0 + n - 1 > c->t) return QUAPI_EINVAL;
+    std::vector<StepStatsDev> h(n);
+    if (n) {
+        const hipError_t e = hipMemcpy(h.data(), c->d_stats + t0, (size_t)n * sizeof(StepStatsDev),
+                                       hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_to_code(e);
+    }
+    for (int k = 0; k < n; ++k) {
+        out[k].t = t0 + k;
+        out[k].n_groups = (long long)h[k].n_groups;
+        out[k].n_children = (long long)h[k].n_children;
+        out[k].n_survivors = (long long)h[k].n_survivors;
+        out[k].n_stored = (long long)h[k].n_stored;
+        out[k].dropped_abs = h[k].dropped_abs;
+    }
+    return QUAPI_OK;
+}
+
+int quapi_groups(quapi_ctx* c, long long cap, unsigned char* hist, quapi_c64* w, long long* n_out) {
+    if (!c || !n_out || cap < 0 || (cap > 0 && (!hist || !w))) return QUAPI_EINVAL;
+    const int rc = sync_ctx(c);
+    if (rc == QUAPI_EDEVICE) return rc;
+    std::vector<unsigned int> cnt(c->P);
+    hipError_t e = hipMemcpy(cnt.data(), c->counts[c->cur], c->P * sizeof(unsigned int), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_to_code(e);
+    long long n = 0;
+    for (unsigned int x : cnt) n += x;
+    *n_out = n;
+    long long written = 0;
+    const unsigned long long dm = (1ull << c->bits) - 1;
+    for (int p = 0; p < c->P && written < cap; ++p) {
+        const long long m = std::min<long long>(cnt[p], cap - written);
+        if (m <= 0) continue;
+        std::vector<unsigned long long> k(m), tl(m);
+        std::vector<double2> ww(m);
+        const size_t o = (size_t)p * c->cap;
+        e = hipMemcpy(k.data(), c->buf[c->cur].key + o, m * 8, hipMemcpyDeviceToHost);
+        if (e == hipSuccess) e = hipMemcpy(tl.data(), c->buf[c->cur].tail + o, m * 8, hipMemcpyDeviceToHost);
+        if (e == hipSuccess) e = hipMemcpy(ww.data(), c->buf[c->cur].w + o, m * 16, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_to_code(e);
+        for (long long i = 0; i < m; ++i) {
+            unsigned char* row = hist + (size_t)(written + i) * c->K;
+            for (int j = 0; j < c->K; ++j) {
+                unsigned long long d;
+                if (j < c->L) d = (k[i] >> (c->bits * (c->L - 1 - j))) & dm;
+                else d = (tl[i] >> (c->bits * (j - c->L))) & dm;
+                row[j] = (unsigned char)d;
+            }
+            w[written + i].re = ww[i].x;
+            w[written + i].im = ww[i].y;
+        }
+        written += m;
+    }
+    return QUAPI_OK;
+}
+
+int quapi_reset(quapi_ctx* c) {
+    if (!c) return QUAPI_EINVAL;
+    (void)hipStreamSynchronize(c->stream);
+    return upload_initial(c);
+}
+
+int quapi_info(quapi_ctx* c, quapi_info_t* out) {
+    if (!c || !out) return QUAPI_EINVAL;
+    out->M = c->M;
+    out->P = c->P;
+    out->K = c->K;
+    out->L = c->L;
+    out->bits_per_point = c->bits;
+    out->record_bytes = 32;
+    out->capacity = (long long)c->P * c->cap;
+    out->device_bytes = c->device_bytes;
+    return QUAPI_OK;
+}
+
+void* quapi_stream(quapi_ctx* c) { return c ? (void*)c->stream : nullptr; }
+
+void quapi_destroy(quapi_ctx* c) {
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (void* p : c->allocations) (void)hipFree(p);
+    c->allocations.clear();
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+}  // extern "C"

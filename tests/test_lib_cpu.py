@@ -1,0 +1,102 @@
+"""CPU tests of the HIP library's C ABI: it loads, exports every function its
+header declares, its host tables agree with independent references, and it
+rejects invalid input before touching a device."""
+import ctypes
+import os
+
+import numpy as np
+import pytest
+from scipy.linalg import expm
+
+from paper_2506_03127_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def Q():
+    from paper_2506_03127_amd import quapi
+    if not os.path.exists(quapi.LIB_PATH):
+        from paper_2506_03127_amd import _build
+        _build.build()
+    return quapi
+
+
+def test_library_exports_every_declared_function(Q):
+    names = Q.header_functions()
+    assert len(names) >= 15
+    lib = ctypes.CDLL(Q.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_propagator_matches_expm(Q):
+    for M, seed in [(2, 1), (3, 2), (4, 3), (6, 4)]:
+        H = W.random_hermitian(M, 0.7, seed)
+        U = Q.quapi_propagator(H, 0.3)
+        assert np.abs(U - expm(-0.3j * H)).max() < 1e-13
+    assert np.abs(Q.quapi_propagator(W.tls_hamiltonian(0.5, 1.0), 0.2)
+                  - expm(-0.2j * W.tls_hamiltonian(0.5, 1.0))).max() < 1e-14
+
+
+def test_propagator_rejects_non_hermitian(Q):
+    H = np.array([[0.0, 1.0], [0.5, 0.0]], dtype=complex)
+    with pytest.raises(Q.QuapiError) as e:
+        Q.quapi_propagator(H, 0.1)
+    assert e.value.code == Q.QUAPI_EINVAL
+
+
+@pytest.mark.parametrize("wl", [W.spin_boson_ohmic(), W.structured_bath()], ids=lambda w: w.name)
+def test_eta_generator_matches_oracle_quadrature(Q, eta_cache, wl):
+    """The library's Gauss-Legendre panels against the oracle's adaptive quadrature."""
+    b = wl.bath
+    peaks = [x for pk in b.peaks for x in pk]
+    mine = Q.quapi_eta(b.ohmic_alpha, b.ohmic_wc, peaks, wl.beta, wl.dt, wl.K)
+    ref = eta_cache(wl)
+    assert np.abs(mine - ref).max() < 1e-12
+
+
+def test_eta_rejects_bad_arguments(Q):
+    with pytest.raises(Q.QuapiError):
+        Q.quapi_eta(0.1, 5.0, [], -1.0, 0.2, 4)
+    with pytest.raises(Q.QuapiError):
+        Q.quapi_eta(0.1, 5.0, [1.0, -0.05, 0.1], 5.0, 0.2, 4)
+    with pytest.raises(Q.QuapiError):
+        Q.quapi_eta(0.1, 5.0, [], 5.0, 0.2, 0)
+
+
+def _create_code(Q, **over):
+    wl = W.spin_boson_ohmic()
+    args = dict(H=wl.H, q=wl.q, dt=wl.dt, dk_max=wl.K, eta=np.zeros((3, wl.K + 1)), rho0=wl.rho0,
+                mask=None, theta=0.0, mode=Q.QUAPI_POST)
+    args.update(over)
+    try:
+        ctx = Q.quapi_create(**args)
+    except Q.QuapiError as e:
+        return e.code
+    Q.quapi_destroy(ctx)
+    return 0
+
+
+def test_create_rejects_invalid_input_without_device(Q):
+    assert _create_code(Q, H=np.array([[0, 1], [2, 0]], dtype=complex)) == Q.QUAPI_EINVAL
+    assert _create_code(Q, dt=-0.1) == Q.QUAPI_EINVAL
+    assert _create_code(Q, theta=-1.0) == Q.QUAPI_EINVAL
+    assert _create_code(Q, mask=[0, 2, 3]) == Q.QUAPI_EINVAL          # lag 1 missing
+    assert _create_code(Q, mask=[1, 2]) == Q.QUAPI_EINVAL             # lag 0 missing
+    assert _create_code(Q, mask=[0, 1, 1]) == Q.QUAPI_EINVAL          # not strictly sorted
+    assert _create_code(Q, mask=[0, 1, 8]) == Q.QUAPI_EINVAL          # lag beyond dk_max - 1
+    assert _create_code(Q, mode=7) == Q.QUAPI_EINVAL
+    eta_nan = np.zeros((3, 9), dtype=complex)
+    eta_nan[0, 3] = np.nan
+    assert _create_code(Q, eta=eta_nan) == Q.QUAPI_EINVAL
+    # valid but outside this build: merge positions not contiguous, M = 4
+    assert _create_code(Q, mask=[0, 1, 3]) == Q.QUAPI_EUNSUPPORTED
+    assert _create_code(Q, mask=[0, 1], mode=Q.QUAPI_PRE) == Q.QUAPI_EUNSUPPORTED
+    H4 = W.random_hermitian(4, 0.5, 1)
+    assert _create_code(Q, H=H4, q=[1, 0.5, -0.5, -1], rho0=W.ground_projector(4)) == Q.QUAPI_EUNSUPPORTED
+
+
+def test_strerror_names_every_code(Q):
+    names = {Q.strerror(c) for c in (0, -1, -2, -3, -4, -5)}
+    assert len(names) == 6 and "unknown error" not in names
