@@ -1,0 +1,170 @@
+"""Benchmark: MACGIC-iQUAPI path propagation on one MI355X.
+
+One benchmark step = one whole propagation of the structured-bath workload
+(two-level system, Ohmic + underdamped Brownian-oscillator bath, dk_max = 24,
+mask keeping lags 0..11, theta = 1e-8, 1000 time steps, FP64, pre-merging):
+reset to t = 0, 1000 fused step kernels, read back rho(t) for all t.  The
+bath coefficients and propagator tables are built once before timing (they
+stay resident in HBM with the path store).
+
+Prints one JSON line:  value = path-steps/s over the timed propagations
+(path-step = one child, i.e. one group extended by one forward/backward pair
+in one time step), plus a roofline object for the step kernel (algorithmic
+bytes = 32 B per group read + 32 B per group written, over the kernel's mean
+launch time measured with HIP events on its stream) and the CPU oracle timed
+on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "path-steps/sec + HBM roofline fraction at dk_max=24, theta=1e-8; time per rho(t)"
+HBM_PEAK_GBS = 8000.0
+RECORD_BYTES = 32
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(wl, steps: int) -> dict:
+    """The oracle as it stands, single-threaded, on the first `steps` time steps."""
+    import oracle
+    from oracle.eta import Bath, eta_columns
+    b = wl.bath
+    eta = eta_columns(Bath(b.ohmic_alpha, b.ohmic_wc, b.peaks), wl.beta, wl.dt, wl.K)
+    o = oracle.Oracle(wl.H, wl.q, wl.dt, wl.K, eta, wl.rho0, mask=wl.mask, theta=wl.theta,
+                      mode=oracle.PRE)
+    t0 = time.perf_counter()
+    o.step(steps)
+    el = time.perf_counter() - t0
+    children = sum(o.stats(t)["n_children"] for t in range(1, steps + 1))
+    return {"value": children / el, "unit": "path-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"time steps 1..{steps} of the same workload ({children} path-steps, "
+                      f"{el:.1f} s, single thread, {cpu_model()})"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5, help="timed propagations")
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--cpu-steps", type=int, default=22,
+                    help="time steps of the oracle sample for the CPU baseline (0: skip)")
+    ap.add_argument("--no-roofline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the path is built "
+              "and measured at one GPU's share", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2506_03127_amd import quapi, workloads
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    wl = workloads.structured_bath()
+    b = wl.bath
+    peaks = [x for pk in b.peaks for x in pk]
+    eta = quapi.quapi_eta(b.ohmic_alpha, b.ohmic_wc, peaks, wl.beta, wl.dt, wl.K)
+    stream = torch.cuda.Stream()
+    prop = quapi.Propagator(wl.H, wl.q, wl.dt, wl.K, eta, wl.rho0, mask=wl.mask, theta=wl.theta,
+                            mode=quapi.QUAPI_PRE, max_steps=wl.n_steps, stream=stream.cuda_stream)
+    n_t = wl.n_steps
+
+    def run_once():
+        prop.reset()
+        quapi.quapi_step(prop.ctx, n_t)
+        return quapi.quapi_rho_history(prop.ctx, 0, n_t + 1, wl.M)
+
+    for _ in range(args.warmup):
+        run_once()
+    torch.cuda.synchronize()
+    times = []
+    rho = None
+    for _ in range(args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rho = run_once()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    st = prop.stats(1, n_t)
+    children = sum(s["n_children"] for s in st)
+    groups_in = np.array([s["n_groups"] for s in st], dtype=np.float64)
+    groups_out = np.array([s["n_stored"] for s in st], dtype=np.float64)
+    total = sum(times)
+    ms_per_step = 1e3 * total / len(times)
+    value = children * len(times) / total
+    alg_bytes = RECORD_BYTES * (groups_in + groups_out)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "path-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (model Hamiltonian and spectral density; no dataset)",
+        "config": {
+            "workload": wl.name, "M": wl.M, "dk_max": wl.K, "mask": list(wl.mask),
+            "theta": wl.theta, "time_steps": n_t, "mode": "pre-merging",
+            "bath": {"ohmic_alpha": b.ohmic_alpha, "ohmic_wc": b.ohmic_wc,
+                     "peaks_w0_gamma_lambda": [list(p) for p in b.peaks]},
+            "beta": wl.beta, "dt": wl.dt, "eps": 0.5, "Delta": 1.0,
+        },
+        "time_per_rho_us": 1e3 * ms_per_step / n_t,
+        "path_steps_per_propagation": children,
+        "mean_groups_per_step": float(groups_in.mean()),
+        "run_hbm_fraction": float(alg_bytes.sum() / (total / len(times)) / (HBM_PEAK_GBS * 1e9)),
+        "trace_final": float(np.trace(rho[-1]).real),
+    }
+
+    if not args.no_roofline:
+        # per-launch durations of the step kernel: events around each launch on its stream
+        prop.reset()
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(n_t + 1)]
+        evs[0].record(stream)
+        for k in range(n_t):
+            quapi.quapi_step(prop.ctx, 1)
+            evs[k + 1].record(stream)
+        torch.cuda.synchronize()
+        dur_ms = np.array([evs[k].elapsed_time(evs[k + 1]) for k in range(n_t)])
+        mean_s = float(dur_ms.mean()) * 1e-3
+        per_launch_bytes = float(alg_bytes.mean())
+        achieved = per_launch_bytes / mean_s / 1e9
+        out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                           "kernel": "step_kernel<4,2>", "launches": n_t,
+                           "mean_launch_us": mean_s * 1e6,
+                           "alg_bytes_per_launch": per_launch_bytes}
+
+    if args.cpu_steps > 0:
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)
+
+    prop.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

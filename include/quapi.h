@@ -76,7 +76,9 @@ typedef struct {
                               /* multiply-add) with its low qbits mantissa bits cleared; equal values    */
                               /* go to the history that is smaller read from the oldest point.          */
                               /* < 0: default 32                                                        */
-    long long max_groups;     /* cap on stored groups that share their newest point; 0: 2^25          */
+    long long max_groups;     /* stored groups to allocate for, spread evenly over the key buckets     */
+                              /* (at least one each; an uneven fill reports ENOMEM first); 0: room   */
+                              /* for every key of the merge positions                                 */
     int max_steps;            /* initial capacity of the rho(t) history; grows on demand; <= 0: 1024    */
     void* stream;             /* hipStream_t to run on (e.g. a torch stream); NULL: a library stream   */
 } quapi_params;

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -17,28 +18,34 @@ using quapi_dev::GroupBuf;
 using quapi_dev::StepArgs;
 using quapi_dev::StepStatsDev;
 using quapi_dev::TableLayout;
-using quapi_dev::TilePartial;
 
 struct quapi_ctx {
     int M = 0, P = 0, K = 0, L = 0, bits = 0, mode = 0, qbits = 32;
+    int D = 0;                   // bucket key length in points
+    int n_super = 0;             // P^(D-1)
+    long long n_buckets = 0;     // P^D
     double dt = 0, theta = 0;
-    long long cap = 0;           // groups per run
-    int max_tiles = 0;
-    int grid = 0;
+    long long cap = 0;           // groups per bucket
     std::vector<double> tables;  // host copy of the device tables
+    std::vector<double> coef;    // per-step coefficient sets, t = 1..K+1 (t > K uses set K+1)
     std::vector<double> rho0;    // 2*P
-    std::vector<unsigned long long> init_key, init_tail;
+    std::vector<unsigned long long> init_key;
     std::vector<double2> init_w;
-    std::vector<unsigned int> init_count;
+    std::vector<long long> init_bucket;
 
     hipStream_t stream = nullptr;
     bool own_stream = false;
     GroupBuf buf[2] = {};
     unsigned int* counts[2] = {nullptr, nullptr};
     double* d_tables = nullptr;
-    unsigned int* d_counters = nullptr;
-    unsigned long long* d_status = nullptr;
-    TilePartial* d_partials = nullptr;
+    double* d_coef = nullptr;
+    double* d_partials = nullptr;
+    unsigned int* d_prefix = nullptr;        // [n_buckets + 1]
+    unsigned int* d_chunk_start = nullptr;   // [2 * max_chunks]
+    quapi_dev::Plan* d_plan = nullptr;       // [2], by step parity
+    unsigned long long* d_chain = nullptr;   // [(P + 1) * max_chunks]
+    int max_chunks = 0;
+    int grid = 0;
     double2* d_rho = nullptr;
     StepStatsDev* d_stats = nullptr;
     unsigned int* d_error = nullptr;
@@ -66,73 +73,99 @@ int dev_alloc(quapi_ctx* c, T** p, size_t count) {
     const size_t bytes = count * sizeof(T);
     void* q = nullptr;
     const hipError_t e = hipMalloc(&q, bytes);
-    if (e != hipSuccess) return hip_to_code(e);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return hip_to_code(e);
+    }
     c->allocations.push_back(q);
     c->device_bytes += bytes;
     *p = (T*)q;
     return QUAPI_OK;
 }
 
-void dev_free(quapi_ctx* c, void* p) {
+void dev_free(quapi_ctx* c, void* p, size_t bytes) {
     if (!p) return;
     auto it = std::find(c->allocations.begin(), c->allocations.end(), p);
     if (it != c->allocations.end()) c->allocations.erase(it);
+    c->device_bytes -= bytes;
     (void)hipFree(p);
 }
 
+int launch_planner(quapi_ctx* c, int t);
+
 int upload_initial(quapi_ctx* c) {
-    hipError_t e = hipSuccess;
-    for (int p = 0; p < c->P && e == hipSuccess; ++p) {
-        if (!c->init_count[p]) continue;
-        const size_t o = (size_t)p * c->cap;
-        e = hipMemcpyAsync(c->buf[0].key + o, &c->init_key[p], 8, hipMemcpyHostToDevice, c->stream);
+    hipError_t e = hipMemsetAsync(c->counts[0], 0, (size_t)c->n_buckets * sizeof(unsigned int), c->stream);
+    for (size_t k = 0; k < c->init_key.size() && e == hipSuccess; ++k) {
+        const size_t o = (size_t)c->init_bucket[k] * (size_t)c->cap;
+        const unsigned long long zero = 0;
+        const unsigned int one = 1;
+        e = hipMemcpyAsync(c->buf[0].key + o, &c->init_key[k], 8, hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(c->buf[0].tail + o, &zero, 8, hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(c->buf[0].w + o, &c->init_w[k], 16, hipMemcpyHostToDevice, c->stream);
         if (e == hipSuccess)
-            e = hipMemcpyAsync(c->buf[0].tail + o, &c->init_tail[p], 8, hipMemcpyHostToDevice, c->stream);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(c->buf[0].w + o, &c->init_w[p], 16, hipMemcpyHostToDevice, c->stream);
+            e = hipMemcpyAsync(c->counts[0] + c->init_bucket[k], &one, 4, hipMemcpyHostToDevice, c->stream);
+        // the copies read host stack values: complete them before the next iteration reuses them
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     }
+    if (e == hipSuccess) e = hipMemsetAsync(c->d_error, 0, sizeof(unsigned int), c->stream);
+    std::vector<double2> r0(c->P);
+    for (int p = 0; p < c->P; ++p) r0[p] = make_double2(c->rho0[2 * p], c->rho0[2 * p + 1]);
+    StepStatsDev s0 = {};
+    s0.n_stored = c->init_key.size();
     if (e == hipSuccess)
-        e = hipMemcpyAsync(c->counts[0], c->init_count.data(), c->P * sizeof(unsigned int),
-                           hipMemcpyHostToDevice, c->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(c->d_error, 0, 2 * sizeof(unsigned int), c->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(c->d_counters, 0, 4 * sizeof(unsigned int), c->stream);
-    if (e == hipSuccess) {
-        std::vector<double2> r0(c->P);
-        for (int p = 0; p < c->P; ++p) r0[p] = make_double2(c->rho0[2 * p], c->rho0[2 * p + 1]);
         e = hipMemcpyAsync(c->d_rho, r0.data(), c->P * sizeof(double2), hipMemcpyHostToDevice, c->stream);
-        StepStatsDev s0 = {};
-        unsigned long long n0 = 0;
-        for (unsigned int x : c->init_count) n0 += x;
-        s0.n_stored = n0;
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(c->d_stats, &s0, sizeof s0, hipMemcpyHostToDevice, c->stream);
-    }
-    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->d_stats, &s0, sizeof s0, hipMemcpyHostToDevice, c->stream);
     c->t = 0;
     c->cur = 0;
     c->err = QUAPI_OK;
+    if (e == hipSuccess && launch_planner(c, 0) != QUAPI_OK) e = hipErrorLaunchFailure;
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     return hip_to_code(e);
+}
+
+// Plan step t+1 from the groups stored after step t (and reduce step t's sums when t >= 1).
+int launch_planner(quapi_ctx* c, int t) {
+    quapi_dev::PlanArgs pa;
+    pa.counts = c->counts[c->cur];
+    pa.counts_next = c->counts[1 - c->cur];
+    pa.prefix = c->d_prefix;
+    pa.chunk_start = c->d_chunk_start;
+    pa.plan = c->d_plan + ((t + 1) & 1);
+    pa.plan_prev = c->d_plan + (t & 1);
+    pa.n_buckets = c->n_buckets;
+    pa.chunk_heads = quapi_dev::chunk_heads(c->P);
+    pa.max_chunks = c->max_chunks;
+    pa.P = c->P;
+    pa.reduce_t = t;
+    pa.partials = c->d_partials;
+    pa.rho_hist = c->d_rho;
+    pa.stats_hist = c->d_stats;
+    pa.error = c->d_error;
+    return quapi_dev::launch_plan(pa, c->stream) == (int)hipSuccess ? QUAPI_OK : QUAPI_EDEVICE;
 }
 
 int grow_history(quapi_ctx* c, int need) {
     if (need <= c->hist_cap) return QUAPI_OK;
-    int ncap = std::max(need, 2 * c->hist_cap);
+    const int ncap = std::max(need, 2 * c->hist_cap);
     double2* nr = nullptr;
     StepStatsDev* ns = nullptr;
     int rc = dev_alloc(c, &nr, (size_t)(ncap + 1) * c->P);
     if (rc) return rc;
     rc = dev_alloc(c, &ns, (size_t)(ncap + 1));
-    if (rc) { dev_free(c, nr); return rc; }
+    if (rc) { dev_free(c, nr, (size_t)(ncap + 1) * c->P * sizeof(double2)); return rc; }
     hipError_t e = hipMemcpyAsync(nr, c->d_rho, (size_t)(c->hist_cap + 1) * c->P * sizeof(double2),
                                   hipMemcpyDeviceToDevice, c->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(ns, c->d_stats, (size_t)(c->hist_cap + 1) * sizeof(StepStatsDev),
                            hipMemcpyDeviceToDevice, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    if (e != hipSuccess) { dev_free(c, nr); dev_free(c, ns); return hip_to_code(e); }
-    c->device_bytes -= (size_t)(c->hist_cap + 1) * (c->P * sizeof(double2) + sizeof(StepStatsDev));
-    dev_free(c, c->d_rho);
-    dev_free(c, c->d_stats);
+    if (e != hipSuccess) {
+        dev_free(c, nr, (size_t)(ncap + 1) * c->P * sizeof(double2));
+        dev_free(c, ns, (size_t)(ncap + 1) * sizeof(StepStatsDev));
+        return hip_to_code(e);
+    }
+    dev_free(c, c->d_rho, (size_t)(c->hist_cap + 1) * c->P * sizeof(double2));
+    dev_free(c, c->d_stats, (size_t)(c->hist_cap + 1) * sizeof(StepStatsDev));
     c->d_rho = nr;
     c->d_stats = ns;
     c->hist_cap = ncap;
@@ -143,12 +176,12 @@ int grow_history(quapi_ctx* c, int need) {
 // context back to the last complete step.
 int check_device_error(quapi_ctx* c) {
     if (c->err) return c->err;
-    unsigned int h[2] = {0, 0};
-    hipError_t e = hipMemcpy(h, c->d_error, sizeof h, hipMemcpyDeviceToHost);
+    unsigned int h = 0;
+    hipError_t e = hipMemcpy(&h, c->d_error, sizeof h, hipMemcpyDeviceToHost);
     if (e != hipSuccess) { c->err = hip_to_code(e); return c->err; }
-    if (h[0] == quapi_dev::kErrNone) return QUAPI_OK;
-    c->err = (h[0] == quapi_dev::kErrOverflow) ? QUAPI_ENOMEM : QUAPI_EDEVICE;
-    const int failed = (int)h[1];
+    if (h == 0u) return QUAPI_OK;
+    c->err = ((h & 15u) == quapi_dev::kErrOverflow) ? QUAPI_ENOMEM : QUAPI_EDEVICE;
+    const int failed = (int)(h >> 4);
     if (failed >= 1 && failed <= c->t) {
         c->t = failed - 1;
         c->cur = c->t & 1;
@@ -163,6 +196,12 @@ int sync_ctx(quapi_ctx* c) {
 }
 
 bool is_finite_d(double x) { return std::isfinite(x); }
+
+long long ipow(long long b, int e) {
+    long long r = 1;
+    for (int i = 0; i < e; ++i) r *= b;
+    return r;
+}
 
 }  // namespace
 
@@ -255,13 +294,20 @@ int quapi_create(const quapi_params* p, quapi_ctx** out) {
     c->dt = p->dt;
     c->theta = p->theta;
 
-    // capacity of one run: all keys with a fixed newest point, or the cap given
-    long long space = 1;
-    for (int i = 0; i < L - 1 && space < (1ll << 40); ++i) space *= P;
-    long long cap = std::min(space, p->max_groups > 0 ? p->max_groups : (1ll << 25));
-    cap = std::min(cap, (1ll << 30) - 1);
+    // buckets: the top D points of the key; D-1 chosen so that there are up to
+    // 8192 super-buckets (one workgroup each); a bucket holds every key of its
+    // prefix, or its share of max_groups
+    long long max_super = 8192;   // tuning knob: upper bound on the number of super-buckets
+    if (const char* env = std::getenv("QUAPI_MAX_SUPER")) max_super = std::max(1ll, std::atoll(env));
+    int dm1 = 0;
+    while (dm1 + 1 <= L - 1 && ipow(P, dm1 + 1) <= max_super) ++dm1;
+    c->D = dm1 + 1;
+    c->n_super = (int)ipow(P, dm1);
+    c->n_buckets = ipow(P, c->D);
+    long long cap = ipow(P, L - c->D);
+    if (p->max_groups > 0) cap = std::max(1ll, std::min(cap, (p->max_groups + c->n_buckets - 1) / c->n_buckets));
+    if (cap >= (1ll << 31)) cap = (1ll << 31) - 1;
     c->cap = cap;
-    c->max_tiles = quapi_dev::max_tiles_for(P, cap);
 
     // tables: K4[pn][po] = U[an][ao] conj(U[bn][bo]); ds, ss; eta
     std::vector<double> U(2 * M * M);
@@ -283,14 +329,31 @@ int quapi_create(const quapi_params* p, quapi_ctx** out) {
         c->tables[TableLayout::eta(P) + 2 * i] = p->eta[i].re;
         c->tables[TableLayout::eta(P) + 2 * i + 1] = p->eta[i].im;
     }
+    // coefficients of the new point at step t with the point at lag d (eq. inf_fun
+    // windows): interior partners use the interior column, the time-0 partner
+    // (d == t) the half-window column; the end-point correction of rho(t) swaps
+    // the final point's interior coefficients for its half-window ones
+    const int n = K + 1;
+    c->coef.assign((size_t)(K + 1) * 4 * n, 0.0);
+    for (int t = 1; t <= K + 1; ++t) {
+        double* cs = c->coef.data() + (size_t)(t - 1) * 4 * n;
+        for (int d = 0; d <= K && d <= t; ++d) {
+            const quapi_c64 in = p->eta[d], hf = p->eta[n + d], hh = p->eta[2 * n + d];
+            const quapi_c64 cc = (d == t) ? hf : in;
+            quapi_c64 dd;
+            if (d == 0) dd = {hf.re - in.re, hf.im - in.im};
+            else if (d == t) dd = {hh.re - hf.re, hh.im - hf.im};
+            else dd = {hf.re - in.re, hf.im - in.im};
+            cs[d] = cc.re;
+            cs[n + d] = cc.im;
+            cs[2 * n + d] = dd.re;
+            cs[3 * n + d] = dd.im;
+        }
+    }
 
     // t = 0: one group per nonzero element of rho0 with the initial point's self term
     c->rho0.resize(2 * P);
-    c->init_key.assign(P, 0);
-    c->init_tail.assign(P, 0);
-    c->init_w.assign(P, make_double2(0, 0));
-    c->init_count.assign(P, 0);
-    const std::complex<double> e0(p->eta[K + 1].re, p->eta[K + 1].im);   // end-point self term
+    const std::complex<double> e0(p->eta[n].re, p->eta[n].im);   // end-point self term
     for (int pp = 0; pp < P; ++pp) {
         const std::complex<double> r(p->rho0[pp].re, p->rho0[pp].im);
         c->rho0[2 * pp] = r.real();
@@ -298,9 +361,9 @@ int quapi_create(const quapi_params* p, quapi_ctx** out) {
         if (r == std::complex<double>(0, 0)) continue;
         const double ds = c->tables[TableLayout::ds(P) + pp], ss = c->tables[TableLayout::ss(P) + pp];
         const std::complex<double> w = r * std::exp(std::complex<double>(-ds * e0.real() * ds, -ds * e0.imag() * ss));
-        c->init_key[pp] = (unsigned long long)pp << (bits * (L - 1));
-        c->init_w[pp] = make_double2(w.real(), w.imag());
-        c->init_count[pp] = 1;
+        c->init_key.push_back((unsigned long long)pp << (bits * (L - 1)));
+        c->init_w.push_back(make_double2(w.real(), w.imag()));
+        c->init_bucket.push_back((long long)pp * c->n_super);   // top D points (pp, 0, ..., 0)
     }
 
     int rc = QUAPI_OK;
@@ -313,26 +376,23 @@ int quapi_create(const quapi_params* p, quapi_ctx** out) {
         }
         c->own_stream = true;
     }
-    int dev = 0, ncu = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
-        quapi_destroy(c);
-        return QUAPI_EDEVICE;
-    }
-    c->grid = std::max(1, std::min(c->max_tiles, 4 * std::max(ncu, 1)));
 
-    const size_t n = (size_t)P * (size_t)cap;
+    const size_t nrec = (size_t)c->n_buckets * (size_t)cap;
     for (int b = 0; b < 2 && rc == QUAPI_OK; ++b) {
-        rc = dev_alloc(c, &c->buf[b].key, n);
-        if (!rc) rc = dev_alloc(c, &c->buf[b].tail, n);
-        if (!rc) rc = dev_alloc(c, &c->buf[b].w, n);
-        if (!rc) rc = dev_alloc(c, &c->counts[b], (size_t)P);
+        rc = dev_alloc(c, &c->buf[b].key, nrec);
+        if (!rc) rc = dev_alloc(c, &c->buf[b].tail, nrec);
+        if (!rc) rc = dev_alloc(c, &c->buf[b].w, nrec);
+        if (!rc) rc = dev_alloc(c, &c->counts[b], (size_t)c->n_buckets);
     }
     if (!rc) rc = dev_alloc(c, &c->d_tables, c->tables.size());
-    if (!rc) rc = dev_alloc(c, &c->d_counters, 4);
-    if (!rc) rc = dev_alloc(c, &c->d_status, (size_t)P * c->max_tiles);
-    if (!rc) rc = dev_alloc(c, &c->d_partials, (size_t)c->max_tiles);
-    if (!rc) rc = dev_alloc(c, &c->d_error, 2);
+    if (!rc) rc = dev_alloc(c, &c->d_coef, c->coef.size());
+    c->max_chunks = (int)std::min<long long>((long long)nrec / quapi_dev::chunk_heads(P) + 2, 1ll << 30);
+    if (!rc) rc = dev_alloc(c, &c->d_partials, (size_t)c->max_chunks * quapi_dev::partial_stride(P));
+    if (!rc) rc = dev_alloc(c, &c->d_prefix, (size_t)c->n_buckets + 1);
+    if (!rc) rc = dev_alloc(c, &c->d_chunk_start, (size_t)2 * c->max_chunks);
+    if (!rc) rc = dev_alloc(c, &c->d_plan, 2);
+    if (!rc) rc = dev_alloc(c, &c->d_chain, (size_t)(P + 1) * c->max_chunks);
+    if (!rc) rc = dev_alloc(c, &c->d_error, 1);
     c->hist_cap = p->max_steps > 0 ? p->max_steps : 1024;
     if (!rc) rc = dev_alloc(c, &c->d_rho, (size_t)(c->hist_cap + 1) * P);
     if (!rc) rc = dev_alloc(c, &c->d_stats, (size_t)(c->hist_cap + 1));
@@ -342,14 +402,27 @@ int quapi_create(const quapi_params* p, quapi_ctx** out) {
     }
     hipError_t e = hipMemcpyAsync(c->d_tables, c->tables.data(), c->tables.size() * sizeof(double),
                                   hipMemcpyHostToDevice, c->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(c->d_counters, 0, 4 * sizeof(unsigned int), c->stream);
     if (e == hipSuccess)
-        e = hipMemsetAsync(c->d_status, 0, (size_t)P * c->max_tiles * sizeof(unsigned long long), c->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(c->counts[1], 0, P * sizeof(unsigned int), c->stream);
+        e = hipMemcpyAsync(c->d_coef, c->coef.data(), c->coef.size() * sizeof(double), hipMemcpyHostToDevice,
+                           c->stream);
+    if (e == hipSuccess)
+        e = hipMemsetAsync(c->d_chain, 0, (size_t)(P + 1) * c->max_chunks * sizeof(unsigned long long), c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c->d_plan, 0, 2 * sizeof(quapi_dev::Plan), c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
         quapi_destroy(c);
         return hip_to_code(e);
     }
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        quapi_destroy(c);
+        return QUAPI_EDEVICE;
+    }
+    // persistent workgroups per compute unit (tuning knob; any value >= 1 is correct)
+    int per_cu = 3;
+    if (const char* env = std::getenv("QUAPI_BLOCKS_PER_CU")) per_cu = std::max(1, std::min(16, std::atoi(env)));
+    c->grid = std::max(1, std::min(c->max_chunks, per_cu * std::max(ncu, 1)));
     rc = upload_initial(c);
     if (rc) {
         quapi_destroy(c);
@@ -367,35 +440,42 @@ int quapi_step(quapi_ctx* c, int n_steps) {
     if (rc) return rc;
     StepArgs a;
     a.cap = c->cap;
+    a.n_buckets = c->n_buckets;
     a.P = c->P;
     a.L = c->L;
     a.K = c->K;
-    a.bits = c->bits;
-    a.max_tiles = c->max_tiles;
+    a.n_super = c->n_super;
     a.theta2 = c->theta * c->theta;
     a.qmask = c->qbits >= 64 ? 0ull : ~((1ull << c->qbits) - 1ull);
     a.tables = c->d_tables;
-    a.counters = c->d_counters;
-    a.status = c->d_status;
+    a.prefix = c->d_prefix;
+    a.chunk_start = c->d_chunk_start;
+    a.chain = c->d_chain;
+    a.max_chunks = c->max_chunks;
     a.partials = c->d_partials;
     a.error = c->d_error;
+    const int n = c->K + 1;
     for (int k = 0; k < n_steps; ++k) {
         const int t = c->t + 1;
         a.in = c->buf[c->cur];
         a.out = c->buf[1 - c->cur];
         a.in_count = c->counts[c->cur];
         a.out_count = c->counts[1 - c->cur];
+        a.plan = c->d_plan + (t & 1);
         a.t = t;
         a.epoch = ++c->epoch;
-        a.rho_out = c->d_rho + (size_t)t * c->P;
-        a.stats_out = c->d_stats + t;
-        const int e = quapi_dev::launch_step(a, c->grid, c->stream);
-        if (e != (int)hipSuccess) {
+        a.coef = c->d_coef + (size_t)(std::min(t, c->K + 1) - 1) * 4 * n;
+        if (quapi_dev::launch_step(a, c->grid, c->stream) != (int)hipSuccess) {
             c->err = QUAPI_EDEVICE;
             return c->err;
         }
         c->t = t;
         c->cur = 1 - c->cur;
+        // reduce step t and plan step t+1
+        if (launch_planner(c, t) != QUAPI_OK) {
+            c->err = QUAPI_EDEVICE;
+            return c->err;
+        }
     }
     return QUAPI_OK;
 }
@@ -451,36 +531,37 @@ int quapi_groups(quapi_ctx* c, long long cap, unsigned char* hist, quapi_c64* w,
     if (!c || !n_out || cap < 0 || (cap > 0 && (!hist || !w))) return QUAPI_EINVAL;
     const int rc = sync_ctx(c);
     if (rc == QUAPI_EDEVICE) return rc;
-    std::vector<unsigned int> cnt(c->P);
-    hipError_t e = hipMemcpy(cnt.data(), c->counts[c->cur], c->P * sizeof(unsigned int), hipMemcpyDeviceToHost);
+    std::vector<unsigned int> cnt((size_t)c->n_buckets);
+    hipError_t e = hipMemcpy(cnt.data(), c->counts[c->cur], cnt.size() * sizeof(unsigned int),
+                             hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_to_code(e);
     long long n = 0;
     for (unsigned int x : cnt) n += x;
     *n_out = n;
-    long long written = 0;
+    if (cap == 0) return QUAPI_OK;
+    const size_t nrec = (size_t)c->n_buckets * (size_t)c->cap;
+    std::vector<unsigned long long> k(nrec), tl(nrec);
+    std::vector<double2> ww(nrec);
+    e = hipMemcpy(k.data(), c->buf[c->cur].key, nrec * 8, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(tl.data(), c->buf[c->cur].tail, nrec * 8, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(ww.data(), c->buf[c->cur].w, nrec * 16, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_to_code(e);
     const unsigned long long dm = (1ull << c->bits) - 1;
-    for (int p = 0; p < c->P && written < cap; ++p) {
-        const long long m = std::min<long long>(cnt[p], cap - written);
-        if (m <= 0) continue;
-        std::vector<unsigned long long> k(m), tl(m);
-        std::vector<double2> ww(m);
-        const size_t o = (size_t)p * c->cap;
-        e = hipMemcpy(k.data(), c->buf[c->cur].key + o, m * 8, hipMemcpyDeviceToHost);
-        if (e == hipSuccess) e = hipMemcpy(tl.data(), c->buf[c->cur].tail + o, m * 8, hipMemcpyDeviceToHost);
-        if (e == hipSuccess) e = hipMemcpy(ww.data(), c->buf[c->cur].w + o, m * 16, hipMemcpyDeviceToHost);
-        if (e != hipSuccess) return hip_to_code(e);
-        for (long long i = 0; i < m; ++i) {
-            unsigned char* row = hist + (size_t)(written + i) * c->K;
+    long long written = 0;
+    for (long long b = 0; b < c->n_buckets && written < cap; ++b) {
+        for (unsigned int r = 0; r < cnt[b] && written < cap; ++r) {
+            const size_t o = (size_t)b * (size_t)c->cap + r;
+            unsigned char* row = hist + (size_t)written * c->K;
             for (int j = 0; j < c->K; ++j) {
                 unsigned long long d;
-                if (j < c->L) d = (k[i] >> (c->bits * (c->L - 1 - j))) & dm;
-                else d = (tl[i] >> (c->bits * (j - c->L))) & dm;
+                if (j < c->L) d = (k[o] >> (c->bits * (c->L - 1 - j))) & dm;
+                else d = (tl[o] >> (c->bits * (j - c->L))) & dm;
                 row[j] = (unsigned char)d;
             }
-            w[written + i].re = ww[i].x;
-            w[written + i].im = ww[i].y;
+            w[written].re = ww[o].x;
+            w[written].im = ww[o].y;
+            ++written;
         }
-        written += m;
     }
     return QUAPI_OK;
 }
@@ -499,7 +580,7 @@ int quapi_info(quapi_ctx* c, quapi_info_t* out) {
     out->L = c->L;
     out->bits_per_point = c->bits;
     out->record_bytes = 32;
-    out->capacity = (long long)c->P * c->cap;
+    out->capacity = c->n_buckets * c->cap;
     out->device_bytes = c->device_bytes;
     return QUAPI_OK;
 }

@@ -14,20 +14,21 @@ constexpr int kThreads = 256;      // threads per tile = parents loaded per tile
 constexpr int kMaxP = 16;          // pairs per point (M <= 4)
 constexpr int kMaxK = 64;          // memory length bound (history words)
 
-// Stored group list: P runs ("classes"), one per value of the newest point.
-// Run c holds count[c] groups sorted by key; its arrays start at c * cap.
+// Stored group list: the key space is cut into P^D buckets by the top D
+// points of the merge key (point 0 most significant); bucket b holds count[b]
+// groups sorted by key at [b * cap, b * cap + count[b]).  A group is its key
+// (points 0..L-1, point 0 in the top bits), the rest of the representative's
+// history (points L..K-1, point L in the low bits) and the group amplitude.
 struct GroupBuf {
-    uint64_t* key;     // merge key: points 0..L-1, point 0 in the top bits
-    uint64_t* tail;    // points L..K-1, point L in the low bits
-    double2* w;        // group amplitude
+    uint64_t* key;
+    uint64_t* tail;
+    double2* w;
 };
 
-// Per-tile partial sums, reduced in tile order by the last tile to finish.
-struct TilePartial {
-    double2 rho[kMaxP];
-    double dropped;
-    unsigned long long n_surv;
-};
+// Per-chunk partial sums, partial_stride(P) doubles: rho(t) re/im for the P
+// pairs, dropped |w|, survivors.  The planner that follows a step reduces
+// them in chunk order.
+constexpr int partial_stride(int P) { return 2 * P + 2; }
 
 struct StepStatsDev {
     unsigned long long n_groups, n_children, n_survivors, n_stored;
@@ -35,24 +36,49 @@ struct StepStatsDev {
     double pad;
 };
 
+// Plan of one step, written by the planner: total groups, chunks, chunk counter.
+struct Plan {
+    unsigned int n_groups, n_chunks, counter, pad;
+};
+
 struct StepArgs {
     GroupBuf in, out;
-    const unsigned int* in_count;   // [P]
-    unsigned int* out_count;        // [P]
-    long long cap;                  // capacity of one run
+    const unsigned int* in_count;   // [P^D] bucket sizes
+    unsigned int* out_count;        // [P^D], zeroed by the planner
+    const unsigned int* prefix;     // [P^D + 1] exclusive prefix of in_count
+    const unsigned int* chunk_start;// [max_chunks] bucket holding each chunk's first group
+    Plan* plan;                     // this step's plan (counter is the chunk ticket)
+    long long cap;                  // capacity of one bucket
+    long long n_buckets;            // P^D
     int P, L, K, t;
+    int n_super;                    // P^(D-1)
     unsigned int epoch;             // monotonically increasing step number of the context
-    int bits;                       // bits per point
-    int max_tiles;
     double theta2;
     unsigned long long qmask;       // keep-mask of the |w|^2 bit pattern
     const double* tables;           // device tables, see TableLayout
-    unsigned int* counters;         // [4]: tile counter x2, done counter x2 (indexed by epoch parity)
-    unsigned long long* status;     // [P * max_tiles] look-back words
-    TilePartial* partials;          // [max_tiles]
-    double2* rho_out;               // rho(t): P values
-    StepStatsDev* stats_out;        // counters of step t
-    unsigned int* error;            // [2]: code, step
+    const double* coef;             // this step's coefficients: cre, cim, dre, dim [4][K+1]
+    unsigned long long* chain;      // [(P + 1) * max_chunks]: last super-bucket and its run totals per chunk
+    int max_chunks;
+    double* partials;               // [max_chunks * partial_stride(P)]
+    unsigned int* error;            // (failing step << 4) | code, 0 if none
+};
+
+struct PlanArgs {
+    const unsigned int* counts;     // [n_buckets] input bucket sizes of the step to plan
+    unsigned int* counts_next;      // [n_buckets] its output bucket sizes: zeroed here
+    unsigned int* prefix;           // [n_buckets + 1]
+    unsigned int* chunk_start;      // [max_chunks]
+    Plan* plan;                     // plan of the step to plan
+    const Plan* plan_prev;          // plan of the step just done (for its counters)
+    long long n_buckets;
+    int chunk_heads;                // groups whose segments start in one chunk
+    int max_chunks;
+    int P;
+    int reduce_t;                   // step whose partials to reduce, 0: none
+    const double* partials;
+    double2* rho_hist;              // [history * P]
+    StepStatsDev* stats_hist;       // [history]
+    const unsigned int* error;
 };
 
 // Device table layout (doubles): K4 re/im [2*P*P], ds[P], ss[P], eta [2*3*(K+1)]
@@ -67,7 +93,7 @@ struct TableLayout {
 enum : unsigned int { kErrNone = 0, kErrOverflow = 1, kErrSpin = 2 };
 
 int launch_step(const StepArgs& a, int grid, void* stream);   // returns hipError_t
-int max_tiles_for(int P, long long cap);
-int tile_heads(int P);
+int launch_plan(const PlanArgs& a, void* stream);
+int chunk_heads(int P);
 
 }  // namespace quapi_dev
