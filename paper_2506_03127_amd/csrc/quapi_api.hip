@@ -40,10 +40,11 @@ struct quapi_ctx {
     double* d_tables = nullptr;
     double* d_coef = nullptr;
     double* d_partials = nullptr;
-    unsigned int* d_prefix = nullptr;        // [n_buckets + 1]
-    unsigned int* d_chunk_start = nullptr;   // [2 * max_chunks]
+    unsigned int* d_nz_bucket = nullptr;     // [n_buckets] nonempty buckets of the stored groups
+    unsigned int* d_nz_prefix = nullptr;     // [n_buckets] their first global group index
+    unsigned int* d_desc = nullptr;          // [max_chunks] bucket rank of each chunk's first group
     quapi_dev::Plan* d_plan = nullptr;       // [2], by step parity
-    unsigned long long* d_chain = nullptr;   // [(P + 1) * max_chunks]
+    unsigned long long* d_chain = nullptr;   // [P * max_chunks] look-back words
     int max_chunks = 0;
     int grid = 0;
     double2* d_rho = nullptr;
@@ -128,8 +129,9 @@ int launch_planner(quapi_ctx* c, int t) {
     quapi_dev::PlanArgs pa;
     pa.counts = c->counts[c->cur];
     pa.counts_next = c->counts[1 - c->cur];
-    pa.prefix = c->d_prefix;
-    pa.chunk_start = c->d_chunk_start;
+    pa.nz_bucket = c->d_nz_bucket;
+    pa.nz_prefix = c->d_nz_prefix;
+    pa.desc = c->d_desc;
     pa.plan = c->d_plan + ((t + 1) & 1);
     pa.plan_prev = c->d_plan + (t & 1);
     pa.n_buckets = c->n_buckets;
@@ -294,11 +296,13 @@ int quapi_create(const quapi_params* p, quapi_ctx** out) {
     c->dt = p->dt;
     c->theta = p->theta;
 
-    // buckets: the top D points of the key; D-1 chosen so that there are up to
-    // 8192 super-buckets (one workgroup each); a bucket holds every key of its
-    // prefix, or its share of max_groups
-    long long max_super = 8192;   // tuning knob: upper bound on the number of super-buckets
-    if (const char* env = std::getenv("QUAPI_MAX_SUPER")) max_super = std::max(1ll, std::atoll(env));
+    // buckets: the top D points of the key; D-1 chosen so that there are as many
+    // super-buckets as the planner covers in one pass; a bucket holds every key
+    // of its prefix, or its share of max_groups
+    const long long plan_super = 1024ll * quapi_dev::plan_super_per_thread(M * M);
+    long long max_super = plan_super;   // tuning knob: upper bound on the number of super-buckets
+    if (const char* env = std::getenv("QUAPI_MAX_SUPER"))
+        max_super = std::max(1ll, std::min(plan_super, std::atoll(env)));
     int dm1 = 0;
     while (dm1 + 1 <= L - 1 && ipow(P, dm1 + 1) <= max_super) ++dm1;
     c->D = dm1 + 1;
@@ -306,7 +310,12 @@ int quapi_create(const quapi_params* p, quapi_ctx** out) {
     c->n_buckets = ipow(P, c->D);
     long long cap = ipow(P, L - c->D);
     if (p->max_groups > 0) cap = std::max(1ll, std::min(cap, (p->max_groups + c->n_buckets - 1) / c->n_buckets));
-    if (cap >= (1ll << 31)) cap = (1ll << 31) - 1;
+    // group indices are 32-bit: keep the whole store below 2^31 groups
+    cap = std::min(cap, ((1ll << 31) - 1) / c->n_buckets);
+    if (cap < 1) {
+        delete c;
+        return QUAPI_EUNSUPPORTED;
+    }
     c->cap = cap;
 
     // tables: K4[pn][po] = U[an][ao] conj(U[bn][bo]); ds, ss; eta
@@ -388,10 +397,11 @@ int quapi_create(const quapi_params* p, quapi_ctx** out) {
     if (!rc) rc = dev_alloc(c, &c->d_coef, c->coef.size());
     c->max_chunks = (int)std::min<long long>((long long)nrec / quapi_dev::chunk_heads(P) + 2, 1ll << 30);
     if (!rc) rc = dev_alloc(c, &c->d_partials, (size_t)c->max_chunks * quapi_dev::partial_stride(P));
-    if (!rc) rc = dev_alloc(c, &c->d_prefix, (size_t)c->n_buckets + 1);
-    if (!rc) rc = dev_alloc(c, &c->d_chunk_start, (size_t)2 * c->max_chunks);
+    if (!rc) rc = dev_alloc(c, &c->d_nz_bucket, (size_t)c->n_buckets);
+    if (!rc) rc = dev_alloc(c, &c->d_nz_prefix, (size_t)c->n_buckets);
+    if (!rc) rc = dev_alloc(c, &c->d_desc, (size_t)c->max_chunks);
     if (!rc) rc = dev_alloc(c, &c->d_plan, 2);
-    if (!rc) rc = dev_alloc(c, &c->d_chain, (size_t)(P + 1) * c->max_chunks);
+    if (!rc) rc = dev_alloc(c, &c->d_chain, (size_t)P * c->max_chunks);
     if (!rc) rc = dev_alloc(c, &c->d_error, 1);
     c->hist_cap = p->max_steps > 0 ? p->max_steps : 1024;
     if (!rc) rc = dev_alloc(c, &c->d_rho, (size_t)(c->hist_cap + 1) * P);
@@ -406,7 +416,7 @@ int quapi_create(const quapi_params* p, quapi_ctx** out) {
         e = hipMemcpyAsync(c->d_coef, c->coef.data(), c->coef.size() * sizeof(double), hipMemcpyHostToDevice,
                            c->stream);
     if (e == hipSuccess)
-        e = hipMemsetAsync(c->d_chain, 0, (size_t)(P + 1) * c->max_chunks * sizeof(unsigned long long), c->stream);
+        e = hipMemsetAsync(c->d_chain, 0, (size_t)P * c->max_chunks * sizeof(unsigned long long), c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(c->d_plan, 0, 2 * sizeof(quapi_dev::Plan), c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
@@ -419,10 +429,15 @@ int quapi_create(const quapi_params* p, quapi_ctx** out) {
         quapi_destroy(c);
         return QUAPI_EDEVICE;
     }
-    // persistent workgroups per compute unit (tuning knob; any value >= 1 is correct)
-    int per_cu = 3;
+    // persistent workgroups: as many as are resident at once (the look-back between
+    // chunks needs every workgroup of the grid resident); QUAPI_BLOCKS_PER_CU lowers it
+    int per_cu = 0;
     if (const char* env = std::getenv("QUAPI_BLOCKS_PER_CU")) per_cu = std::max(1, std::min(16, std::atoi(env)));
-    c->grid = std::max(1, std::min(c->max_chunks, per_cu * std::max(ncu, 1)));
+    c->grid = quapi_dev::step_grid(P, std::max(ncu, 1), per_cu);
+    if (c->grid < 1) {
+        quapi_destroy(c);
+        return QUAPI_EDEVICE;
+    }
     rc = upload_initial(c);
     if (rc) {
         quapi_destroy(c);
@@ -440,7 +455,6 @@ int quapi_step(quapi_ctx* c, int n_steps) {
     if (rc) return rc;
     StepArgs a;
     a.cap = c->cap;
-    a.n_buckets = c->n_buckets;
     a.P = c->P;
     a.L = c->L;
     a.K = c->K;
@@ -448,8 +462,9 @@ int quapi_step(quapi_ctx* c, int n_steps) {
     a.theta2 = c->theta * c->theta;
     a.qmask = c->qbits >= 64 ? 0ull : ~((1ull << c->qbits) - 1ull);
     a.tables = c->d_tables;
-    a.prefix = c->d_prefix;
-    a.chunk_start = c->d_chunk_start;
+    a.nz_bucket = c->d_nz_bucket;
+    a.nz_prefix = c->d_nz_prefix;
+    a.desc = c->d_desc;
     a.chain = c->d_chain;
     a.max_chunks = c->max_chunks;
     a.partials = c->d_partials;
@@ -459,7 +474,6 @@ int quapi_step(quapi_ctx* c, int n_steps) {
         const int t = c->t + 1;
         a.in = c->buf[c->cur];
         a.out = c->buf[1 - c->cur];
-        a.in_count = c->counts[c->cur];
         a.out_count = c->counts[1 - c->cur];
         a.plan = c->d_plan + (t & 1);
         a.t = t;

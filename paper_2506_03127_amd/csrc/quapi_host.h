@@ -36,42 +36,50 @@ struct StepStatsDev {
     double pad;
 };
 
-// Plan of one step, written by the planner: total groups, chunks, chunk counter.
+// Plan of one step, written by the planner.
 struct Plan {
-    unsigned int n_groups, n_chunks, counter, pad;
+    unsigned int n_groups;     // groups stored (input of the planned step)
+    unsigned int n_chunks;     // chunks of the planned step
+    unsigned int pad;
+    unsigned int n_nonempty;   // nonempty buckets
 };
+
+// Chunk c covers the global group indices [c*C, (c+1)*C) with C =
+// chunk_heads(P) (segment heads; it also reads the P-1 groups after them).
+// desc[c] is the index, in the list of nonempty buckets, of the bucket that
+// holds group c*C.
 
 struct StepArgs {
     GroupBuf in, out;
-    const unsigned int* in_count;   // [P^D] bucket sizes
-    unsigned int* out_count;        // [P^D], zeroed by the planner
-    const unsigned int* prefix;     // [P^D + 1] exclusive prefix of in_count
-    const unsigned int* chunk_start;// [max_chunks] bucket holding each chunk's first group
-    Plan* plan;                     // this step's plan (counter is the chunk ticket)
+    unsigned int* out_count;        // [P^D] output bucket sizes (zeroed by the planner)
+    const unsigned int* nz_bucket;  // [n_nonempty] nonempty input buckets, in key order
+    const unsigned int* nz_prefix;  // [n_nonempty] their first global group index
+    const unsigned int* desc;       // [n_chunks]
+    const Plan* plan;               // this step's plan
     long long cap;                  // capacity of one bucket
-    long long n_buckets;            // P^D
     int P, L, K, t;
     int n_super;                    // P^(D-1)
-    unsigned int epoch;             // monotonically increasing step number of the context
+    unsigned int epoch;             // step number of the context, tags the look-back words
     double theta2;
     unsigned long long qmask;       // keep-mask of the |w|^2 bit pattern
     const double* tables;           // device tables, see TableLayout
     const double* coef;             // this step's coefficients: cre, cim, dre, dim [4][K+1]
-    unsigned long long* chain;      // [(P + 1) * max_chunks]: last super-bucket and its run totals per chunk
+    unsigned long long* chain;      // [P * max_chunks] look-back words, one per chunk and pair
     int max_chunks;
     double* partials;               // [max_chunks * partial_stride(P)]
     unsigned int* error;            // (failing step << 4) | code, 0 if none
 };
 
 struct PlanArgs {
-    const unsigned int* counts;     // [n_buckets] input bucket sizes of the step to plan
-    unsigned int* counts_next;      // [n_buckets] its output bucket sizes: zeroed here
-    unsigned int* prefix;           // [n_buckets + 1]
-    unsigned int* chunk_start;      // [max_chunks]
+    const unsigned int* counts;     // [n_buckets] bucket sizes of the stored groups
+    unsigned int* counts_next;      // [n_buckets] output bucket sizes of the planned step: zeroed here
+    unsigned int* nz_bucket;        // [n_buckets]
+    unsigned int* nz_prefix;        // [n_buckets]
+    unsigned int* desc;             // [max_chunks]
     Plan* plan;                     // plan of the step to plan
     const Plan* plan_prev;          // plan of the step just done (for its counters)
     long long n_buckets;
-    int chunk_heads;                // groups whose segments start in one chunk
+    int chunk_heads;                // groups per chunk
     int max_chunks;
     int P;
     int reduce_t;                   // step whose partials to reduce, 0: none
@@ -95,5 +103,7 @@ enum : unsigned int { kErrNone = 0, kErrOverflow = 1, kErrSpin = 2 };
 int launch_step(const StepArgs& a, int grid, void* stream);   // returns hipError_t
 int launch_plan(const PlanArgs& a, void* stream);
 int chunk_heads(int P);
+int plan_super_per_thread(int P);   // super-buckets per planner thread (1024 threads)
+int step_grid(int P, int n_cu, int per_cu);   // persistent workgroups that are co-resident
 
 }  // namespace quapi_dev

@@ -17,22 +17,26 @@
 // (they differ only in point L-1, the lowest digit of the sorted order).  So
 // output positions are local to a super-bucket: no global scan is needed.
 //
-// Planner (between steps): prefix sum of the bucket sizes, so that the next
-// step can cut its input into full chunks of consecutive groups regardless
-// of bucket boundaries; it also zeroes the next bucket sizes, resets the
-// chunk ticket and reduces the finished step's per-chunk sums of rho(t) and
-// counters in chunk order (deterministic).
+// Planner (between steps): scans the bucket sizes, lists the nonempty
+// buckets with their first global group index and, for each chunk of C
+// consecutive groups of the global key order, the bucket holding its first
+// group.  It also zeroes the next bucket sizes and reduces the finished
+// step's per-chunk sums of rho(t) and counters in chunk order
+// (deterministic).
 //
-// Step: persistent workgroups take chunks in order.  A chunk extends each
+// Step: a co-resident grid of persistent workgroups takes chunks round-robin
+// and fetches each chunk's parents one chunk ahead.  A chunk extends each
 // parent by every pair (eq. SysP propagator element times the influence
 // factor of eq. inf_fun), drops children below theta (Sec. 2.1), merges each
 // segment of consecutive parents per p (sum of weights; representative of
 // largest quantised |w|^2, ties to the smaller history read from the oldest
 // point; Sec. 3.1.2), ranks the merged groups per output bucket with wave
-// ballots and a segmented block scan, and writes them.  rho(t) collects the
-// survivors with the end-point correction of the final point (Sec. 3.2.1).
-// A super-bucket cut by a chunk boundary continues at the offsets published
-// by the chunk before it; only such chunks wait, and only on that one chunk.
+// ballots and a block scan segmented by super-bucket, and writes them.
+// rho(t) collects the survivors with the end-point correction of the final
+// point (Sec. 3.2.1).  A super-bucket cut by a chunk boundary continues at
+// offsets found by a decoupled look-back: each chunk publishes the totals of
+// its last super-bucket run at once -- inclusive when they do not depend on
+// the chunks before it, its own otherwise, inclusive later.
 
 #include <hip/hip_runtime.h>
 
@@ -45,11 +49,13 @@ namespace {
 constexpr int kWaves = kThreads / 64;
 constexpr int kPlanThreads = 1024;
 constexpr int kPlanWaves = kPlanThreads / 64;
-constexpr int kWindow = 512;          // prefix entries cached per chunk for the bucket lookup
+constexpr int kWin = kThreads + 2;    // nonempty buckets cached per chunk (covers the group before it too)
 constexpr int kTabPts = 3;            // points per subset-sum table (two-level systems)
 constexpr int kTabEntries = 64;       // 4^3
 constexpr int kMaxTabs = 10;
 constexpr unsigned int kSpinLimit = 1u << 22;
+constexpr unsigned long long kAgg = 1ull << 32;   // look-back word: own totals only
+constexpr unsigned long long kInc = 2ull << 32;   // look-back word: inclusive totals
 
 __device__ inline double norm2_nocontract(double re, double im) {
 #pragma clang fp contract(off)
@@ -94,50 +100,94 @@ __device__ inline unsigned int error_word(const unsigned int* err) {
 }
 
 // ------------------------------------------------------------------ planner
-template <int P>
+// Thread i owns super-buckets [i*SPT, (i+1)*SPT), i.e. SPT*P consecutive buckets.
+template <int P, int SPT>
 __global__ __launch_bounds__(kPlanThreads) void plan_kernel(const PlanArgs a) {
     constexpr int S = partial_stride(P);
-    __shared__ unsigned int wsum[kPlanWaves];
+    constexpr int NBT = SPT * P;
+    __shared__ unsigned long long wsum[kPlanWaves];
     __shared__ double wred[kPlanWaves][S];
     const int i = threadIdx.x;
     const int wave = i >> 6;
     const unsigned int lane = lane_id();
     const long long NB = a.n_buckets;
-    const long long per = (NB + kPlanThreads - 1) / kPlanThreads;
-    const long long b_lo = (long long)i * per < NB ? (long long)i * per : NB;
-    const long long b_hi = b_lo + per < NB ? b_lo + per : NB;
+    const long long b_lo = (long long)i * NBT;
+    const bool full = b_lo + NBT <= NB;
 
-    // ---- exclusive prefix of the bucket sizes
-    unsigned int mine = 0;
-    for (long long b = b_lo; b < b_hi; ++b) mine += a.counts[b];
-    unsigned int incl = mine;
+    // ---- bucket sizes of this thread (one batch of independent loads)
+    unsigned int cnt[NBT];
+    if (full) {
+        if constexpr (NBT % 4 == 0) {
+            const uint4* src = reinterpret_cast<const uint4*>(a.counts + b_lo);
+#pragma unroll
+            for (int k = 0; k < NBT / 4; ++k) {
+                const uint4 v = src[k];
+                cnt[4 * k] = v.x;
+                cnt[4 * k + 1] = v.y;
+                cnt[4 * k + 2] = v.z;
+                cnt[4 * k + 3] = v.w;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < NBT; ++k) cnt[k] = a.counts[b_lo + k];
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < NBT; ++k) cnt[k] = b_lo + k < NB ? a.counts[b_lo + k] : 0u;
+    }
+
+    // ---- exclusive block scan of (groups, nonempty buckets), packed hi/lo
+    unsigned int tot = 0, nz = 0;
+#pragma unroll
+    for (int k = 0; k < NBT; ++k) {
+        tot += cnt[k];
+        nz += cnt[k] != 0u ? 1u : 0u;
+    }
+    const unsigned long long mine = ((unsigned long long)tot << 32) | nz;
+    unsigned long long incl = mine;
     for (int off = 1; off < 64; off <<= 1) {
-        const unsigned int v = __shfl_up(incl, off, 64);
+        const unsigned long long v = __shfl_up(incl, off, 64);
         if ((int)lane >= off) incl += v;
     }
     if (lane == 63) wsum[wave] = incl;
     __syncthreads();
-    unsigned int base = incl - mine;
-    for (int w = 0; w < wave; ++w) base += wsum[w];
-    unsigned int total = 0;
-    for (int w = 0; w < kPlanWaves; ++w) total += wsum[w];
-    const unsigned int C = (unsigned int)a.chunk_heads;
-    unsigned int run = base;
-    for (long long b = b_lo; b < b_hi; ++b) {
-        const unsigned int n = a.counts[b];
-        a.prefix[b] = run;
-        if (n) {
-            // chunk c starts in bucket b when c*C lies in [run, run+n); the
-            // group before it (c*C - 1) lies in b when c*C lies in [run+1, run+n]
-            for (unsigned int c = (run + C - 1) / C; c * C < run + n; ++c)
-                if ((int)c < a.max_chunks) a.chunk_start[2 * c] = (unsigned int)b;
-            for (unsigned int c = run / C + 1; c * C <= run + n; ++c)
-                if ((int)c < a.max_chunks) a.chunk_start[2 * c + 1] = (unsigned int)b;
-        }
-        run += n;
-        a.counts_next[b] = 0u;
+    unsigned long long base = incl - mine, total = 0;
+    for (int w = 0; w < kPlanWaves; ++w) {
+        if (w < wave) base += wsum[w];
+        total += wsum[w];
     }
-    if (i == kPlanThreads - 1) a.prefix[NB] = total;
+    const unsigned int N = (unsigned int)(total >> 32);
+    const unsigned int n_nz = (unsigned int)total;
+    const unsigned int C = (unsigned int)a.chunk_heads;
+    const unsigned int n_chunks = (N + C - 1) / C;
+
+    // ---- nonempty buckets; each chunk's first group lies in the one of rank desc[c]
+    unsigned int run = (unsigned int)(base >> 32), rank = (unsigned int)base;
+#pragma unroll
+    for (int k = 0; k < NBT; ++k) {
+        const unsigned int n = cnt[k];
+        if (n == 0u) continue;
+        a.nz_bucket[rank] = (unsigned int)(b_lo + k);
+        a.nz_prefix[rank] = run;
+        for (unsigned int c = (run + C - 1) / C; c * C < run + n; ++c)
+            if ((int)c < a.max_chunks) a.desc[c] = rank;
+        ++rank;
+        run += n;
+    }
+
+    // ---- zero the next step's bucket sizes
+    if (full) {
+        if constexpr (NBT % 4 == 0) {
+            uint4* dst = reinterpret_cast<uint4*>(a.counts_next + b_lo);
+#pragma unroll
+            for (int k = 0; k < NBT / 4; ++k) dst[k] = make_uint4(0u, 0u, 0u, 0u);
+        } else {
+#pragma unroll
+            for (int k = 0; k < NBT; ++k) a.counts_next[b_lo + k] = 0u;
+        }
+    } else {
+        for (long long b = b_lo; b < NB; ++b) a.counts_next[b] = 0u;
+    }
 
     // ---- counters and rho(t) of the step just finished, summed in chunk order
     const unsigned int err = error_word(a.error);
@@ -147,6 +197,7 @@ __global__ __launch_bounds__(kPlanThreads) void plan_kernel(const PlanArgs a) {
         double acc[S];
 #pragma unroll
         for (int k = 0; k < S; ++k) acc[k] = 0.0;
+#pragma unroll 4
         for (unsigned int c = i; c < nc; c += kPlanThreads)
 #pragma unroll
             for (int k = 0; k < S; ++k) acc[k] += a.partials[(size_t)c * S + k];
@@ -172,17 +223,17 @@ __global__ __launch_bounds__(kPlanThreads) void plan_kernel(const PlanArgs a) {
         st.n_groups = a.plan_prev->n_groups;
         st.n_children = st.n_groups * (unsigned long long)P;
         st.n_survivors = (unsigned long long)sum[2 * P + 1];
-        st.n_stored = total;
+        st.n_stored = N;
         st.dropped_abs = sum[2 * P];
         st.pad = 0.0;
         a.stats_hist[a.reduce_t] = st;
     }
     if (i == 0) {
         Plan pl;
-        pl.n_groups = total;
-        pl.n_chunks = (total + C - 1) / C;
-        pl.counter = 0u;
+        pl.n_groups = N;
+        pl.n_chunks = n_chunks;
         pl.pad = 0u;
+        pl.n_nonempty = n_nz;
         *a.plan = pl;
     }
 }
@@ -200,22 +251,107 @@ struct Lds {
     unsigned int surv[kThreads];           // bit p: child p survives
     unsigned int sig[kThreads];            // super-bucket of each loaded parent
     unsigned int excl[P][kThreads + 1];    // block-exclusive prefix of the output flags
-    unsigned int win[kWindow + 1];         // prefix window of the chunk
+    unsigned int win_b[kWin];              // nonempty buckets of the next chunk ...
+    unsigned int win_p[kWin];              // ... and their first global group index
     unsigned char flags[kThreads];         // bit 0 valid, bit 1 segment head
     unsigned int wcount[kWaves][P];
     int wstart[kWaves];                    // last super-bucket run start in each wave
-    unsigned int base[P];                  // offsets of the first run when it continues a chunk
+    unsigned int base[P];                  // offsets of the first run when it continues
     double2 wrho[kWaves][P];
     double wdrop[kWaves];
     double wsurv[kWaves];
-    unsigned long long prev_key;
+    unsigned long long prev_key;           // key of the group just before the chunk
+    unsigned int prev_sig;                 // its super-bucket
     double e0, f0;
-    int chunk, prev_sig;
 };
+
+// One thread's parent of a chunk, and (thread 0) the group before the chunk.
+struct Parent {
+    unsigned long long key, tail, pkey;
+    double2 w;
+    unsigned int sig, psig;               // 0xffffffff: none
+};
+
+// Window of nonempty buckets around a chunk: entries [rb, rb + kWin) of the
+// list, rb one before the bucket of the chunk's first group.  Thread i holds
+// entries i and kThreads + i (i < 2) until they are written to the LDS.
+struct WinRegs {
+    unsigned int b0, p0, b1, p1;
+};
+
+__device__ inline WinRegs load_window(const StepArgs& a, unsigned int first_rank, unsigned int n_nz,
+                                      unsigned int N, int i) {
+    const unsigned int rb = first_rank > 0u ? first_rank - 1u : 0u;
+    WinRegs w;
+    const unsigned int k0 = rb + (unsigned int)i, k1 = rb + kThreads + (unsigned int)i;
+    w.b0 = k0 < n_nz ? a.nz_bucket[k0] : 0u;
+    w.p0 = k0 < n_nz ? a.nz_prefix[k0] : N;
+    w.b1 = (i < kWin - kThreads && k1 < n_nz) ? a.nz_bucket[k1] : 0u;
+    w.p1 = (i < kWin - kThreads && k1 < n_nz) ? a.nz_prefix[k1] : N;
+    return w;
+}
+
+// largest k with win_p[k] <= g (win_p[0] <= g < win_p[kWin-1] holds for the chunk's groups)
+template <int P>
+__device__ inline int window_search(const Lds<P>& s, unsigned int g) {
+    int lo = 0, hi = kWin - 1;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (s.win_p[mid] <= g) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+template <int P, int C>
+__device__ inline Parent fetch_parent(const StepArgs& a, const Lds<P>& s, unsigned int c, unsigned int N,
+                                      long long nrec, int i) {
+    Parent r;
+    r.key = ~0ull;
+    r.tail = 0ull;
+    r.pkey = ~0ull;
+    r.w = make_double2(0.0, 0.0);
+    r.sig = 0xffffffffu;
+    r.psig = 0xffffffffu;
+    const unsigned int g0 = c * (unsigned int)C;
+    const unsigned int g = g0 + (unsigned int)i;
+    if (g < N && i < kThreads) {
+        const int k = window_search(s, g);
+        const unsigned int b = s.win_b[k];
+        const long long o = (long long)b * a.cap + (long long)(g - s.win_p[k]);
+        if (o < nrec) {
+            r.key = a.in.key[o];
+            r.tail = a.in.tail[o];
+            r.w = a.in.w[o];
+            r.sig = b / P;
+        } else {
+            raise_error(a.error, a.t, kErrOverflow);
+        }
+    }
+    if (i == 0 && g0 > 0u) {
+        const int k = window_search(s, g0 - 1u);
+        const unsigned int b = s.win_b[k];
+        const long long o = (long long)b * a.cap + (long long)(g0 - 1u - s.win_p[k]);
+        if (o < nrec) {
+            r.pkey = a.in.key[o];
+            r.psig = b / P;
+        }
+    }
+    return r;
+}
+
+template <int P>
+__device__ inline void store_window(Lds<P>& s, const WinRegs& w, int i) {
+    s.win_b[i] = w.b0;
+    s.win_p[i] = w.p0;
+    if (i < kWin - kThreads) {
+        s.win_b[kThreads + i] = w.b1;
+        s.win_p[kThreads + i] = w.p1;
+    }
+}
 
 template <int P, int BP>
 __global__ __launch_bounds__(kThreads) void step_kernel(const StepArgs a) {
-    constexpr int C = kThreads - (P - 1);              // segment heads per full chunk
+    constexpr int C = kThreads - (P - 1);              // segment heads per chunk
     constexpr int S = partial_stride(P);
     constexpr unsigned long long DM = (1ull << BP) - 1;
     __shared__ Lds<P> s;
@@ -224,6 +360,19 @@ __global__ __launch_bounds__(kThreads) void step_kernel(const StepArgs a) {
     const unsigned int lane = lane_id();
 
     if (error_word(a.error) != 0u) return;             // an earlier step failed: leave the state alone
+    const unsigned int N = a.plan->n_groups;
+    const unsigned int n_chunks = a.plan->n_chunks;
+    const unsigned int n_nz = a.plan->n_nonempty;
+    const unsigned int G = gridDim.x;
+    unsigned int c = blockIdx.x;
+    if (c >= n_chunks) return;
+
+    // ---- the first chunk's window and the next one's, in flight during the set-up
+    const long long nrec = (long long)a.n_super * P * a.cap;
+    WinRegs wr = load_window(a, a.desc[c], n_nz, N, i);
+    WinRegs wn = {0u, 0u, 0u, 0u};
+    if (c + G < n_chunks) wn = load_window(a, a.desc[c + G], n_nz, N, i);
+    unsigned int d_after = (c + 2 * G < n_chunks) ? a.desc[c + 2 * G] : 0u;
 
     // ---- tables and coefficients of this step
     const int K = a.K, L = a.L, t = a.t;
@@ -242,7 +391,9 @@ __global__ __launch_bounds__(kThreads) void step_kernel(const StepArgs a) {
     }
     const int nk = (L + kTabPts - 1) / kTabPts, nt = (K - L + kTabPts - 1) / kTabPts;
     const bool use_tabs = (P == 4) && (nk + nt <= kMaxTabs);
+    store_window(s, wr, i);
     __syncthreads();
+    Parent cur = fetch_parent<P, C>(a, s, c, N, nrec, i);
     if constexpr (P == 4) {
         if (use_tabs) {
             // tab[q][v] = sum over the points of table q of coefficient(lag) * (ds, ss)(point)
@@ -276,75 +427,44 @@ __global__ __launch_bounds__(kThreads) void step_kernel(const StepArgs a) {
         }
     }
 
-    const unsigned int N = a.plan->n_groups;
-    const unsigned int n_chunks = a.plan->n_chunks;
     const int dmax = t < K ? t : K;
     const int tail_pts = K - L;
     const unsigned long long tail_mask =
         tail_pts <= 0 ? 0ull : (tail_pts * BP >= 64 ? ~0ull : ((1ull << (tail_pts * BP)) - 1));
     const int top_shift = BP * (L - 1);
-    const unsigned long long ep = (unsigned long long)a.epoch << 32;
+    const unsigned long long etag = (unsigned long long)(a.epoch & 0x3fffffffu);
+    const unsigned long long ep = etag << 34;
 
     for (;;) {
-        __syncthreads();
-        if (i == 0) s.chunk = (int)atomicAdd(&a.plan->counter, 1u);
-        __syncthreads();
-        const int c = s.chunk;
-        if (c >= (int)n_chunks) break;
-        const unsigned int g0 = (unsigned int)c * C;
-        const unsigned int nsz = min((unsigned int)kThreads, N - g0);
-        const int H = (c == (int)n_chunks - 1) ? (int)nsz : C;   // heads owned by this chunk: [0, H)
+        // ---- fetch the next chunk's parents now; they arrive while this chunk computes
+        const bool has_next = c + G < n_chunks;
+        Parent nxt = cur;
+        __syncthreads();                                   // the chunk before is done with the LDS
+        if (has_next) {
+            store_window(s, wn, i);
+            __syncthreads();
+            nxt = fetch_parent<P, C>(a, s, c + G, N, nrec, i);
+            if (c + 2 * G < n_chunks) wn = load_window(a, d_after, n_nz, N, i);
+            d_after = (c + 3 * G < n_chunks) ? a.desc[c + 3 * G] : 0u;
+        }
 
-        // ---- bucket lookup: prefix window from the chunk's first bucket
-        const unsigned int b0 = a.chunk_start[2 * c];
-        const int kw = (int)min((long long)kWindow, a.n_buckets - (long long)b0);
-        for (int k = i; k <= kw; k += kThreads) s.win[k] = a.prefix[b0 + k];
-        if (i == 0) {
-            int psig = -1;
-            unsigned long long pk = ~0ull;
-            if (g0 > 0) {
-                const unsigned int bp = a.chunk_start[2 * c + 1];   // bucket of group g0-1
-                const unsigned int off = g0 - 1 - a.prefix[bp];
-                pk = a.in.key[(size_t)bp * a.cap + off];
-                psig = (int)(bp / P);
-            }
-            s.prev_key = pk;
-            s.prev_sig = psig;
-        }
-        __syncthreads();
-        const unsigned int g = g0 + i;
-        const bool valid = i < (int)nsz;
-        unsigned long long key = ~0ull, tail = 0;
-        double2 W = make_double2(0.0, 0.0);
-        unsigned int b = b0;
-        if (valid) {
-            if (g < s.win[kw]) {                              // largest k with win[k] <= g
-                int lo = 0, hi = kw;                           // win[lo] <= g < win[hi]
-                while (hi - lo > 1) {
-                    const int mid = (lo + hi) >> 1;
-                    if (s.win[mid] <= g) lo = mid; else hi = mid;
-                }
-                b = b0 + lo;
-            } else {                                           // beyond the window: search the prefix
-                long long lo = (long long)b0 + kw, hi = a.n_buckets;
-                while (hi - lo > 1) {
-                    const long long mid = (lo + hi) >> 1;
-                    if (a.prefix[mid] <= g) lo = mid; else hi = mid;
-                }
-                b = (unsigned int)lo;
-            }
-            const unsigned int pb = ((int)(b - b0) <= kw) ? s.win[b - b0] : a.prefix[b];
-            const size_t o = (size_t)b * (size_t)a.cap + (g - pb);
-            key = a.in.key[o];
-            tail = a.in.tail[o];
-            W = a.in.w[o];
-        }
-        const unsigned int my_sig = valid ? b / P : 0xffffffffu;
+        // ---- this chunk: groups [g0, g0 + nsz) loaded, segment heads [g0, g0 + H) owned
+        const unsigned int g0 = c * (unsigned int)C;
+        const unsigned int nsz = min((unsigned int)kThreads, N - g0);
+        const int H = (int)min((unsigned int)C, N - g0);
+        const bool valid = cur.sig != 0xffffffffu;
+        const unsigned long long key = cur.key, tail = cur.tail;
+        const double2 W = cur.w;
+        const unsigned int my_sig = cur.sig;
         s.key[i] = key;
         s.sig[i] = my_sig;
+        if (i == 0) {
+            s.prev_key = cur.pkey;
+            s.prev_sig = cur.psig;
+        }
         __syncthreads();
-        const unsigned long long prev_key = i > 0 ? s.key[i - 1] : s.prev_key;
-        const bool head = valid && (g == 0 || (key >> BP) != (prev_key >> BP));
+        const unsigned long long pk = i > 0 ? s.key[i - 1] : s.prev_key;
+        const bool head = valid && (g0 + i == 0u || (key >> BP) != (pk >> BP));
         s.flags[i] = (unsigned char)((valid ? 1 : 0) | (head ? 2 : 0));
         __syncthreads();
         // a parent belongs to this chunk when its segment head does
@@ -427,9 +547,9 @@ __global__ __launch_bounds__(kThreads) void step_kernel(const StepArgs a) {
                     er[p] = 1.0; ei[p] = 0.0; fr[p] = 1.0; fi[p] = 0.0;
                     if (dsp != 0.0) {
                         const double e = exp(-dsp * (s.cre[0] * dsp + A));
-                        double sn, cs;
-                        sincos(-dsp * (s.cim[0] * ssp + B), &sn, &cs);
-                        er[p] = e * cs;
+                        double sn, cs2;
+                        sincos(-dsp * (s.cim[0] * ssp + B), &sn, &cs2);
+                        er[p] = e * cs2;
                         ei[p] = e * sn;
                         const double f = exp(-dsp * (s.dre[0] * dsp + Ac));
                         double fs, fc;
@@ -444,19 +564,19 @@ __global__ __launch_bounds__(kThreads) void step_kernel(const StepArgs a) {
                 const double k4r = s.k4re[p * P + h0], k4i = s.k4im[p * P + h0];
                 const double br = W.x * k4r - W.y * k4i;
                 const double bi = W.x * k4i + W.y * k4r;
-                const double wr = br * er[p] - bi * ei[p];
-                const double wi = br * ei[p] + bi * er[p];
-                const double n2 = norm2_nocontract(wr, wi);
+                const double wr2 = br * er[p] - bi * ei[p];
+                const double wi2 = br * ei[p] + bi * er[p];
+                const double n2 = norm2_nocontract(wr2, wi2);
                 const bool keep = (a.theta2 == 0.0) || !(n2 < a.theta2);
                 if (keep) {
                     surv_bits |= 1u << p;
                     ++n_surv;
-                    rho_re[p] = wr * fr[p] - wi * fi[p];
-                    rho_im[p] = wr * fi[p] + wi * fr[p];
+                    rho_re[p] = wr2 * fr[p] - wi2 * fi[p];
+                    rho_im[p] = wr2 * fi[p] + wi2 * fr[p];
                 } else {
                     dropped += sqrt(n2);
                 }
-                s.cw[p][i] = make_double2(wr, wi);
+                s.cw[p][i] = make_double2(wr2, wi2);
             }
         }
         s.surv[i] = surv_bits;
@@ -473,12 +593,12 @@ __global__ __launch_bounds__(kThreads) void step_kernel(const StepArgs a) {
             if (lane == 0) s.wrho[wave][p] = make_double2(r, m);
         }
         {
-            double d = dropped, ns = (double)n_surv;
+            double dsum = dropped, ns = (double)n_surv;
             for (int off = 32; off > 0; off >>= 1) {
-                d += __shfl_xor(d, off, 64);
+                dsum += __shfl_xor(dsum, off, 64);
                 ns += __shfl_xor(ns, off, 64);
             }
-            if (lane == 0) { s.wdrop[wave] = d; s.wsurv[wave] = ns; }
+            if (lane == 0) { s.wdrop[wave] = dsum; s.wsurv[wave] = ns; }
         }
         __syncthreads();
 
@@ -545,7 +665,7 @@ __global__ __launch_bounds__(kThreads) void step_kernel(const StepArgs a) {
                     if (s.wstart[w] >= 0) { start = s.wstart[w]; break; }
             }
         }
-        if (i < S) {                                           // this chunk's partial sums
+        if (i < S) {                                       // this chunk's partial sums
             double v = 0.0;
             if (i < 2 * P) {
                 const int p = i >> 1;
@@ -559,44 +679,46 @@ __global__ __launch_bounds__(kThreads) void step_kernel(const StepArgs a) {
         }
         __syncthreads();
 
-        // ---- chain between chunks: the first run continues a super-bucket cut by the
-        //      chunk boundary when the group before the chunk lies in the same one
-        const bool first_cont = (g0 > 0) && (s.prev_sig == (int)s.sig[0]);
-        const unsigned int last_sig = s.sig[H - 1];
-        // publish this chunk's last-run totals; they are final unless that run is the
-        // continued first run, which needs the previous chunk's totals first
-        const bool last_needs_base = (i == H - 1) && first_cont && (start == 0);
-        if (i == H - 1 && !last_needs_base) {
+        // ---- look-back: the first run continues a super-bucket cut by the chunk boundary
+        const bool first_cont = g0 > 0u && s.prev_sig == s.sig[0];
+        const bool next_cont = (c + 1 < n_chunks) && s.sig[H - 1] == s.sig[H];
+        const bool from_prev = (start == 0) && first_cont;
+        unsigned long long* const slot_c = a.chain + c;
+        if (next_cont && i == H - 1) {
+            // totals of the last run: inclusive now unless they start with the continued run
 #pragma unroll
             for (int p = 0; p < P; ++p)
-                st_relaxed(a.chain + (size_t)(1 + p) * a.max_chunks + c, ep | (s.excl[p][H] - s.excl[p][start]));
-            st_relaxed(a.chain + c, ep | last_sig);
+                st_relaxed(slot_c + (size_t)p * a.max_chunks,
+                           ep | (from_prev ? kAgg : kInc) | (s.excl[p][H] - s.excl[p][start]));
         }
-        if (wave == 0) {
-            unsigned int base_p = 0;
-            if (first_cont && (int)lane < P) {
-                const unsigned long long* cp = a.chain + (size_t)(1 + lane) * a.max_chunks + (c - 1);
-                unsigned int spins = 0;
+        if (first_cont) {
+            if (wave == 0 && (int)lane < P) {
+                const unsigned long long* row = a.chain + (size_t)lane * a.max_chunks;
+                unsigned int sum = 0u, slot = c - 1u, spins = 0u;
                 for (;;) {
-                    const unsigned long long v = ld_relaxed(cp);
-                    if ((v >> 32) == (unsigned long long)a.epoch) { base_p = (unsigned int)(v & 0xffffffffu); break; }
-                    if (++spins > kSpinLimit) { raise_error(a.error, t, kErrSpin); break; }
-                    __builtin_amdgcn_s_sleep(1);
+                    const unsigned long long v = ld_relaxed(row + slot);
+                    if ((v >> 34) != etag) {
+                        if (++spins > kSpinLimit) { raise_error(a.error, t, kErrSpin); break; }
+                        __builtin_amdgcn_s_sleep(1);
+                        continue;
+                    }
+                    sum += (unsigned int)v;
+                    if (v & kInc) break;
+                    if (slot == 0u) { raise_error(a.error, t, kErrSpin); break; }
+                    --slot;
                 }
+                s.base[lane] = sum;
             }
-            if ((int)lane < P) s.base[lane] = first_cont ? base_p : 0u;
-        }
-        __syncthreads();
-        if (last_needs_base) {
+            __syncthreads();
+            if (next_cont && from_prev && i == H - 1) {
 #pragma unroll
-            for (int p = 0; p < P; ++p)
-                st_relaxed(a.chain + (size_t)(1 + p) * a.max_chunks + c,
-                           ep | (s.excl[p][H] - s.excl[p][0] + s.base[p]));
-            st_relaxed(a.chain + c, ep | last_sig);
+                for (int p = 0; p < P; ++p)
+                    st_relaxed(slot_c + (size_t)p * a.max_chunks,
+                               ep | kInc | (s.excl[p][H] - s.excl[p][0] + s.base[p]));
+            }
         }
 
         // ---- write merged groups to the output buckets (p, sigma)
-        const bool from_prev = (start == 0) && first_cont;
         if (is_head) {
 #pragma unroll
             for (int p = 0; p < P; ++p) {
@@ -613,17 +735,22 @@ __global__ __launch_bounds__(kThreads) void step_kernel(const StepArgs a) {
                 a.out.w[o] = ow[p];
             }
         }
-        // bucket sizes: the last parent of each run records the run totals (a later
-        // chunk continuing the run records larger totals; the maximum wins)
-        if (i < H && (i == H - 1 || s.sig[i + 1] != my_sig)) {
+        // bucket sizes: the last parent of each run that ends in this chunk records the totals
+        if (i < H) {
+            const bool run_end = (i == H - 1) ? !next_cont : (s.sig[i + 1] != my_sig);
+            if (run_end) {
 #pragma unroll
-            for (int p = 0; p < P; ++p) {
-                const unsigned int tot = s.excl[p][i] + (ov[p] ? 1u : 0u) - s.excl[p][start] +
-                                         (from_prev ? s.base[p] : 0u);
-                if (tot) atomicMax(&a.out_count[(size_t)p * a.n_super + my_sig],
-                                   tot > (unsigned long long)a.cap ? (unsigned int)a.cap : tot);
+                for (int p = 0; p < P; ++p) {
+                    const unsigned int tot = s.excl[p][i] + (ov[p] ? 1u : 0u) - s.excl[p][start] +
+                                             (from_prev ? s.base[p] : 0u);
+                    if (tot) a.out_count[(size_t)p * a.n_super + my_sig] =
+                                 tot > (unsigned long long)a.cap ? (unsigned int)a.cap : tot;
+                }
             }
         }
+        if (!has_next) break;
+        cur = nxt;
+        c += G;
     }
 }
 
@@ -631,7 +758,20 @@ __global__ __launch_bounds__(kThreads) void step_kernel(const StepArgs a) {
 
 int chunk_heads(int P) { return kThreads - (P - 1); }
 
+int plan_super_per_thread(int P) { return P == 4 ? 4 : 8; }
+
+int step_grid(int P, int n_cu, int per_cu) {
+    int nb = 0;
+    hipError_t e = hipErrorInvalidValue;
+    if (P == 4) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_kernel<4, 2>, kThreads, 0);
+    if (P == 9) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_kernel<9, 4>, kThreads, 0);
+    if (e != hipSuccess || nb < 1) return 0;
+    // the look-back waits on other workgroups: every workgroup of the grid must be resident
+    return (per_cu > 0 ? (per_cu < nb ? per_cu : nb) : nb) * n_cu;
+}
+
 int launch_step(const StepArgs& a, int grid, void* stream) {
+
     hipStream_t st = (hipStream_t)stream;
     switch (a.P) {
         case 4: hipLaunchKernelGGL((step_kernel<4, 2>), dim3(grid), dim3(kThreads), 0, st, a); break;
@@ -644,8 +784,8 @@ int launch_step(const StepArgs& a, int grid, void* stream) {
 int launch_plan(const PlanArgs& a, void* stream) {
     hipStream_t st = (hipStream_t)stream;
     switch (a.P) {
-        case 4: hipLaunchKernelGGL((plan_kernel<4>), dim3(1), dim3(kPlanThreads), 0, st, a); break;
-        case 9: hipLaunchKernelGGL((plan_kernel<9>), dim3(1), dim3(kPlanThreads), 0, st, a); break;
+        case 4: hipLaunchKernelGGL((plan_kernel<4, 4>), dim3(1), dim3(kPlanThreads), 0, st, a); break;
+        case 9: hipLaunchKernelGGL((plan_kernel<9, 8>), dim3(1), dim3(kPlanThreads), 0, st, a); break;
         default: return (int)hipErrorInvalidValue;
     }
     return (int)hipGetLastError();
