@@ -135,7 +135,6 @@ int launch_planner(quapi_ctx* c, int t) {
     pa.plan = c->d_plan + ((t + 1) & 1);
     pa.plan_prev = c->d_plan + (t & 1);
     pa.n_buckets = c->n_buckets;
-    pa.chunk_heads = quapi_dev::chunk_heads(c->P);
     pa.max_chunks = c->max_chunks;
     pa.P = c->P;
     pa.reduce_t = t;
@@ -296,13 +295,13 @@ int quapi_create(const quapi_params* p, quapi_ctx** out) {
     c->dt = p->dt;
     c->theta = p->theta;
 
-    // buckets: the top D points of the key; D-1 chosen so that there are as many
-    // super-buckets as the planner covers in one pass; a bucket holds every key
-    // of its prefix, or its share of max_groups
-    const long long plan_super = 1024ll * quapi_dev::plan_super_per_thread(M * M);
-    long long max_super = plan_super;   // tuning knob: upper bound on the number of super-buckets
-    if (const char* env = std::getenv("QUAPI_MAX_SUPER"))
-        max_super = std::max(1ll, std::min(plan_super, std::atoll(env)));
+    // buckets: the top D points of the key, D-1 the most points with at most
+    // max_super super-buckets (bounded by what the planner is built for); a
+    // bucket holds every key of its prefix, or its share of max_groups
+    const long long plan_super = quapi_dev::plan_max_buckets() / (M * M);
+    long long max_super = 8192;   // tuning knob: upper bound on the number of super-buckets
+    if (const char* env = std::getenv("QUAPI_MAX_SUPER")) max_super = std::max(1ll, std::atoll(env));
+    max_super = std::min(max_super, plan_super);
     int dm1 = 0;
     while (dm1 + 1 <= L - 1 && ipow(P, dm1 + 1) <= max_super) ++dm1;
     c->D = dm1 + 1;

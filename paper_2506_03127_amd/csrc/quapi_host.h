@@ -66,7 +66,7 @@ struct StepArgs {
     const double* coef;             // this step's coefficients: cre, cim, dre, dim [4][K+1]
     unsigned long long* chain;      // [P * max_chunks] look-back words, one per chunk and pair
     int max_chunks;
-    double* partials;               // [max_chunks * partial_stride(P)]
+    double* partials;               // [partial_stride(P)][max_chunks], component-major
     unsigned int* error;            // (failing step << 4) | code, 0 if none
 };
 
@@ -79,7 +79,6 @@ struct PlanArgs {
     Plan* plan;                     // plan of the step to plan
     const Plan* plan_prev;          // plan of the step just done (for its counters)
     long long n_buckets;
-    int chunk_heads;                // groups per chunk
     int max_chunks;
     int P;
     int reduce_t;                   // step whose partials to reduce, 0: none
@@ -103,7 +102,7 @@ enum : unsigned int { kErrNone = 0, kErrOverflow = 1, kErrSpin = 2 };
 int launch_step(const StepArgs& a, int grid, void* stream);   // returns hipError_t
 int launch_plan(const PlanArgs& a, void* stream);
 int chunk_heads(int P);
-int plan_super_per_thread(int P);   // super-buckets per planner thread (1024 threads)
+int plan_max_buckets();              // bucket count the planner is built for
 int step_grid(int P, int n_cu, int per_cu);   // persistent workgroups that are co-resident
 
 }  // namespace quapi_dev

@@ -100,71 +100,115 @@ __device__ inline unsigned int error_word(const unsigned int* err) {
 }
 
 // ------------------------------------------------------------------ planner
-// Thread i owns super-buckets [i*SPT, (i+1)*SPT), i.e. SPT*P consecutive buckets.
-template <int P, int SPT>
+// Workgroup w < n_regions plans the buckets [w*kRegion, (w+1)*kRegion)
+// (thread i owns kPlanPer consecutive ones) and finds the groups and
+// nonempty buckets before its region by summing the bucket sizes there with
+// coalesced loads; the last workgroup reduces the finished step's per-chunk
+// sums.  All of them run side by side.
+constexpr int kPlanPer = 4;
+constexpr int kRegion = kPlanThreads * kPlanPer;
+
+__device__ inline unsigned long long pack_sizes(unsigned int a0, unsigned int a1, unsigned int a2,
+                                                unsigned int a3) {
+    // (groups << 32) | nonempty buckets
+    const unsigned int nz = (a0 != 0u) + (a1 != 0u) + (a2 != 0u) + (a3 != 0u);
+    return ((unsigned long long)(a0 + a1 + a2 + a3) << 32) | nz;
+}
+
+template <int P>
 __global__ __launch_bounds__(kPlanThreads) void plan_kernel(const PlanArgs a) {
     constexpr int S = partial_stride(P);
-    constexpr int NBT = SPT * P;
+    constexpr unsigned int C = kThreads - (P - 1);
     __shared__ unsigned long long wsum[kPlanWaves];
+    __shared__ unsigned long long wpre[kPlanWaves];
     __shared__ double wred[kPlanWaves][S];
     const int i = threadIdx.x;
     const int wave = i >> 6;
     const unsigned int lane = lane_id();
     const long long NB = a.n_buckets;
-    const long long b_lo = (long long)i * NBT;
-    const bool full = b_lo + NBT <= NB;
+    const int n_regions = (int)((NB + kRegion - 1) / kRegion);
+    const int w = (int)blockIdx.x;
 
-    // ---- bucket sizes of this thread (one batch of independent loads)
-    unsigned int cnt[NBT];
-    if (full) {
-        if constexpr (NBT % 4 == 0) {
-            const uint4* src = reinterpret_cast<const uint4*>(a.counts + b_lo);
+    if (w == n_regions) {
+        // ---- counters and rho(t) of the step just finished, summed in chunk order
+        if (a.reduce_t <= 0) return;
+        const unsigned int err = error_word(a.error);
+        if (err != 0u && (int)(err >> 4) <= a.reduce_t) return;   // that step failed: keep nothing
+        const unsigned int nc = a.plan_prev->n_chunks;
+        double acc[S];
 #pragma unroll
-            for (int k = 0; k < NBT / 4; ++k) {
-                const uint4 v = src[k];
-                cnt[4 * k] = v.x;
-                cnt[4 * k + 1] = v.y;
-                cnt[4 * k + 2] = v.z;
-                cnt[4 * k + 3] = v.w;
-            }
-        } else {
+        for (int k = 0; k < S; ++k) acc[k] = 0.0;
+#pragma unroll 2
+        for (unsigned int c = i; c < nc; c += kPlanThreads)
 #pragma unroll
-            for (int k = 0; k < NBT; ++k) cnt[k] = a.counts[b_lo + k];
+            for (int k = 0; k < S; ++k) acc[k] += a.partials[(size_t)k * a.max_chunks + c];
+#pragma unroll
+        for (int k = 0; k < S; ++k) {
+            double v = acc[k];
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+            if (lane == 0) wred[wave][k] = v;
         }
+        __syncthreads();
+        if (i < S) {
+            double v = 0.0;
+            for (int q = 0; q < kPlanWaves; ++q) v += wred[q][i];
+            wred[0][i] = v;
+        }
+        __syncthreads();
+        if (i == 0) {
+            const unsigned long long ng = a.plan_prev->n_groups;
+#pragma unroll
+            for (int p = 0; p < P; ++p)
+                a.rho_hist[(size_t)a.reduce_t * P + p] = make_double2(wred[0][2 * p], wred[0][2 * p + 1]);
+            StepStatsDev* st = a.stats_hist + a.reduce_t;   // n_stored comes from the last region
+            st->n_groups = ng;
+            st->n_children = ng * (unsigned long long)P;
+            st->n_survivors = (unsigned long long)wred[0][2 * P + 1];
+            st->dropped_abs = wred[0][2 * P];
+            st->pad = 0.0;
+        }
+        return;
+    }
+
+    // ---- this thread's bucket sizes and, in the same batch, those before the region
+    const long long b_lo = (long long)w * kRegion + (long long)i * kPlanPer;
+    unsigned int cnt[kPlanPer];
+    if (b_lo + kPlanPer <= NB) {
+        const uint4 v = *reinterpret_cast<const uint4*>(a.counts + b_lo);
+        cnt[0] = v.x; cnt[1] = v.y; cnt[2] = v.z; cnt[3] = v.w;
     } else {
 #pragma unroll
-        for (int k = 0; k < NBT; ++k) cnt[k] = b_lo + k < NB ? a.counts[b_lo + k] : 0u;
+        for (int k = 0; k < kPlanPer; ++k) cnt[k] = b_lo + k < NB ? a.counts[b_lo + k] : 0u;
+    }
+    unsigned long long before = 0;                     // this thread's share of the earlier regions
+#pragma unroll 8
+    for (int r = 0; r < w; ++r) {
+        const uint4 v = *reinterpret_cast<const uint4*>(a.counts + (long long)r * kRegion + (long long)i * kPlanPer);
+        before += pack_sizes(v.x, v.y, v.z, v.w);
     }
 
-    // ---- exclusive block scan of (groups, nonempty buckets), packed hi/lo
-    unsigned int tot = 0, nz = 0;
-#pragma unroll
-    for (int k = 0; k < NBT; ++k) {
-        tot += cnt[k];
-        nz += cnt[k] != 0u ? 1u : 0u;
-    }
-    const unsigned long long mine = ((unsigned long long)tot << 32) | nz;
-    unsigned long long incl = mine;
+    // ---- block sums: exclusive scan of this region, plus the earlier regions' total
+    const unsigned long long mine = pack_sizes(cnt[0], cnt[1], cnt[2], cnt[3]);
+    unsigned long long incl = mine, bsum = before;
     for (int off = 1; off < 64; off <<= 1) {
         const unsigned long long v = __shfl_up(incl, off, 64);
         if ((int)lane >= off) incl += v;
     }
+    for (int off = 32; off > 0; off >>= 1) bsum += __shfl_xor(bsum, off, 64);
     if (lane == 63) wsum[wave] = incl;
+    if (lane == 0) wpre[wave] = bsum;
     __syncthreads();
-    unsigned long long base = incl - mine, total = 0;
-    for (int w = 0; w < kPlanWaves; ++w) {
-        if (w < wave) base += wsum[w];
-        total += wsum[w];
+    unsigned long long base = incl - mine, region = 0;
+    for (int q = 0; q < kPlanWaves; ++q) {
+        if (q < wave) base += wsum[q];
+        base += wpre[q];
+        region += wsum[q] + wpre[q];
     }
-    const unsigned int N = (unsigned int)(total >> 32);
-    const unsigned int n_nz = (unsigned int)total;
-    const unsigned int C = (unsigned int)a.chunk_heads;
-    const unsigned int n_chunks = (N + C - 1) / C;
 
     // ---- nonempty buckets; each chunk's first group lies in the one of rank desc[c]
     unsigned int run = (unsigned int)(base >> 32), rank = (unsigned int)base;
 #pragma unroll
-    for (int k = 0; k < NBT; ++k) {
+    for (int k = 0; k < kPlanPer; ++k) {
         const unsigned int n = cnt[k];
         if (n == 0u) continue;
         a.nz_bucket[rank] = (unsigned int)(b_lo + k);
@@ -176,64 +220,21 @@ __global__ __launch_bounds__(kPlanThreads) void plan_kernel(const PlanArgs a) {
     }
 
     // ---- zero the next step's bucket sizes
-    if (full) {
-        if constexpr (NBT % 4 == 0) {
-            uint4* dst = reinterpret_cast<uint4*>(a.counts_next + b_lo);
-#pragma unroll
-            for (int k = 0; k < NBT / 4; ++k) dst[k] = make_uint4(0u, 0u, 0u, 0u);
-        } else {
-#pragma unroll
-            for (int k = 0; k < NBT; ++k) a.counts_next[b_lo + k] = 0u;
-        }
+    if (b_lo + kPlanPer <= NB) {
+        *reinterpret_cast<uint4*>(a.counts_next + b_lo) = make_uint4(0u, 0u, 0u, 0u);
     } else {
         for (long long b = b_lo; b < NB; ++b) a.counts_next[b] = 0u;
     }
 
-    // ---- counters and rho(t) of the step just finished, summed in chunk order
-    const unsigned int err = error_word(a.error);
-    const bool reduce = a.reduce_t > 0 && (err == 0u || (int)(err >> 4) > a.reduce_t);
-    if (reduce) {
-        const unsigned int nc = a.plan_prev->n_chunks;
-        double acc[S];
-#pragma unroll
-        for (int k = 0; k < S; ++k) acc[k] = 0.0;
-#pragma unroll 4
-        for (unsigned int c = i; c < nc; c += kPlanThreads)
-#pragma unroll
-            for (int k = 0; k < S; ++k) acc[k] += a.partials[(size_t)c * S + k];
-#pragma unroll
-        for (int k = 0; k < S; ++k) {
-            double v = acc[k];
-            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-            if (lane == 0) wred[wave][k] = v;
-        }
-    }
-    __syncthreads();
-    if (reduce && i == 0) {
-        double sum[S];
-#pragma unroll
-        for (int k = 0; k < S; ++k) {
-            sum[k] = 0.0;
-            for (int w = 0; w < kPlanWaves; ++w) sum[k] += wred[w][k];
-        }
-#pragma unroll
-        for (int p = 0; p < P; ++p)
-            a.rho_hist[(size_t)a.reduce_t * P + p] = make_double2(sum[2 * p], sum[2 * p + 1]);
-        StepStatsDev st;
-        st.n_groups = a.plan_prev->n_groups;
-        st.n_children = st.n_groups * (unsigned long long)P;
-        st.n_survivors = (unsigned long long)sum[2 * P + 1];
-        st.n_stored = N;
-        st.dropped_abs = sum[2 * P];
-        st.pad = 0.0;
-        a.stats_hist[a.reduce_t] = st;
-    }
-    if (i == 0) {
+    // ---- the last region knows the totals
+    if (w == n_regions - 1 && i == 0) {
+        const unsigned int N = (unsigned int)(region >> 32);
+        if (a.reduce_t > 0) a.stats_hist[a.reduce_t].n_stored = N;
         Plan pl;
         pl.n_groups = N;
-        pl.n_chunks = n_chunks;
+        pl.n_chunks = (N + C - 1) / C;
         pl.pad = 0u;
-        pl.n_nonempty = n_nz;
+        pl.n_nonempty = (unsigned int)region;
         *a.plan = pl;
     }
 }
@@ -675,7 +676,7 @@ __global__ __launch_bounds__(kThreads) void step_kernel(const StepArgs a) {
             } else {
                 for (int w = 0; w < kWaves; ++w) v += s.wsurv[w];
             }
-            a.partials[(size_t)c * S + i] = v;
+            a.partials[(size_t)i * a.max_chunks + c] = v;
         }
         __syncthreads();
 
@@ -758,7 +759,7 @@ __global__ __launch_bounds__(kThreads) void step_kernel(const StepArgs a) {
 
 int chunk_heads(int P) { return kThreads - (P - 1); }
 
-int plan_super_per_thread(int P) { return P == 4 ? 4 : 8; }
+int plan_max_buckets() { return 64 * kRegion; }
 
 int step_grid(int P, int n_cu, int per_cu) {
     int nb = 0;
@@ -783,9 +784,10 @@ int launch_step(const StepArgs& a, int grid, void* stream) {
 
 int launch_plan(const PlanArgs& a, void* stream) {
     hipStream_t st = (hipStream_t)stream;
+    const int grid = (int)((a.n_buckets + kRegion - 1) / kRegion) + 1;
     switch (a.P) {
-        case 4: hipLaunchKernelGGL((plan_kernel<4, 4>), dim3(1), dim3(kPlanThreads), 0, st, a); break;
-        case 9: hipLaunchKernelGGL((plan_kernel<9, 8>), dim3(1), dim3(kPlanThreads), 0, st, a); break;
+        case 4: hipLaunchKernelGGL((plan_kernel<4>), dim3(grid), dim3(kPlanThreads), 0, st, a); break;
+        case 9: hipLaunchKernelGGL((plan_kernel<9>), dim3(grid), dim3(kPlanThreads), 0, st, a); break;
         default: return (int)hipErrorInvalidValue;
     }
     return (int)hipGetLastError();
