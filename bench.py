@@ -3,20 +3,25 @@
 One benchmark step = one whole propagation of the structured-bath workload
 (two-level system, Ohmic + underdamped Brownian-oscillator bath, dk_max = 24,
 mask keeping lags 0..11, theta = 1e-8, 1000 time steps, FP64, pre-merging):
-reset to t = 0, 1000 fused step kernels, read back rho(t) for all t.  The
-bath coefficients and propagator tables are built once before timing (they
-stay resident in HBM with the path store).
+reset to t = 0, 1000 time steps (step kernel + planner each), read back rho(t)
+for all t.  The bath coefficients and propagator tables are built once before
+timing and stay resident in HBM with the path store.
 
 Prints one JSON line:  value = path-steps/s over the timed propagations
 (path-step = one child, i.e. one group extended by one forward/backward pair
-in one time step), plus a roofline object for the step kernel (algorithmic
-bytes = 32 B per group read + 32 B per group written, over the kernel's mean
-launch time measured with HIP events on its stream) and the CPU oracle timed
-on a bounded sample of the same workload.
+in one time step), a roofline object for the step kernel (algorithmic bytes =
+32 B per group read + 32 B per group written, over the kernel's mean launch
+time from HIP events the library records on its stream around each launch),
+and the CPU oracle timed on a bounded sample of the same workload.
+
+--copy-mib N adds one plain device-to-device copy of N MiB after the timed
+work: a kernel of known traffic against which the PMC byte counters of a
+profiled run are scaled.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import platform
@@ -31,6 +36,27 @@ sys.path.insert(0, ROOT)
 METRIC = "path-steps/sec + HBM roofline fraction at dk_max=24, theta=1e-8; time per rho(t)"
 HBM_PEAK_GBS = 8000.0
 RECORD_BYTES = 32
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_traffic.json")
+KERNEL_SOURCES = ["paper_2506_03127_amd/csrc/quapi_step.hip", "paper_2506_03127_amd/csrc/quapi_host.h"]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per step-kernel launch from the committed PMC measurement, or None when
+    the kernel sources changed since the counters were taken."""
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
 
 
 def cpu_model() -> str:
@@ -68,6 +94,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=22,
                     help="time steps of the oracle sample for the CPU baseline (0: skip)")
     ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="one plain device copy of this size after the timed work (PMC calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the path is built "
@@ -141,23 +169,31 @@ def main():
     }
 
     if not args.no_roofline:
-        # per-launch durations of the step kernel: events around each launch on its stream
+        # per-launch durations of the step kernel: HIP events recorded by the library on its
+        # stream right before and after each step-kernel launch
         prop.reset()
-        evs = [torch.cuda.Event(enable_timing=True) for _ in range(n_t + 1)]
-        evs[0].record(stream)
-        for k in range(n_t):
-            quapi.quapi_step(prop.ctx, 1)
-            evs[k + 1].record(stream)
-        torch.cuda.synchronize()
-        dur_ms = np.array([evs[k].elapsed_time(evs[k + 1]) for k in range(n_t)])
-        mean_s = float(dur_ms.mean()) * 1e-3
+        quapi.quapi_profile_begin(prop.ctx, n_t)
+        quapi.quapi_step(prop.ctx, n_t)
+        step_ms, plan_ms = quapi.quapi_profile_end(prop.ctx, n_t)
+        mean_s = float(step_ms.mean()) * 1e-3
         per_launch_bytes = float(alg_bytes.mean())
         achieved = per_launch_bytes / mean_s / 1e9
         out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                           "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                            "kernel": "step_kernel<4,2>", "launches": n_t,
                            "mean_launch_us": mean_s * 1e6,
+                           "planner_mean_launch_us": float(plan_ms.mean()) * 1e3,
                            "alg_bytes_per_launch": per_launch_bytes}
+
+    if args.copy_mib > 0:
+        import torch
+        nb = args.copy_mib << 20
+        src = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        with torch.cuda.stream(stream):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = nb
 
     if args.cpu_steps > 0:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)

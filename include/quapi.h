@@ -105,7 +105,7 @@ typedef struct {
 /* Create a context and its initial state t = 0 (one path per nonzero
  * element of rho0, weighted by the initial point's self term).
  * Errors: EINVAL (bad argument), EUNSUPPORTED (a mask whose merge positions
- * are not 0..L-1 with L >= 2, or M > 4), ENOMEM, EDEVICE.  *out is NULL on error. */
+ * are not 0..L-1 with L >= 2, or M > 3), ENOMEM, EDEVICE.  *out is NULL on error. */
 int quapi_create(const quapi_params* p, quapi_ctx** out);
 
 /* Enqueue n_steps time steps on the context's stream; returns without waiting.
@@ -145,6 +145,19 @@ int quapi_info(quapi_ctx* c, quapi_info_t* out);
 void* quapi_stream(quapi_ctx* c);
 
 const char* quapi_strerror(int code);
+
+/* Launch timing, for measurement.  quapi_profile_begin clears the record and
+ * makes the next quapi_step calls record HIP events on the context's stream
+ * around each of the next max_launches steps: one before the step kernel, one
+ * between it and the planner that follows it, one after the planner.
+ * Errors: EINVAL (max_launches < 1), ENOMEM, EDEVICE. */
+int quapi_profile_begin(quapi_ctx* c, int max_launches);
+
+/* Durations in milliseconds of the recorded steps, oldest first: step_ms[k] of
+ * the step kernel, plan_ms[k] of the planner after it (either array may be NULL).
+ * Writes min(cap, n) entries, *n_out = n; synchronises and stops recording.
+ * Errors: EINVAL, ESTATE (no recording began), EDEVICE. */
+int quapi_profile_end(quapi_ctx* c, int cap, double* step_ms, double* plan_ms, int* n_out);
 
 /* Free the context and its device memory (synchronises first).  NULL is a no-op. */
 void quapi_destroy(quapi_ctx* c);

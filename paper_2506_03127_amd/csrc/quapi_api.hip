@@ -57,6 +57,10 @@ struct quapi_ctx {
     int err = QUAPI_OK;          // sticky error of a failed step
     size_t device_bytes = 0;
     std::vector<void*> allocations;
+    // launch timing: three events per recorded step
+    bool prof_on = false;
+    int prof_cap = 0, prof_n = 0;
+    std::vector<hipEvent_t> prof_ev;
 };
 
 namespace {
@@ -478,10 +482,13 @@ int quapi_step(quapi_ctx* c, int n_steps) {
         a.t = t;
         a.epoch = ++c->epoch;
         a.coef = c->d_coef + (size_t)(std::min(t, c->K + 1) - 1) * 4 * n;
+        hipEvent_t* ev = (c->prof_on && c->prof_n < c->prof_cap) ? &c->prof_ev[3 * (size_t)c->prof_n++] : nullptr;
+        if (ev && hipEventRecord(ev[0], c->stream) != hipSuccess) ev = nullptr;
         if (quapi_dev::launch_step(a, c->grid, c->stream) != (int)hipSuccess) {
             c->err = QUAPI_EDEVICE;
             return c->err;
         }
+        if (ev) (void)hipEventRecord(ev[1], c->stream);
         c->t = t;
         c->cur = 1 - c->cur;
         // reduce step t and plan step t+1
@@ -489,6 +496,7 @@ int quapi_step(quapi_ctx* c, int n_steps) {
             c->err = QUAPI_EDEVICE;
             return c->err;
         }
+        if (ev) (void)hipEventRecord(ev[2], c->stream);
     }
     return QUAPI_OK;
 }
@@ -600,9 +608,47 @@ int quapi_info(quapi_ctx* c, quapi_info_t* out) {
 
 void* quapi_stream(quapi_ctx* c) { return c ? (void*)c->stream : nullptr; }
 
+int quapi_profile_begin(quapi_ctx* c, int max_launches) {
+    if (!c || max_launches < 1) return QUAPI_EINVAL;
+    (void)hipStreamSynchronize(c->stream);
+    const size_t need = 3 * (size_t)max_launches;
+    while (c->prof_ev.size() < need) {
+        hipEvent_t e = nullptr;
+        const hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess) {
+            (void)hipGetLastError();
+            return hip_to_code(r);
+        }
+        c->prof_ev.push_back(e);
+    }
+    c->prof_cap = max_launches;
+    c->prof_n = 0;
+    c->prof_on = true;
+    return QUAPI_OK;
+}
+
+int quapi_profile_end(quapi_ctx* c, int cap, double* step_ms, double* plan_ms, int* n_out) {
+    if (!c || !n_out || cap < 0) return QUAPI_EINVAL;
+    if (!c->prof_on) return QUAPI_ESTATE;
+    c->prof_on = false;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return QUAPI_EDEVICE;
+    *n_out = c->prof_n;
+    for (int k = 0; k < c->prof_n && k < cap; ++k) {
+        float a = 0.f, b = 0.f;
+        if (hipEventElapsedTime(&a, c->prof_ev[3 * k], c->prof_ev[3 * k + 1]) != hipSuccess ||
+            hipEventElapsedTime(&b, c->prof_ev[3 * k + 1], c->prof_ev[3 * k + 2]) != hipSuccess)
+            return QUAPI_EDEVICE;
+        if (step_ms) step_ms[k] = a;
+        if (plan_ms) plan_ms[k] = b;
+    }
+    return QUAPI_OK;
+}
+
 void quapi_destroy(quapi_ctx* c) {
     if (!c) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (hipEvent_t e : c->prof_ev) (void)hipEventDestroy(e);
+    c->prof_ev.clear();
     for (void* p : c->allocations) (void)hipFree(p);
     c->allocations.clear();
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);

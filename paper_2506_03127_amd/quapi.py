@@ -92,6 +92,8 @@ def lib() -> ctypes.CDLL:
         L.quapi_destroy.argtypes = [vp]
         L.quapi_eta.argtypes = [ctypes.POINTER(quapi_bath), cd, cd, ci, vp]
         L.quapi_propagator.argtypes = [ci, vp, cd, vp]
+        L.quapi_profile_begin.argtypes = [vp, ci]
+        L.quapi_profile_end.argtypes = [vp, ci, vp, vp, ctypes.POINTER(ci)]
         _lib = L
     return _lib
 
@@ -206,6 +208,21 @@ def quapi_stream(ctx) -> int:
 def quapi_destroy(ctx):
     if ctx:
         lib().quapi_destroy(ctx)
+
+
+def quapi_profile_begin(ctx, max_launches: int):
+    _check(lib().quapi_profile_begin(ctx, int(max_launches)), "quapi_profile_begin")
+
+
+def quapi_profile_end(ctx, cap: int):
+    """(step_ms, plan_ms): per recorded step, the step kernel's and the planner's duration."""
+    step = np.zeros(max(int(cap), 1))
+    plan = np.zeros(max(int(cap), 1))
+    n = ctypes.c_int(0)
+    _check(lib().quapi_profile_end(ctx, int(cap), step.ctypes.data, plan.ctypes.data, ctypes.byref(n)),
+           "quapi_profile_end")
+    k = min(n.value, int(cap))
+    return step[:k], plan[:k]
 
 
 def quapi_eta(ohmic_alpha, ohmic_wc, peaks, beta, dt, dk_max) -> np.ndarray:

@@ -251,3 +251,20 @@ def test_structured_bath_full_run(Q, eta_cache):
     tr = np.trace(r, axis1=1, axis2=2)
     assert np.abs(tr.imag).max() < 1e-12
     assert tr.real.max() < 1.0 + 1e-12 and tr.real[-1] > 0.9
+
+
+def test_launch_timing_record(Q, eta_cache):
+    """The launch-timing entry points record one positive duration per step kernel and
+    planner launch, and recording ends at the requested count."""
+    wl = W.structured_bath(K=10)
+    eta = eta_cache(wl, 10)
+    g = Q.Propagator(wl.H, wl.q, wl.dt, 10, eta, wl.rho0, mask=(0, 1, 2, 3, 4), theta=1e-7)
+    Q.quapi_profile_begin(g.ctx, 5)
+    g.step(8)
+    step_ms, plan_ms = Q.quapi_profile_end(g.ctx, 16)
+    assert len(step_ms) == 5 and len(plan_ms) == 5
+    assert (step_ms > 0).all() and (plan_ms > 0).all() and step_ms.max() < 100.0
+    with pytest.raises(Q.QuapiError) as e:
+        Q.quapi_profile_end(g.ctx, 16)
+    assert e.value.code == Q.QUAPI_ESTATE
+    assert g.t == 8
