@@ -49,10 +49,10 @@ namespace {
 constexpr int kWaves = kThreads / 64;
 constexpr int kPlanThreads = 1024;
 constexpr int kPlanWaves = kPlanThreads / 64;
-constexpr int kWin = kThreads + 2;    // nonempty buckets cached per chunk (covers the group before it too)
-constexpr int kTabPts = 3;            // points per subset-sum table (two-level systems)
-constexpr int kTabEntries = 64;       // 4^3
-constexpr int kMaxTabs = 10;
+constexpr int kWin = kThreads + 3;    // nonempty buckets cached per chunk (covers the groups around it too)
+constexpr int kTabPts = 2;            // points per subset-sum table (two-level systems)
+constexpr int kTabEntries = 16;       // 4^2
+constexpr int kMaxTabs = 16;
 constexpr unsigned int kSpinLimit = 1u << 22;
 constexpr unsigned long long kAgg = 1ull << 32;   // look-back word: own totals only
 constexpr unsigned long long kInc = 2ull << 32;   // look-back word: inclusive totals
@@ -80,6 +80,30 @@ __device__ inline double recip(double x) {
     r = __builtin_fma(r, e, r);
     e = __builtin_fma(-x, r, 1.0);
     return __builtin_fma(r, e, r);
+}
+
+// Sum over the 64 lanes of a wave, in a fixed order, returned to every lane:
+// butterflies inside each row of 16 lanes by DPP (quad_perm xor 1, xor 2,
+// half-row mirror, row mirror), then the four row sums read from lanes 0, 16,
+// 32, 48.
+template <int CTRL>
+__device__ inline double dpp_pair(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ inline double readlane_d(double v, int l) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                            __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+
+__device__ inline double wave_sum(double v) {
+    v += dpp_pair<0xB1>(v);      // quad_perm [1,0,3,2]
+    v += dpp_pair<0x4E>(v);      // quad_perm [2,3,0,1]
+    v += dpp_pair<0x141>(v);     // row_half_mirror
+    v += dpp_pair<0x140>(v);     // row_mirror
+    return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
 }
 
 __device__ inline unsigned long long ld_relaxed(const unsigned long long* p) {
@@ -247,35 +271,34 @@ struct Lds {
     double cre[kMaxK + 1], cim[kMaxK + 1], dre[kMaxK + 1], dim[kMaxK + 1];   // this step's coefficients
     double tab[P == 4 ? kMaxTabs : 1][P == 4 ? kTabEntries : 1][4];         // subset sums (two levels)
     double2 cw[P][kThreads];               // child weights
-    unsigned long long key[kThreads];
-    unsigned long long ctail[kThreads];
+    unsigned long long ctail[kThreads];    // child history tails
     unsigned int surv[kThreads];           // bit p: child p survives
-    unsigned int sig[kThreads];            // super-bucket of each loaded parent
-    unsigned int excl[P][kThreads + 1];    // block-exclusive prefix of the output flags
     unsigned int win_b[kWin];              // nonempty buckets of the next chunk ...
     unsigned int win_p[kWin];              // ... and their first global group index
-    unsigned char flags[kThreads];         // bit 0 valid, bit 1 segment head
-    unsigned int wcount[kWaves][P];
+    unsigned long long hmask[kWaves];      // segment heads, one word per wave
+    unsigned long long vmask[kWaves];      // loaded parents
+    unsigned long long omask[P][kWaves];   // merged groups written, per pair
+    unsigned int ocount[P][kWaves];        // their popcounts
     int wstart[kWaves];                    // last super-bucket run start in each wave
     unsigned int base[P];                  // offsets of the first run when it continues
     double2 wrho[kWaves][P];
     double wdrop[kWaves];
     double wsurv[kWaves];
-    unsigned long long prev_key;           // key of the group just before the chunk
-    unsigned int prev_sig;                 // its super-bucket
+    unsigned int sig0, prev_sig;           // super-bucket of the first parent and of the group before
     double e0, f0;
 };
 
-// One thread's parent of a chunk, and (thread 0) the group before the chunk.
+// One thread's parent of a chunk.  Lane 0 of each wave also holds the group
+// before it (pkey, psig) and lane 63 the super-bucket of the group after it.
 struct Parent {
     unsigned long long key, tail, pkey;
     double2 w;
-    unsigned int sig, psig;               // 0xffffffff: none
+    unsigned int sig, psig, nsig;         // 0xffffffff: none
 };
 
 // Window of nonempty buckets around a chunk: entries [rb, rb + kWin) of the
 // list, rb one before the bucket of the chunk's first group.  Thread i holds
-// entries i and kThreads + i (i < 2) until they are written to the LDS.
+// entries i and kThreads + i (i < kWin - kThreads) until they are written to the LDS.
 struct WinRegs {
     unsigned int b0, p0, b1, p1;
 };
@@ -292,7 +315,7 @@ __device__ inline WinRegs load_window(const StepArgs& a, unsigned int first_rank
     return w;
 }
 
-// largest k with win_p[k] <= g (win_p[0] <= g < win_p[kWin-1] holds for the chunk's groups)
+// largest k with win_p[k] <= g; the window holds groups g0-1 .. g0+kThreads of its chunk
 template <int P>
 __device__ inline int window_search(const Lds<P>& s, unsigned int g) {
     int lo = 0, hi = kWin - 1;
@@ -305,7 +328,7 @@ __device__ inline int window_search(const Lds<P>& s, unsigned int g) {
 
 template <int P, int C>
 __device__ inline Parent fetch_parent(const StepArgs& a, const Lds<P>& s, unsigned int c, unsigned int N,
-                                      long long nrec, int i) {
+                                      long long nrec, int i, unsigned int lane) {
     Parent r;
     r.key = ~0ull;
     r.tail = 0ull;
@@ -313,9 +336,9 @@ __device__ inline Parent fetch_parent(const StepArgs& a, const Lds<P>& s, unsign
     r.w = make_double2(0.0, 0.0);
     r.sig = 0xffffffffu;
     r.psig = 0xffffffffu;
-    const unsigned int g0 = c * (unsigned int)C;
-    const unsigned int g = g0 + (unsigned int)i;
-    if (g < N && i < kThreads) {
+    r.nsig = 0xffffffffu;
+    const unsigned int g = c * (unsigned int)C + (unsigned int)i;
+    if (g < N) {
         const int k = window_search(s, g);
         const unsigned int b = s.win_b[k];
         const long long o = (long long)b * a.cap + (long long)(g - s.win_p[k]);
@@ -327,14 +350,20 @@ __device__ inline Parent fetch_parent(const StepArgs& a, const Lds<P>& s, unsign
         } else {
             raise_error(a.error, a.t, kErrOverflow);
         }
-    }
-    if (i == 0 && g0 > 0u) {
-        const int k = window_search(s, g0 - 1u);
-        const unsigned int b = s.win_b[k];
-        const long long o = (long long)b * a.cap + (long long)(g0 - 1u - s.win_p[k]);
-        if (o < nrec) {
-            r.pkey = a.in.key[o];
-            r.psig = b / P;
+        // lane 0: the group before; lane 63: the group after (one search for both)
+        if ((lane == 0u && g > 0u) || (lane == 63u && g + 1u < N)) {
+            const unsigned int gn = lane == 0u ? g - 1u : g + 1u;
+            const int kn = window_search(s, gn);
+            const unsigned int bn = s.win_b[kn];
+            if (lane == 0u) {
+                const long long op = (long long)bn * a.cap + (long long)(gn - s.win_p[kn]);
+                if (op < nrec) {
+                    r.pkey = a.in.key[op];
+                    r.psig = bn / P;
+                }
+            } else {
+                r.nsig = bn / P;
+            }
         }
     }
     return r;
@@ -350,8 +379,22 @@ __device__ inline void store_window(Lds<P>& s, const WinRegs& w, int i) {
     }
 }
 
+// number of merged groups of pair p before position j of the chunk (0 <= j <= kThreads)
+template <int P>
+__device__ inline unsigned int excl_at(const Lds<P>& s, int p, int j) {
+    const int wj = j >> 6;
+    unsigned int e = 0u;
+    for (int w = 0; w < wj && w < kWaves; ++w) e += s.ocount[p][w];
+    if (wj < kWaves) e += (unsigned int)__popcll(s.omask[p][wj] & ((1ull << (j & 63)) - 1ull));
+    return e;
+}
+
+__device__ inline unsigned long long shfl_up1_u64(unsigned long long v) {
+    return (unsigned long long)__shfl_up((long long)v, 1, 64);
+}
+
 template <int P, int BP>
-__global__ __launch_bounds__(kThreads) void step_kernel(const StepArgs a) {
+__global__ __launch_bounds__(kThreads, P == 4 ? 4 : 1) void step_kernel(const StepArgs a) {
     constexpr int C = kThreads - (P - 1);              // segment heads per chunk
     constexpr int S = partial_stride(P);
     constexpr unsigned long long DM = (1ull << BP) - 1;
@@ -394,7 +437,7 @@ __global__ __launch_bounds__(kThreads) void step_kernel(const StepArgs a) {
     const bool use_tabs = (P == 4) && (nk + nt <= kMaxTabs);
     store_window(s, wr, i);
     __syncthreads();
-    Parent cur = fetch_parent<P, C>(a, s, c, N, nrec, i);
+    Parent cur = fetch_parent<P, C>(a, s, c, N, nrec, i, lane);
     if constexpr (P == 4) {
         if (use_tabs) {
             // tab[q][v] = sum over the points of table q of coefficient(lag) * (ds, ss)(point)
@@ -435,6 +478,7 @@ __global__ __launch_bounds__(kThreads) void step_kernel(const StepArgs a) {
     const int top_shift = BP * (L - 1);
     const unsigned long long etag = (unsigned long long)(a.epoch & 0x3fffffffu);
     const unsigned long long ep = etag << 34;
+    const unsigned long long lane_le = (lane == 63u) ? ~0ull : ((2ull << lane) - 1ull);   // lanes 0..lane
 
     for (;;) {
         // ---- fetch the next chunk's parents now; they arrive while this chunk computes
@@ -444,40 +488,73 @@ __global__ __launch_bounds__(kThreads) void step_kernel(const StepArgs a) {
         if (has_next) {
             store_window(s, wn, i);
             __syncthreads();
-            nxt = fetch_parent<P, C>(a, s, c + G, N, nrec, i);
+            nxt = fetch_parent<P, C>(a, s, c + G, N, nrec, i, lane);
             if (c + 2 * G < n_chunks) wn = load_window(a, d_after, n_nz, N, i);
             d_after = (c + 3 * G < n_chunks) ? a.desc[c + 3 * G] : 0u;
         }
 
-        // ---- this chunk: groups [g0, g0 + nsz) loaded, segment heads [g0, g0 + H) owned
+        // ---- this chunk: groups [g0, g0 + nsz) loaded, segment heads [g0, g0 + H) owned;
+        //      for all but the last chunk H = C and positions >= H lie in the last wave
         const unsigned int g0 = c * (unsigned int)C;
-        const unsigned int nsz = min((unsigned int)kThreads, N - g0);
         const int H = (int)min((unsigned int)C, N - g0);
         const bool valid = cur.sig != 0xffffffffu;
         const unsigned long long key = cur.key, tail = cur.tail;
         const double2 W = cur.w;
         const unsigned int my_sig = cur.sig;
-        s.key[i] = key;
-        s.sig[i] = my_sig;
+        // neighbours: inside the wave by shuffles, across waves from the fetch
+        const unsigned long long up_key = shfl_up1_u64(key);
+        const unsigned int up_sig = (unsigned int)__shfl_up((int)my_sig, 1, 64);
+        const unsigned int dn_sig = (unsigned int)__shfl_down((int)my_sig, 1, 64);
+        const unsigned long long pk = lane == 0u ? cur.pkey : up_key;
+        const unsigned int psg = lane == 0u ? cur.psig : up_sig;
+        const unsigned int nsg = lane == 63u ? cur.nsig : dn_sig;
+        const bool head = valid && (g0 + i == 0u || (key >> BP) != (pk >> BP));
+        const bool rstart = valid && (i == 0 || my_sig != psg);
+        const unsigned long long hm = __ballot(head), vm = __ballot(valid), rsm = __ballot(rstart);
+        if (lane == 0u) {
+            s.hmask[wave] = hm;
+            s.vmask[wave] = vm;
+            s.wstart[wave] = rsm ? wave * 64 + 63 - __builtin_clzll(rsm) : -1;
+        }
         if (i == 0) {
-            s.prev_key = cur.pkey;
+            s.sig0 = my_sig;
             s.prev_sig = cur.psig;
         }
         __syncthreads();
-        const unsigned long long pk = i > 0 ? s.key[i - 1] : s.prev_key;
-        const bool head = valid && (g0 + i == 0u || (key >> BP) != (pk >> BP));
-        s.flags[i] = (unsigned char)((valid ? 1 : 0) | (head ? 2 : 0));
-        __syncthreads();
+
         // a parent belongs to this chunk when its segment head does
         bool owned = false;
         if (valid) {
             if (i < H) {
-                for (int k = i; k >= 0 && k > i - P; --k)
-                    if (s.flags[k] & 2) { owned = true; break; }
+                const int lo = (int)lane - (P - 1);
+                const unsigned long long span = lo >= 0 ? (lane_le & ~((1ull << lo) - 1ull)) : lane_le;
+                owned = (hm & span) != 0ull;
+                if (!owned && lo < 0 && wave > 0) owned = (s.hmask[wave - 1] >> (64 + lo)) != 0ull;
             } else {
-                owned = true;
-                for (int k = H; k <= i; ++k)
-                    if (s.flags[k] & 2) { owned = false; break; }
+                const int hl = H - wave * 64;              // H lies in this wave (see above)
+                owned = (hm & lane_le & ~((1ull << hl) - 1ull)) == 0ull;
+            }
+        }
+        // segment length of a head: up to the next head or the end of the loaded parents
+        const bool is_head = (i < H) && head;
+        int len = 0;
+        if (is_head) {
+            const unsigned long long stop_lo = hm | ~vm;
+            const unsigned long long stop_hi = wave + 1 < kWaves ? (s.hmask[wave + 1] | ~s.vmask[wave + 1]) : ~0ull;
+            const unsigned long long after = lane == 63u ? stop_hi : ((stop_lo >> (lane + 1)) | (stop_hi << (63 - lane)));
+            len = 1 + (after ? __builtin_ctzll(after) : 64);
+            if (len > P) len = P;
+        }
+        // start of this parent's super-bucket run inside the chunk
+        int start;
+        {
+            const unsigned long long m = rsm & lane_le;
+            if (m) {
+                start = wave * 64 + 63 - __builtin_clzll(m);
+            } else {
+                start = 0;
+                for (int w = wave - 1; w >= 0; --w)
+                    if (s.wstart[w] >= 0) { start = s.wstart[w]; break; }
             }
         }
 
@@ -492,16 +569,16 @@ __global__ __launch_bounds__(kThreads) void step_kernel(const StepArgs a) {
             double A = 0.0, B = 0.0, Ac = 0.0, Bc = 0.0;
             if (use_tabs) {
                 for (int q = 0; q < nk; ++q) {
-                    const int st = kTabPts * q, len = min(kTabPts, L - st);
-                    const int v = (int)((key >> (BP * (L - st - len))) & ((1ull << (BP * len)) - 1));
+                    const int st = kTabPts * q, ln = min(kTabPts, L - st);
+                    const int v = (int)((key >> (BP * (L - st - ln))) & ((1ull << (BP * ln)) - 1));
                     A += s.tab[q][v][0];
                     B += s.tab[q][v][1];
                     Ac += s.tab[q][v][2];
                     Bc += s.tab[q][v][3];
                 }
                 for (int q = nk; q < nk + nt; ++q) {
-                    const int st = L + kTabPts * (q - nk), len = min(kTabPts, K - st);
-                    const int v = (int)((tail >> (BP * (st - L))) & ((1ull << (BP * len)) - 1));
+                    const int st = L + kTabPts * (q - nk), ln = min(kTabPts, K - st);
+                    const int v = (int)((tail >> (BP * (st - L))) & ((1ull << (BP * ln)) - 1));
                     A += s.tab[q][v][0];
                     B += s.tab[q][v][1];
                     Ac += s.tab[q][v][2];
@@ -586,20 +663,12 @@ __global__ __launch_bounds__(kThreads) void step_kernel(const StepArgs a) {
         // ---- partial sums of rho, dropped weight and survivor count
 #pragma unroll
         for (int p = 0; p < P; ++p) {
-            double r = rho_re[p], m = rho_im[p];
-            for (int off = 32; off > 0; off >>= 1) {
-                r += __shfl_xor(r, off, 64);
-                m += __shfl_xor(m, off, 64);
-            }
-            if (lane == 0) s.wrho[wave][p] = make_double2(r, m);
+            const double r = wave_sum(rho_re[p]), m = wave_sum(rho_im[p]);
+            if (lane == 0u) s.wrho[wave][p] = make_double2(r, m);
         }
         {
-            double dsum = dropped, ns = (double)n_surv;
-            for (int off = 32; off > 0; off >>= 1) {
-                dsum += __shfl_xor(dsum, off, 64);
-                ns += __shfl_xor(ns, off, 64);
-            }
-            if (lane == 0) { s.wdrop[wave] = dsum; s.wsurv[wave] = ns; }
+            const double dsum = wave_sum(dropped), ns = wave_sum((double)n_surv);
+            if (lane == 0u) { s.wdrop[wave] = dsum; s.wsurv[wave] = ns; }
         }
         __syncthreads();
 
@@ -607,26 +676,31 @@ __global__ __launch_bounds__(kThreads) void step_kernel(const StepArgs a) {
         bool ov[P];
         double2 ow[P];
         unsigned long long otail[P];
-        const bool is_head = (i < H) && (s.flags[i] & 2);
-        int len = 0;
-        if (is_head) {
-            len = 1;
-            while (i + len < kThreads && len < P && (s.flags[i + len] & 1) && !(s.flags[i + len] & 2)) ++len;
+        unsigned int msurv[P];
+        unsigned long long mtail[P];
+#pragma unroll
+        for (int m = 0; m < P; ++m) {                      // members of the segment (clamped reads)
+            const int j = min(i + m, kThreads - 1);
+            msurv[m] = m < len ? s.surv[j] : 0u;
+            mtail[m] = s.ctail[j];
         }
 #pragma unroll
         for (int p = 0; p < P; ++p) {
+            double2 mw[P];
+#pragma unroll
+            for (int m = 0; m < P; ++m) mw[m] = s.cw[p][min(i + m, kThreads - 1)];
             bool any = false;
             double sr = 0.0, si = 0.0;
             unsigned long long bq = 0, bt = 0;
-            for (int m = 0; m < len; ++m) {
-                if (!((s.surv[i + m] >> p) & 1u)) continue;
-                const double2 w = s.cw[p][i + m];
+#pragma unroll
+            for (int m = 0; m < P; ++m) {
+                if (!((msurv[m] >> p) & 1u)) continue;
+                const double2 w = mw[m];
                 sr += w.x;
                 si += w.y;
                 const unsigned long long q =
                     (unsigned long long)__double_as_longlong(norm2_nocontract(w.x, w.y)) & a.qmask;
-                const unsigned long long ct = s.ctail[i + m];
-                if (!any || q > bq || (q == bq && ct < bt)) { bq = q; bt = ct; }
+                if (!any || q > bq || (q == bq && mtail[m] < bt)) { bq = q; bt = mtail[m]; }
                 any = true;
             }
             ov[p] = any;
@@ -634,36 +708,15 @@ __global__ __launch_bounds__(kThreads) void step_kernel(const StepArgs a) {
             otail[p] = bt;
         }
 
-        // ---- ranks: block prefix of the output flags per pair, segmented by super-bucket
-        const bool run_start = valid && (i == 0 || s.sig[i - 1] != my_sig);
-        const unsigned long long rs_mask = __ballot(run_start);
+        // ---- ranks: per pair, wave ballots; block offsets from the per-wave counts
         unsigned int lrank[P];
 #pragma unroll
         for (int p = 0; p < P; ++p) {
             const unsigned long long bal = __ballot(ov[p]);
             lrank[p] = rank_below(bal);
-            if (lane == 0) s.wcount[wave][p] = (unsigned int)__popcll(bal);
-        }
-        if (lane == 0) s.wstart[wave] = rs_mask ? wave * 64 + 63 - __builtin_clzll(rs_mask) : -1;
-        __syncthreads();
-#pragma unroll
-        for (int p = 0; p < P; ++p) {
-            unsigned int e = lrank[p];
-            for (int w = 0; w < wave; ++w) e += s.wcount[w][p];
-            s.excl[p][i] = e;
-            if (i == kThreads - 1) s.excl[p][kThreads] = e + (ov[p] ? 1u : 0u);
-        }
-        // start of this parent's super-bucket run inside the chunk
-        int start;
-        {
-            const unsigned long long le = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
-            const unsigned long long m = rs_mask & le;
-            if (m) {
-                start = wave * 64 + 63 - __builtin_clzll(m);
-            } else {
-                start = 0;
-                for (int w = wave - 1; w >= 0; --w)
-                    if (s.wstart[w] >= 0) { start = s.wstart[w]; break; }
+            if (lane == 0u) {
+                s.omask[p][wave] = bal;
+                s.ocount[p][wave] = (unsigned int)__popcll(bal);
             }
         }
         if (i < S) {                                       // this chunk's partial sums
@@ -679,18 +732,26 @@ __global__ __launch_bounds__(kThreads) void step_kernel(const StepArgs a) {
             a.partials[(size_t)i * a.max_chunks + c] = v;
         }
         __syncthreads();
+        unsigned int my_excl[P], run_base[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            unsigned int e = lrank[p];
+            for (int w = 0; w < wave; ++w) e += s.ocount[p][w];
+            my_excl[p] = e;
+            run_base[p] = excl_at(s, p, start);
+        }
 
         // ---- look-back: the first run continues a super-bucket cut by the chunk boundary
-        const bool first_cont = g0 > 0u && s.prev_sig == s.sig[0];
-        const bool next_cont = (c + 1 < n_chunks) && s.sig[H - 1] == s.sig[H];
+        const bool first_cont = g0 > 0u && s.prev_sig == s.sig0;
+        const bool next_cont = (i == H - 1) && (c + 1 < n_chunks) && nsg == my_sig;
         const bool from_prev = (start == 0) && first_cont;
         unsigned long long* const slot_c = a.chain + c;
-        if (next_cont && i == H - 1) {
+        if (next_cont) {
             // totals of the last run: inclusive now unless they start with the continued run
 #pragma unroll
             for (int p = 0; p < P; ++p)
                 st_relaxed(slot_c + (size_t)p * a.max_chunks,
-                           ep | (from_prev ? kAgg : kInc) | (s.excl[p][H] - s.excl[p][start]));
+                           ep | (from_prev ? kAgg : kInc) | (my_excl[p] + (ov[p] ? 1u : 0u) - run_base[p]));
         }
         if (first_cont) {
             if (wave == 0 && (int)lane < P) {
@@ -711,11 +772,11 @@ __global__ __launch_bounds__(kThreads) void step_kernel(const StepArgs a) {
                 s.base[lane] = sum;
             }
             __syncthreads();
-            if (next_cont && from_prev && i == H - 1) {
+            if (next_cont && from_prev) {
 #pragma unroll
                 for (int p = 0; p < P; ++p)
                     st_relaxed(slot_c + (size_t)p * a.max_chunks,
-                               ep | kInc | (s.excl[p][H] - s.excl[p][0] + s.base[p]));
+                               ep | kInc | (my_excl[p] + (ov[p] ? 1u : 0u) - run_base[p] + s.base[p]));
             }
         }
 
@@ -725,7 +786,7 @@ __global__ __launch_bounds__(kThreads) void step_kernel(const StepArgs a) {
             for (int p = 0; p < P; ++p) {
                 if (!ov[p]) continue;
                 const unsigned long long idx =
-                    (unsigned long long)(s.excl[p][i] - s.excl[p][start]) + (from_prev ? s.base[p] : 0u);
+                    (unsigned long long)(my_excl[p] - run_base[p]) + (from_prev ? s.base[p] : 0u);
                 if ((long long)idx >= a.cap) {
                     raise_error(a.error, t, kErrOverflow);
                     continue;
@@ -737,16 +798,13 @@ __global__ __launch_bounds__(kThreads) void step_kernel(const StepArgs a) {
             }
         }
         // bucket sizes: the last parent of each run that ends in this chunk records the totals
-        if (i < H) {
-            const bool run_end = (i == H - 1) ? !next_cont : (s.sig[i + 1] != my_sig);
-            if (run_end) {
+        if (i < H && ((i == H - 1) ? !next_cont : (nsg != my_sig))) {
 #pragma unroll
-                for (int p = 0; p < P; ++p) {
-                    const unsigned int tot = s.excl[p][i] + (ov[p] ? 1u : 0u) - s.excl[p][start] +
-                                             (from_prev ? s.base[p] : 0u);
-                    if (tot) a.out_count[(size_t)p * a.n_super + my_sig] =
-                                 tot > (unsigned long long)a.cap ? (unsigned int)a.cap : tot;
-                }
+            for (int p = 0; p < P; ++p) {
+                const unsigned int tot = my_excl[p] + (ov[p] ? 1u : 0u) - run_base[p] +
+                                         (from_prev ? s.base[p] : 0u);
+                if (tot) a.out_count[(size_t)p * a.n_super + my_sig] =
+                             tot > (unsigned long long)a.cap ? (unsigned int)a.cap : tot;
             }
         }
         if (!has_next) break;
