@@ -106,6 +106,32 @@ __device__ inline double wave_sum(double v) {
     return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
 }
 
+// Eight per-lane values reduced over the lanes of each row of 16, four rows
+// per wave, in a fixed order: two butterfly levels (partners lane^1, lane^2)
+// that each keep half of the values, then a shift-add scan by 4 and 8 lanes
+// inside the row.  Afterwards lane 12 + r of a row holds the row sums of
+// values 4*(r&1) + 2*(r>>1) + {0, 1}.
+__device__ inline double dpp_sel_xor(double keep, double send, int level) {
+    return keep + (level == 1 ? dpp_pair<0xB1>(send) : dpp_pair<0x4E>(send));
+}
+
+__device__ inline void row_sums8(const double (&v)[8], unsigned int lane, double& x0, double& x1) {
+    const bool h1 = lane & 1u, h2 = (lane >> 1) & 1u;
+    double u[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) u[j] = dpp_sel_xor(h1 ? v[4 + j] : v[j], h1 ? v[j] : v[4 + j], 1);
+    double x[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) x[j] = dpp_sel_xor(h2 ? u[2 + j] : u[j], h2 ? u[j] : u[2 + j], 2);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        x[j] += dpp_pair<0x114>(x[j]);   // row_shr:4 (lanes 0..3 of a row add 0)
+        x[j] += dpp_pair<0x118>(x[j]);   // row_shr:8
+    }
+    x0 = x[0];
+    x1 = x[1];
+}
+
 __device__ inline unsigned long long ld_relaxed(const unsigned long long* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -281,9 +307,9 @@ struct Lds {
     unsigned int ocount[P][kWaves];        // their popcounts
     int wstart[kWaves];                    // last super-bucket run start in each wave
     unsigned int base[P];                  // offsets of the first run when it continues
-    double2 wrho[kWaves][P];
+    double wrho[kWaves][4][P == 4 ? 8 : 2 * P];   // rho sums per wave and row of 16 lanes (two levels)
     double wdrop[kWaves];
-    double wsurv[kWaves];
+    unsigned int wsurv[kWaves];
     unsigned int sig0, prev_sig;           // super-bucket of the first parent and of the group before
     double e0, f0;
 };
@@ -328,7 +354,7 @@ __device__ inline int window_search(const Lds<P>& s, unsigned int g) {
 
 template <int P, int C>
 __device__ inline Parent fetch_parent(const StepArgs& a, const Lds<P>& s, unsigned int c, unsigned int N,
-                                      long long nrec, int i, unsigned int lane) {
+                                      unsigned int nrec, int i, unsigned int lane) {
     Parent r;
     r.key = ~0ull;
     r.tail = 0ull;
@@ -341,7 +367,7 @@ __device__ inline Parent fetch_parent(const StepArgs& a, const Lds<P>& s, unsign
     if (g < N) {
         const int k = window_search(s, g);
         const unsigned int b = s.win_b[k];
-        const long long o = (long long)b * a.cap + (long long)(g - s.win_p[k]);
+        const unsigned int o = b * (unsigned int)a.cap + (g - s.win_p[k]);   // the store has < 2^31 records
         if (o < nrec) {
             r.key = a.in.key[o];
             r.tail = a.in.tail[o];
@@ -356,7 +382,7 @@ __device__ inline Parent fetch_parent(const StepArgs& a, const Lds<P>& s, unsign
             const int kn = window_search(s, gn);
             const unsigned int bn = s.win_b[kn];
             if (lane == 0u) {
-                const long long op = (long long)bn * a.cap + (long long)(gn - s.win_p[kn]);
+                const unsigned int op = bn * (unsigned int)a.cap + (gn - s.win_p[kn]);
                 if (op < nrec) {
                     r.pkey = a.in.key[op];
                     r.psig = bn / P;
@@ -412,7 +438,7 @@ __global__ __launch_bounds__(kThreads, P == 4 ? 4 : 1) void step_kernel(const St
     if (c >= n_chunks) return;
 
     // ---- the first chunk's window and the next one's, in flight during the set-up
-    const long long nrec = (long long)a.n_super * P * a.cap;
+    const unsigned int nrec = (unsigned int)((long long)a.n_super * P * a.cap);
     WinRegs wr = load_window(a, a.desc[c], n_nz, N, i);
     WinRegs wn = {0u, 0u, 0u, 0u};
     if (c + G < n_chunks) wn = load_window(a, a.desc[c + G], n_nz, N, i);
@@ -563,7 +589,7 @@ __global__ __launch_bounds__(kThreads, P == 4 ? 4 : 1) void step_kernel(const St
 #pragma unroll
         for (int p = 0; p < P; ++p) { rho_re[p] = 0.0; rho_im[p] = 0.0; }
         double dropped = 0.0;
-        unsigned int n_surv = 0, surv_bits = 0;
+        unsigned int surv_bits = 0;
         unsigned long long ctail = 0;
         if (owned) {
             double A = 0.0, B = 0.0, Ac = 0.0, Bc = 0.0;
@@ -648,7 +674,6 @@ __global__ __launch_bounds__(kThreads, P == 4 ? 4 : 1) void step_kernel(const St
                 const bool keep = (a.theta2 == 0.0) || !(n2 < a.theta2);
                 if (keep) {
                     surv_bits |= 1u << p;
-                    ++n_surv;
                     rho_re[p] = wr2 * fr[p] - wi2 * fi[p];
                     rho_im[p] = wr2 * fi[p] + wi2 * fr[p];
                 } else {
@@ -661,13 +686,32 @@ __global__ __launch_bounds__(kThreads, P == 4 ? 4 : 1) void step_kernel(const St
         s.ctail[i] = ctail;
 
         // ---- partial sums of rho, dropped weight and survivor count
+        if constexpr (P == 4) {
+            const double v[8] = {rho_re[0], rho_im[0], rho_re[1], rho_im[1],
+                                 rho_re[2], rho_im[2], rho_re[3], rho_im[3]};
+            double x0, x1;
+            row_sums8(v, lane, x0, x1);
+            if ((lane & 15u) >= 12u) {
+                const unsigned int r = lane & 3u;
+                const int k = 4 * (int)(r & 1u) + 2 * (int)(r >> 1);
+                s.wrho[wave][lane >> 4][k] = x0;
+                s.wrho[wave][lane >> 4][k + 1] = x1;
+            }
+        } else {
 #pragma unroll
-        for (int p = 0; p < P; ++p) {
-            const double r = wave_sum(rho_re[p]), m = wave_sum(rho_im[p]);
-            if (lane == 0u) s.wrho[wave][p] = make_double2(r, m);
+            for (int p = 0; p < P; ++p) {
+                const double r = wave_sum(rho_re[p]), m = wave_sum(rho_im[p]);
+                if (lane == 0u) {
+                    s.wrho[wave][0][2 * p] = r;
+                    s.wrho[wave][0][2 * p + 1] = m;
+                }
+            }
         }
         {
-            const double dsum = wave_sum(dropped), ns = wave_sum((double)n_surv);
+            const double dsum = wave_sum(dropped);
+            unsigned int ns = 0u;
+#pragma unroll
+            for (int p = 0; p < P; ++p) ns += (unsigned int)__popcll(__ballot((surv_bits >> p) & 1u));
             if (lane == 0u) { s.wdrop[wave] = dsum; s.wsurv[wave] = ns; }
         }
         __syncthreads();
@@ -722,12 +766,14 @@ __global__ __launch_bounds__(kThreads, P == 4 ? 4 : 1) void step_kernel(const St
         if (i < S) {                                       // this chunk's partial sums
             double v = 0.0;
             if (i < 2 * P) {
-                const int p = i >> 1;
-                for (int w = 0; w < kWaves; ++w) v += (i & 1) ? s.wrho[w][p].y : s.wrho[w][p].x;
+                for (int w = 0; w < kWaves; ++w)
+                    for (int r = 0; r < (P == 4 ? 4 : 1); ++r) v += s.wrho[w][r][i];
             } else if (i == 2 * P) {
                 for (int w = 0; w < kWaves; ++w) v += s.wdrop[w];
             } else {
-                for (int w = 0; w < kWaves; ++w) v += s.wsurv[w];
+                unsigned int ns = 0u;
+                for (int w = 0; w < kWaves; ++w) ns += s.wsurv[w];
+                v = (double)ns;
             }
             a.partials[(size_t)i * a.max_chunks + c] = v;
         }
@@ -785,13 +831,12 @@ __global__ __launch_bounds__(kThreads, P == 4 ? 4 : 1) void step_kernel(const St
 #pragma unroll
             for (int p = 0; p < P; ++p) {
                 if (!ov[p]) continue;
-                const unsigned long long idx =
-                    (unsigned long long)(my_excl[p] - run_base[p]) + (from_prev ? s.base[p] : 0u);
-                if ((long long)idx >= a.cap) {
+                const unsigned int idx = my_excl[p] - run_base[p] + (from_prev ? s.base[p] : 0u);
+                if (idx >= (unsigned int)a.cap) {
                     raise_error(a.error, t, kErrOverflow);
                     continue;
                 }
-                const size_t o = ((size_t)p * a.n_super + my_sig) * (size_t)a.cap + idx;
+                const unsigned int o = ((unsigned int)p * (unsigned int)a.n_super + my_sig) * (unsigned int)a.cap + idx;
                 a.out.key[o] = ((unsigned long long)p << top_shift) | (key >> BP);
                 a.out.tail[o] = otail[p];
                 a.out.w[o] = ow[p];
@@ -803,8 +848,8 @@ __global__ __launch_bounds__(kThreads, P == 4 ? 4 : 1) void step_kernel(const St
             for (int p = 0; p < P; ++p) {
                 const unsigned int tot = my_excl[p] + (ov[p] ? 1u : 0u) - run_base[p] +
                                          (from_prev ? s.base[p] : 0u);
-                if (tot) a.out_count[(size_t)p * a.n_super + my_sig] =
-                             tot > (unsigned long long)a.cap ? (unsigned int)a.cap : tot;
+                if (tot) a.out_count[(unsigned int)p * (unsigned int)a.n_super + my_sig] =
+                             tot > (unsigned int)a.cap ? (unsigned int)a.cap : tot;
             }
         }
         if (!has_next) break;
