@@ -376,20 +376,20 @@ __device__ inline Parent fetch_parent(const StepArgs& a, const Lds<P>& s, unsign
         } else {
             raise_error(a.error, a.t, kErrOverflow);
         }
-        // lane 0: the group before; lane 63: the group after (one search for both)
-        if ((lane == 0u && g > 0u) || (lane == 63u && g + 1u < N)) {
-            const unsigned int gn = lane == 0u ? g - 1u : g + 1u;
-            const int kn = window_search(s, gn);
+        // lane 0: the group before; lane 63: the group after.  Each lies in the
+        // bucket of g or in the nonempty bucket next to it in the list.
+        if (lane == 0u && g > 0u) {
+            const int kn = (g - 1u >= s.win_p[k] || k == 0) ? k : k - 1;
             const unsigned int bn = s.win_b[kn];
-            if (lane == 0u) {
-                const unsigned int op = bn * (unsigned int)a.cap + (gn - s.win_p[kn]);
-                if (op < nrec) {
-                    r.pkey = a.in.key[op];
-                    r.psig = bn / P;
-                }
-            } else {
-                r.nsig = bn / P;
+            const unsigned int op = bn * (unsigned int)a.cap + (g - 1u - s.win_p[kn]);
+            if (op < nrec) {
+                r.pkey = a.in.key[op];
+                r.psig = bn / P;
             }
+        }
+        if (lane == 63u && g + 1u < N) {
+            const int kn = (k + 1 < kWin && g + 1u >= s.win_p[k + 1]) ? k + 1 : k;
+            r.nsig = s.win_b[kn] / P;
         }
     }
     return r;
