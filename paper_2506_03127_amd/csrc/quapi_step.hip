@@ -182,9 +182,9 @@ __global__ __launch_bounds__(kPlanThreads) void plan_kernel(const PlanArgs a) {
     if (w == n_regions) {
         // ---- counters and rho(t) of the step just finished, summed in chunk order
         if (a.reduce_t <= 0) return;
+        const unsigned int nc = a.plan_prev->n_chunks;
         const unsigned int err = error_word(a.error);
         if (err != 0u && (int)(err >> 4) <= a.reduce_t) return;   // that step failed: keep nothing
-        const unsigned int nc = a.plan_prev->n_chunks;
         double acc[S];
 #pragma unroll
         for (int k = 0; k < S; ++k) acc[k] = 0.0;
@@ -194,8 +194,7 @@ __global__ __launch_bounds__(kPlanThreads) void plan_kernel(const PlanArgs a) {
             for (int k = 0; k < S; ++k) acc[k] += a.partials[(size_t)k * a.max_chunks + c];
 #pragma unroll
         for (int k = 0; k < S; ++k) {
-            double v = acc[k];
-            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+            const double v = wave_sum(acc[k]);
             if (lane == 0) wred[wave][k] = v;
         }
         __syncthreads();
