@@ -715,10 +715,8 @@ __global__ __launch_bounds__(kThreads, P == 4 ? 4 : 1) void step_kernel(const St
         }
         __syncthreads();
 
-        // ---- merge each segment per pair
+        // ---- which pairs of each segment keep a merged group (any member survives)
         bool ov[P];
-        double2 ow[P];
-        unsigned long long otail[P];
         unsigned int msurv[P];
         unsigned long long mtail[P];
 #pragma unroll
@@ -727,28 +725,12 @@ __global__ __launch_bounds__(kThreads, P == 4 ? 4 : 1) void step_kernel(const St
             msurv[m] = m < len ? s.surv[j] : 0u;
             mtail[m] = s.ctail[j];
         }
+        {
+            unsigned int anyp = 0u;
 #pragma unroll
-        for (int p = 0; p < P; ++p) {
-            double2 mw[P];
+            for (int m = 0; m < P; ++m) anyp |= msurv[m];
 #pragma unroll
-            for (int m = 0; m < P; ++m) mw[m] = s.cw[p][min(i + m, kThreads - 1)];
-            bool any = false;
-            double sr = 0.0, si = 0.0;
-            unsigned long long bq = 0, bt = 0;
-#pragma unroll
-            for (int m = 0; m < P; ++m) {
-                if (!((msurv[m] >> p) & 1u)) continue;
-                const double2 w = mw[m];
-                sr += w.x;
-                si += w.y;
-                const unsigned long long q =
-                    (unsigned long long)__double_as_longlong(norm2_nocontract(w.x, w.y)) & a.qmask;
-                if (!any || q > bq || (q == bq && mtail[m] < bt)) { bq = q; bt = mtail[m]; }
-                any = true;
-            }
-            ov[p] = any;
-            ow[p] = make_double2(sr, si);
-            otail[p] = bt;
+            for (int p = 0; p < P; ++p) ov[p] = (anyp >> p) & 1u;
         }
 
         // ---- ranks: per pair, wave ballots; block offsets from the per-wave counts
@@ -786,18 +768,47 @@ __global__ __launch_bounds__(kThreads, P == 4 ? 4 : 1) void step_kernel(const St
             run_base[p] = excl_at(s, p, start);
         }
 
-        // ---- look-back: the first run continues a super-bucket cut by the chunk boundary
+        // ---- publish the totals of the last run for the chunk after this one: inclusive
+        //      now unless the last run is the continued first run
         const bool first_cont = g0 > 0u && s.prev_sig == s.sig0;
         const bool next_cont = (i == H - 1) && (c + 1 < n_chunks) && nsg == my_sig;
         const bool from_prev = (start == 0) && first_cont;
         unsigned long long* const slot_c = a.chain + c;
         if (next_cont) {
-            // totals of the last run: inclusive now unless they start with the continued run
 #pragma unroll
             for (int p = 0; p < P; ++p)
                 st_relaxed(slot_c + (size_t)p * a.max_chunks,
                            ep | (from_prev ? kAgg : kInc) | (my_excl[p] + (ov[p] ? 1u : 0u) - run_base[p]));
         }
+
+        // ---- merge each segment per pair: sum of the surviving weights and the
+        //      representative (while the word published above travels)
+        double2 ow[P];
+        unsigned long long otail[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            double2 mw[P];
+#pragma unroll
+            for (int m = 0; m < P; ++m) mw[m] = s.cw[p][min(i + m, kThreads - 1)];
+            bool any = false;
+            double sr = 0.0, si = 0.0;
+            unsigned long long bq = 0, bt = 0;
+#pragma unroll
+            for (int m = 0; m < P; ++m) {
+                if (!((msurv[m] >> p) & 1u)) continue;
+                const double2 w = mw[m];
+                sr += w.x;
+                si += w.y;
+                const unsigned long long q =
+                    (unsigned long long)__double_as_longlong(norm2_nocontract(w.x, w.y)) & a.qmask;
+                if (!any || q > bq || (q == bq && mtail[m] < bt)) { bq = q; bt = mtail[m]; }
+                any = true;
+            }
+            ow[p] = make_double2(sr, si);
+            otail[p] = bt;
+        }
+
+        // ---- look-back: the first run continues a super-bucket cut by the chunk boundary
         if (first_cont) {
             if (wave == 0 && (int)lane < P) {
                 const unsigned long long* row = a.chain + (size_t)lane * a.max_chunks;
