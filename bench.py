@@ -86,6 +86,44 @@ def cpu_baseline(wl, steps: int) -> dict:
                       f"{el:.1f} s, single thread, {cpu_model()})"}
 
 
+def traffic_from_counters(fetch_csv: str, write_csv: str, out_path: str, copy_mib: int) -> dict:
+    """HBM bytes per step-kernel launch from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE,
+    KiB per dispatch) of ``bench.py --copy-mib N``: each counter is scaled by what it reads for
+    that plain N-MiB device copy, whose true traffic is N MiB read and N MiB written."""
+    import csv
+
+    def read(path, counter):
+        step, other = [], []
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            v = float(r["Counter_Value"])
+            name = r.get("Kernel_Name", "")
+            if "step_kernel" in name:
+                step.append(v)
+            elif "plan_kernel" not in name:
+                other.append(v)
+        return step, max(other)
+
+    f_step, f_copy = read(fetch_csv, "FETCH_SIZE")
+    w_step, w_copy = read(write_csv, "WRITE_SIZE")
+    rec = {"copy_bytes": copy_mib << 20}
+    copy_kib = copy_mib * 1024.0
+    ff, fw = copy_kib / f_copy, copy_kib / w_copy
+    fetch_b = float(np.mean(f_step)) * 1024.0 * ff
+    write_b = float(np.mean(w_step)) * 1024.0 * fw
+    rec.update({"kernel_source_sha256": kernel_source_hash(),
+                "launches": len(f_step),
+                "fetch_kib_per_launch_raw": float(np.mean(f_step)),
+                "write_kib_per_launch_raw": float(np.mean(w_step)),
+                "copy_fetch_kib_raw": f_copy, "copy_write_kib_raw": w_copy,
+                "fetch_scale": ff, "write_scale": fw,
+                "fetch_bytes_per_launch": fetch_b, "write_bytes_per_launch": write_b,
+                "bytes_per_launch": fetch_b + write_b})
+    json.dump(rec, open(out_path, "w"), indent=1)
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,7 +134,14 @@ def main():
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="one plain device copy of this size after the timed work (PMC calibration)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the step kernel's HBM traffic per launch from the counter files of "
+                         "two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of bench.py --copy-mib; no GPU")
     args = ap.parse_args()
+    if args.traffic_from:
+        print(json.dumps(traffic_from_counters(args.traffic_from[0], args.traffic_from[1], TRAFFIC_FILE,
+                                               args.copy_mib or 256)))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the path is built "
               "and measured at one GPU's share", file=sys.stderr)
