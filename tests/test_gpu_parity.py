@@ -165,6 +165,23 @@ def test_three_level_system(Q, eta_cache):
     assert_groups(o, g)
 
 
+@pytest.mark.parametrize("make,mode,K,mask,theta,n", [
+    # long memory: the two-level history sums take the per-lag loop instead of the tables
+    (W.structured_bath, "pre", 40, tuple(range(12)), 1e-8, 14),
+    # three levels (9 pairs, 4-bit points), larger memory and both merging orders
+    (W.three_level, "pre", 10, tuple(range(6)), 1e-7, 25),
+    (W.three_level, "post", 8, (0, 1, 2, 3, 4), 1e-6, 40),
+], ids=["two-level-K40", "three-level-K10-pre", "three-level-K8-post"])
+def test_other_shapes(Q, eta_cache, make, mode, K, mask, theta, n):
+    wl = make(K=K)
+    eta = eta_cache(wl, K)
+    o, g = run_both(Q, wl.H, wl.q, wl.dt, K, eta, wl.rho0, n, mode=mode, mask=mask, theta=theta)
+    assert ambiguous(o, n) == 0
+    assert_rho(o, g, n)
+    assert_stats(o, g, n)
+    assert_groups(o, g)
+
+
 # ------------------------------------------------------------------ edge cases
 def test_determinism_and_reset(Q, eta_cache):
     wl = W.structured_bath(K=12)
