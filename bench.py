@@ -37,7 +37,8 @@ METRIC = "path-steps/sec + HBM roofline fraction at dk_max=24, theta=1e-8; time 
 HBM_PEAK_GBS = 8000.0
 RECORD_BYTES = 32
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_traffic.json")
-KERNEL_SOURCES = ["paper_2506_03127_amd/csrc/quapi_step.hip", "paper_2506_03127_amd/csrc/quapi_host.h"]
+KERNEL_SOURCES = ["paper_2506_03127_amd/csrc/quapi_step.hip", "paper_2506_03127_amd/csrc/quapi_device.h",
+                  "paper_2506_03127_amd/csrc/quapi_host.h"]
 
 
 def kernel_source_hash() -> str:

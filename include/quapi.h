@@ -67,7 +67,10 @@ typedef struct {
                               /*  eta[2*(K+1)+d]  initial x final point (d >= 1);                       */
                               /* eta[1*(K+1)+0] is the end-point self term (eq. inf_fun)                 */
     const int* mask;          /* MACGIC mask (Sec. 2.1): n_mask sorted lags, mask[0]=0, mask[1]=1,      */
-                              /* mask[n_mask-1] <= K-1; NULL: every lag 0..K-1                          */
+                              /* mask[n_mask-1] <= K-1; NULL: every lag 0..K-1.  Merge positions       */
+                              /* 0..L-1 (L >= 2) run on the bucketed store; any other set merges       */
+                              /* through a hash table and needs the whole history in 64 bits           */
+                              /* (K <= 32 for M = 2, K <= 16 for M = 3)                                 */
     int n_mask;
     double theta;             /* filter: drop a child when |w|^2 < theta^2; 0 disables                  */
     const quapi_c64* rho0;    /* M*M initial reduced density matrix                                     */
@@ -78,7 +81,7 @@ typedef struct {
                               /* < 0: default 32                                                        */
     long long max_groups;     /* stored groups to allocate for, spread evenly over the key buckets     */
                               /* (at least one each; an uneven fill reports ENOMEM first); 0: room   */
-                              /* for every key of the merge positions                                 */
+                              /* for every key of the merge positions (hash-table merge: up to 2^21) */
     int max_steps;            /* initial capacity of the rho(t) history; grows on demand; <= 0: 1024    */
     void* stream;             /* hipStream_t to run on (e.g. a torch stream); NULL: a library stream   */
 } quapi_params;
@@ -97,15 +100,17 @@ typedef struct {
 typedef struct {
     int M, P, K, L;           /* P = M*M pairs; L = key length in points (merge positions 0..L-1)     */
     int bits_per_point;       /* history bits per point                                                 */
-    int record_bytes;         /* bytes of one stored group: 8 key + 8 history tail + 16 weight          */
+    int record_bytes;         /* bytes of one stored group: 8 key + 8 history tail + 16 weight (32),    */
+                              /* or 8 history + 16 weight (24) on the hash-table merge                  */
     long long capacity;       /* maximum number of stored groups                                        */
     size_t device_bytes;      /* device memory held by the context                                      */
 } quapi_info_t;
 
 /* Create a context and its initial state t = 0 (one path per nonzero
  * element of rho0, weighted by the initial point's self term).
- * Errors: EINVAL (bad argument), EUNSUPPORTED (a mask whose merge positions
- * are not 0..L-1 with L >= 2, or M > 3), ENOMEM, EDEVICE.  *out is NULL on error. */
+ * Errors: EINVAL (bad argument), EUNSUPPORTED (M > 3; merge positions 0..L-1
+ * with L bits-per-point > 62 bits or a tail over 64 bits; other merge positions
+ * with a history over 64 bits), ENOMEM, EDEVICE.  *out is NULL on error. */
 int quapi_create(const quapi_params* p, quapi_ctx** out);
 
 /* Enqueue n_steps time steps on the context's stream; returns without waiting.

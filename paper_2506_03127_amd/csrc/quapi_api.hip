@@ -32,6 +32,25 @@ struct quapi_ctx {
     std::vector<unsigned long long> init_key;
     std::vector<double2> init_w;
     std::vector<long long> init_bucket;
+    std::vector<int> init_pair;
+
+    // sparse-mask path (merge positions not 0..L-1): hash-table merge
+    bool sparse = false;
+    std::vector<int> qpos;       // merge positions, most significant first
+    long long sp_cap = 0;        // group capacity
+    uint64_t* sp_h[2] = {nullptr, nullptr};
+    double2* sp_w[2] = {nullptr, nullptr};
+    unsigned int* sp_count = nullptr;            // [2] by step parity
+    unsigned long long* sp_tkey = nullptr;
+    unsigned long long* sp_tq = nullptr;
+    unsigned long long* sp_tT = nullptr;
+    double2* sp_tw = nullptr;
+    unsigned long long sp_tsize = 0;
+    unsigned int* sp_cslot = nullptr;
+    unsigned long long* sp_cT = nullptr;
+    unsigned long long* sp_cq = nullptr;
+    double* sp_partials = nullptr;
+    int sp_grid = 0;
 
     hipStream_t stream = nullptr;
     bool own_stream = false;
@@ -98,9 +117,36 @@ void dev_free(quapi_ctx* c, void* p, size_t bytes) {
 
 int launch_planner(quapi_ctx* c, int t);
 
+int upload_initial_sparse(quapi_ctx* c) {
+    const size_t n0 = c->init_pair.size();
+    std::vector<uint64_t> h(n0);
+    for (size_t k = 0; k < n0; ++k) h[k] = (uint64_t)c->init_pair[k];
+    const unsigned int cnt[2] = {(unsigned int)n0, 0u};
+    const size_t ts = (size_t)c->sp_tsize;
+    hipError_t e = hipSuccess;
+    if (n0) {
+        e = hipMemcpyAsync(c->sp_h[0], h.data(), n0 * sizeof(uint64_t), hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(c->sp_w[0], c->init_w.data(), n0 * sizeof(double2), hipMemcpyHostToDevice, c->stream);
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(c->sp_count, cnt, sizeof cnt, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c->sp_tkey, 0xff, ts * sizeof(unsigned long long), c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c->sp_tq, 0, ts * sizeof(unsigned long long), c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c->sp_tT, 0xff, ts * sizeof(unsigned long long), c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c->sp_tw, 0, ts * sizeof(double2), c->stream);
+    // the copies read host vectors of this frame: complete them before returning
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    return hip_to_code(e);
+}
+
 int upload_initial(quapi_ctx* c) {
-    hipError_t e = hipMemsetAsync(c->counts[0], 0, (size_t)c->n_buckets * sizeof(unsigned int), c->stream);
-    for (size_t k = 0; k < c->init_key.size() && e == hipSuccess; ++k) {
+    hipError_t e = hipSuccess;
+    if (c->sparse) {
+        if (upload_initial_sparse(c) != QUAPI_OK) e = hipErrorLaunchFailure;
+    } else {
+        e = hipMemsetAsync(c->counts[0], 0, (size_t)c->n_buckets * sizeof(unsigned int), c->stream);
+    }
+    for (size_t k = 0; !c->sparse && k < c->init_key.size() && e == hipSuccess; ++k) {
         const size_t o = (size_t)c->init_bucket[k] * (size_t)c->cap;
         const unsigned long long zero = 0;
         const unsigned int one = 1;
@@ -123,7 +169,7 @@ int upload_initial(quapi_ctx* c) {
     c->t = 0;
     c->cur = 0;
     c->err = QUAPI_OK;
-    if (e == hipSuccess && launch_planner(c, 0) != QUAPI_OK) e = hipErrorLaunchFailure;
+    if (e == hipSuccess && !c->sparse && launch_planner(c, 0) != QUAPI_OK) e = hipErrorLaunchFailure;
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     return hip_to_code(e);
 }
@@ -202,6 +248,56 @@ int sync_ctx(quapi_ctx* c) {
 
 bool is_finite_d(double x) { return std::isfinite(x); }
 
+// n time steps on the hash-table path (merge positions other than 0..L-1)
+int step_sparse(quapi_ctx* c, int n_steps) {
+    quapi_dev::SparseArgs a;
+    a.count = c->sp_count;
+    a.tkey = c->sp_tkey;
+    a.tq = c->sp_tq;
+    a.tT = c->sp_tT;
+    a.tw = c->sp_tw;
+    a.tmask = c->sp_tsize - 1;
+    a.cslot = c->sp_cslot;
+    a.cT = c->sp_cT;
+    a.cq = c->sp_cq;
+    a.cap = c->sp_cap;
+    a.P = c->P;
+    a.K = c->K;
+    a.theta2 = c->theta * c->theta;
+    a.qmask = c->qbits >= 64 ? 0ull : ~((1ull << c->qbits) - 1ull);
+    a.tables = c->d_tables;
+    a.nq = (int)c->qpos.size();
+    for (int k = 0; k < quapi_dev::kMaxK; ++k) a.qpos[k] = k < a.nq ? c->qpos[k] : 0;
+    a.partials = c->sp_partials;
+    a.grid = c->sp_grid;
+    a.rho_hist = c->d_rho;
+    a.stats_hist = c->d_stats;
+    a.error = c->d_error;
+    const int n = c->K + 1;
+    for (int k = 0; k < n_steps; ++k) {
+        const int t = c->t + 1;
+        a.h_in = c->sp_h[c->cur];
+        a.w_in = c->sp_w[c->cur];
+        a.h_out = c->sp_h[1 - c->cur];
+        a.w_out = c->sp_w[1 - c->cur];
+        a.t = t;
+        a.coef = c->d_coef + (size_t)(std::min(t, c->K + 1) - 1) * 4 * n;
+        hipEvent_t* ev = (c->prof_on && c->prof_n < c->prof_cap) ? &c->prof_ev[3 * (size_t)c->prof_n++] : nullptr;
+        if (ev && hipEventRecord(ev[0], c->stream) != hipSuccess) ev = nullptr;
+        if (quapi_dev::launch_sparse_step(a, c->stream) != (int)hipSuccess) {
+            c->err = QUAPI_EDEVICE;
+            return c->err;
+        }
+        if (ev) {
+            (void)hipEventRecord(ev[1], c->stream);
+            (void)hipEventRecord(ev[2], c->stream);
+        }
+        c->t = t;
+        c->cur = 1 - c->cur;
+    }
+    return QUAPI_OK;
+}
+
 long long ipow(long long b, int e) {
     long long r = 1;
     for (int i = 0; i < e; ++i) r *= b;
@@ -279,13 +375,19 @@ int quapi_create(const quapi_params* p, quapi_ctx** out) {
     } else {
         pos = mask;
     }
+    // merge positions 0..L-1 (L >= 2) take the bucketed path; any other set the
+    // hash-table path, which keeps each history in one 64-bit word
+    bool contiguous = pos.size() >= 2;
     for (size_t i = 0; i < pos.size(); ++i)
-        if (pos[i] != (int)i) return QUAPI_EUNSUPPORTED;   // merge positions must be 0..L-1
+        if (pos[i] != (int)i) contiguous = false;
     const int L = (int)pos.size();
-    if (L < 2) return QUAPI_EUNSUPPORTED;
     const int P = M * M;
     const int bits = P <= 4 ? 2 : 4;
-    if (L * bits > 62 || (K - L) * bits > 64) return QUAPI_EUNSUPPORTED;
+    if (contiguous) {
+        if (L * bits > 62 || (K - L) * bits > 64) return QUAPI_EUNSUPPORTED;
+    } else {
+        if (K * bits > 64 || L * bits > 62) return QUAPI_EUNSUPPORTED;
+    }
 
     quapi_ctx* c = new (std::nothrow) quapi_ctx();
     if (!c) return QUAPI_ENOMEM;
@@ -298,6 +400,8 @@ int quapi_create(const quapi_params* p, quapi_ctx** out) {
     c->qbits = p->qbits < 0 ? 32 : std::min(p->qbits, 63);
     c->dt = p->dt;
     c->theta = p->theta;
+    c->sparse = !contiguous;
+    c->qpos = pos;
 
     // buckets: the top D points of the key, D-1 the most points with at most
     // max_super super-buckets (bounded by what the planner is built for); a
@@ -307,11 +411,11 @@ int quapi_create(const quapi_params* p, quapi_ctx** out) {
     if (const char* env = std::getenv("QUAPI_MAX_SUPER")) max_super = std::max(1ll, std::atoll(env));
     max_super = std::min(max_super, plan_super);
     int dm1 = 0;
-    while (dm1 + 1 <= L - 1 && ipow(P, dm1 + 1) <= max_super) ++dm1;
+    while (!c->sparse && dm1 + 1 <= L - 1 && ipow(P, dm1 + 1) <= max_super) ++dm1;
     c->D = dm1 + 1;
     c->n_super = (int)ipow(P, dm1);
     c->n_buckets = ipow(P, c->D);
-    long long cap = ipow(P, L - c->D);
+    long long cap = c->sparse ? 1 : ipow(P, L - c->D);
     if (p->max_groups > 0) cap = std::max(1ll, std::min(cap, (p->max_groups + c->n_buckets - 1) / c->n_buckets));
     // group indices are 32-bit: keep the whole store below 2^31 groups
     cap = std::min(cap, ((1ll << 31) - 1) / c->n_buckets);
@@ -373,7 +477,8 @@ int quapi_create(const quapi_params* p, quapi_ctx** out) {
         if (r == std::complex<double>(0, 0)) continue;
         const double ds = c->tables[TableLayout::ds(P) + pp], ss = c->tables[TableLayout::ss(P) + pp];
         const std::complex<double> w = r * std::exp(std::complex<double>(-ds * e0.real() * ds, -ds * e0.imag() * ss));
-        c->init_key.push_back((unsigned long long)pp << (bits * (L - 1)));
+        c->init_key.push_back(c->sparse ? 0ull : (unsigned long long)pp << (bits * (L - 1)));
+        c->init_pair.push_back(pp);
         c->init_w.push_back(make_double2(w.real(), w.imag()));
         c->init_bucket.push_back((long long)pp * c->n_super);   // top D points (pp, 0, ..., 0)
     }
@@ -389,7 +494,7 @@ int quapi_create(const quapi_params* p, quapi_ctx** out) {
         c->own_stream = true;
     }
 
-    const size_t nrec = (size_t)c->n_buckets * (size_t)cap;
+    const size_t nrec = c->sparse ? 1 : (size_t)c->n_buckets * (size_t)cap;
     for (int b = 0; b < 2 && rc == QUAPI_OK; ++b) {
         rc = dev_alloc(c, &c->buf[b].key, nrec);
         if (!rc) rc = dev_alloc(c, &c->buf[b].tail, nrec);
@@ -406,6 +511,28 @@ int quapi_create(const quapi_params* p, quapi_ctx** out) {
     if (!rc) rc = dev_alloc(c, &c->d_plan, 2);
     if (!rc) rc = dev_alloc(c, &c->d_chain, (size_t)P * c->max_chunks);
     if (!rc) rc = dev_alloc(c, &c->d_error, 1);
+    if (!rc && c->sparse) {
+        // capacity: max_groups, else every key of the merge positions up to 2^21 groups;
+        // the table holds twice the children a step can insert
+        long long scap = p->max_groups > 0 ? p->max_groups : std::min(ipow(P, std::min(L, 12)), 1ll << 21);
+        scap = std::max((long long)c->init_pair.size(), std::min(scap, ((1ll << 31) - 1) / P));
+        c->sp_cap = scap;
+        unsigned long long ts = 1024;
+        while (ts < 2ull * (unsigned long long)P * (unsigned long long)scap) ts <<= 1;
+        c->sp_tsize = ts;
+        for (int b = 0; b < 2 && !rc; ++b) {
+            rc = dev_alloc(c, &c->sp_h[b], (size_t)scap);
+            if (!rc) rc = dev_alloc(c, &c->sp_w[b], (size_t)scap);
+        }
+        if (!rc) rc = dev_alloc(c, &c->sp_count, 2);
+        if (!rc) rc = dev_alloc(c, &c->sp_tkey, (size_t)ts);
+        if (!rc) rc = dev_alloc(c, &c->sp_tq, (size_t)ts);
+        if (!rc) rc = dev_alloc(c, &c->sp_tT, (size_t)ts);
+        if (!rc) rc = dev_alloc(c, &c->sp_tw, (size_t)ts);
+        if (!rc) rc = dev_alloc(c, &c->sp_cslot, (size_t)scap * P);
+        if (!rc) rc = dev_alloc(c, &c->sp_cT, (size_t)scap * P);
+        if (!rc) rc = dev_alloc(c, &c->sp_cq, (size_t)scap * P);
+    }
     c->hist_cap = p->max_steps > 0 ? p->max_steps : 1024;
     if (!rc) rc = dev_alloc(c, &c->d_rho, (size_t)(c->hist_cap + 1) * P);
     if (!rc) rc = dev_alloc(c, &c->d_stats, (size_t)(c->hist_cap + 1));
@@ -441,6 +568,13 @@ int quapi_create(const quapi_params* p, quapi_ctx** out) {
         quapi_destroy(c);
         return QUAPI_EDEVICE;
     }
+    if (c->sparse) {
+        c->sp_grid = 4 * std::max(ncu, 1);
+        if (dev_alloc(c, &c->sp_partials, (size_t)c->sp_grid * quapi_dev::partial_stride(P)) != QUAPI_OK) {
+            quapi_destroy(c);
+            return QUAPI_ENOMEM;
+        }
+    }
     rc = upload_initial(c);
     if (rc) {
         quapi_destroy(c);
@@ -456,6 +590,7 @@ int quapi_step(quapi_ctx* c, int n_steps) {
     if (n_steps == 0) return QUAPI_OK;
     int rc = grow_history(c, c->t + n_steps);
     if (rc) return rc;
+    if (c->sparse) return step_sparse(c, n_steps);
     StepArgs a;
     a.cap = c->cap;
     a.P = c->P;
@@ -552,6 +687,27 @@ int quapi_groups(quapi_ctx* c, long long cap, unsigned char* hist, quapi_c64* w,
     if (!c || !n_out || cap < 0 || (cap > 0 && (!hist || !w))) return QUAPI_EINVAL;
     const int rc = sync_ctx(c);
     if (rc == QUAPI_EDEVICE) return rc;
+    if (c->sparse) {
+        unsigned int cnt2[2] = {0u, 0u};
+        hipError_t e = hipMemcpy(cnt2, c->sp_count, sizeof cnt2, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_to_code(e);
+        const long long n = cnt2[c->t & 1];
+        *n_out = n;
+        if (cap == 0 || n == 0) return QUAPI_OK;
+        std::vector<uint64_t> hh((size_t)n);
+        std::vector<double2> ww((size_t)n);
+        e = hipMemcpy(hh.data(), c->sp_h[c->cur], (size_t)n * 8, hipMemcpyDeviceToHost);
+        if (e == hipSuccess) e = hipMemcpy(ww.data(), c->sp_w[c->cur], (size_t)n * 16, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_to_code(e);
+        const unsigned long long dm = (1ull << c->bits) - 1;
+        for (long long r = 0; r < n && r < cap; ++r) {
+            unsigned char* row = hist + (size_t)r * c->K;
+            for (int j = 0; j < c->K; ++j) row[j] = (unsigned char)((hh[r] >> (c->bits * j)) & dm);
+            w[r].re = ww[r].x;
+            w[r].im = ww[r].y;
+        }
+        return QUAPI_OK;
+    }
     std::vector<unsigned int> cnt((size_t)c->n_buckets);
     hipError_t e = hipMemcpy(cnt.data(), c->counts[c->cur], cnt.size() * sizeof(unsigned int),
                              hipMemcpyDeviceToHost);
@@ -600,8 +756,8 @@ int quapi_info(quapi_ctx* c, quapi_info_t* out) {
     out->K = c->K;
     out->L = c->L;
     out->bits_per_point = c->bits;
-    out->record_bytes = 32;
-    out->capacity = c->n_buckets * c->cap;
+    out->record_bytes = c->sparse ? 24 : 32;
+    out->capacity = c->sparse ? c->sp_cap : c->n_buckets * c->cap;
     out->device_bytes = c->device_bytes;
     return QUAPI_OK;
 }

@@ -88,6 +88,41 @@ struct PlanArgs {
     const unsigned int* error;
 };
 
+// Sparse-mask path: groups as full histories (point j at bits [BP*j, BP*j+BP),
+// the newest point lowest) in no particular order, merged through an
+// open-addressing hash table keyed on the gathered merge positions.
+constexpr int kSparseThreads = 256;
+constexpr unsigned long long kEmptyKey = ~0ull;
+
+struct SparseArgs {
+    const uint64_t* h_in;           // stored groups (state at t-1)
+    const double2* w_in;
+    uint64_t* h_out;                // groups after step t
+    double2* w_out;
+    unsigned int* count;            // [2] stored groups, by parity of the time step
+    unsigned long long* tkey;       // [table] merge key, kEmptyKey when free
+    unsigned long long* tq;         // [table] largest quantised |w|^2 of the key's children
+    unsigned long long* tT;         // [table] smallest history among those (the representative)
+    double2* tw;                    // [table] sum of the key's child weights
+    unsigned long long tmask;       // table size - 1 (a power of two)
+    unsigned int* cslot;            // [cap * P] table slot of each child, ~0u if filtered
+    unsigned long long* cT;         // [cap * P] its history
+    unsigned long long* cq;         // [cap * P] its quantised |w|^2
+    long long cap;                  // group capacity
+    int P, K, t;
+    double theta2;
+    unsigned long long qmask;
+    const double* tables;
+    const double* coef;
+    int nq;                         // merge positions, most significant first
+    int qpos[kMaxK];
+    double* partials;               // [partial_stride(P)][grid] per expand workgroup
+    int grid;
+    double2* rho_hist;
+    StepStatsDev* stats_hist;
+    unsigned int* error;
+};
+
 // Device table layout (doubles): K4 re/im [2*P*P], ds[P], ss[P], eta [2*3*(K+1)]
 struct TableLayout {
     static constexpr size_t k4(int) { return 0; }
@@ -104,5 +139,6 @@ int launch_plan(const PlanArgs& a, void* stream);
 int chunk_heads(int P);
 int plan_max_buckets();              // bucket count the planner is built for
 int step_grid(int P, int n_cu, int per_cu);   // persistent workgroups that are co-resident
+int launch_sparse_step(const SparseArgs& a, void* stream);   // expand, resolve, compact, reduce
 
 }  // namespace quapi_dev

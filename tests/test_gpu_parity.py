@@ -182,6 +182,48 @@ def test_other_shapes(Q, eta_cache, make, mode, K, mask, theta, n):
     assert_groups(o, g)
 
 
+# ------------------------------------------------------------------ sparse MACGIC masks (hash-table merge)
+@pytest.mark.parametrize("make,mode,K,mask,theta,n", [
+    (W.structured_bath, "pre", 12, (0, 1, 2, 3, 4, 5, 8, 11), 1e-7, 30),
+    (W.structured_bath, "pre", 16, (0, 1, 2, 3, 4, 5, 6, 7, 11, 15), 1e-7, 25),
+    (W.structured_bath, "post", 8, (0, 1, 2, 5), 1e-6, 40),
+    (W.structured_bath, "pre", 6, (0, 1), 0.0, 20),
+    (W.three_level, "pre", 8, (0, 1, 2, 5, 7), 1e-7, 25),
+    # the structured bath with distant lags kept exact: ~1e6 groups by step 16
+    (W.structured_bath, "pre", 24, tuple(range(12)) + (15, 19, 23), 1e-8, 16),
+], ids=["K12-pre", "K16-pre", "K8-post", "K6-newest-only", "three-level-K8", "K24-tail-15-19-23"])
+def test_sparse_masks(Q, eta_cache, make, mode, K, mask, theta, n):
+    """Masks whose merge positions are not a contiguous run from 0: the children a
+    group receives are not neighbours in key order and merge through a hash table."""
+    wl = make(K=K)
+    eta = eta_cache(wl, K)
+    o, g = run_both(Q, wl.H, wl.q, wl.dt, K, eta, wl.rho0, n, mode=mode, mask=mask, theta=theta)
+    assert ambiguous(o, n) == 0
+    assert_rho(o, g, n)
+    assert_stats(o, g, n)
+    assert_groups(o, g)
+
+
+def test_sparse_mask_capacity_overflow(Q, eta_cache):
+    wl = W.structured_bath(K=10)
+    eta = eta_cache(wl, 10)
+    g = Q.Propagator(wl.H, wl.q, wl.dt, 10, eta, wl.rho0, mask=(0, 1, 2, 5), mode=Q.QUAPI_POST, max_groups=50)
+    g.step(12)
+    with pytest.raises(Q.QuapiError) as e:
+        g.sync()
+    assert e.value.code == Q.QUAPI_ENOMEM
+    t = Q.quapi_time(g.ctx)
+    o = oracle.Oracle(wl.H, wl.q, wl.dt, 10, eta, wl.rho0, mask=(0, 1, 2, 5), mode=oracle.POST)
+    o.step(t)
+    assert np.abs(Q.quapi_rho(g.ctx, t, 2) - o.rho(t)).max() < RHO_TOL
+    # after a reset the context runs again (two steps stay within 50 groups)
+    g.reset()
+    g.step(2)
+    o2 = oracle.Oracle(wl.H, wl.q, wl.dt, 10, eta, wl.rho0, mask=(0, 1, 2, 5), mode=oracle.POST)
+    o2.step(2)
+    assert np.abs(g.rho_history(0, 3) - o2.rho_history()).max() < RHO_TOL
+
+
 # ------------------------------------------------------------------ edge cases
 def test_determinism_and_reset(Q, eta_cache):
     wl = W.structured_bath(K=12)
