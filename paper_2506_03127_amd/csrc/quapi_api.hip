@@ -37,15 +37,15 @@ struct quapi_ctx {
     // sparse-mask path (merge positions not 0..L-1): hash-table merge
     bool sparse = false;
     std::vector<int> qpos;       // merge positions, most significant first
+    std::vector<int> npos;       // the other positions, oldest first
+    bool sp_packed = false;      // representative word holds the other positions
     long long sp_cap = 0;        // group capacity
     uint64_t* sp_h[2] = {nullptr, nullptr};
     double2* sp_w[2] = {nullptr, nullptr};
     unsigned int* sp_count = nullptr;            // [2] by step parity
-    unsigned long long* sp_tkey = nullptr;
-    unsigned long long* sp_tq = nullptr;
-    unsigned long long* sp_tT = nullptr;
-    double2* sp_tw = nullptr;
+    quapi_dev::SpSlot* sp_slot = nullptr;        // [sp_tsize] hash table
     unsigned long long sp_tsize = 0;
+    unsigned long long* sp_tT = nullptr;         // unpacked form only
     unsigned int* sp_cslot = nullptr;
     unsigned long long* sp_cT = nullptr;
     unsigned long long* sp_cq = nullptr;
@@ -130,10 +130,9 @@ int upload_initial_sparse(quapi_ctx* c) {
             e = hipMemcpyAsync(c->sp_w[0], c->init_w.data(), n0 * sizeof(double2), hipMemcpyHostToDevice, c->stream);
     }
     if (e == hipSuccess) e = hipMemcpyAsync(c->sp_count, cnt, sizeof cnt, hipMemcpyHostToDevice, c->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(c->sp_tkey, 0xff, ts * sizeof(unsigned long long), c->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(c->sp_tq, 0, ts * sizeof(unsigned long long), c->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(c->sp_tT, 0xff, ts * sizeof(unsigned long long), c->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(c->sp_tw, 0, ts * sizeof(double2), c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c->sp_slot, 0, ts * sizeof(quapi_dev::SpSlot), c->stream);
+    if (e == hipSuccess && c->sp_tT)
+        e = hipMemsetAsync(c->sp_tT, 0xff, ts * sizeof(unsigned long long), c->stream);
     // the copies read host vectors of this frame: complete them before returning
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     return hip_to_code(e);
@@ -252,11 +251,9 @@ bool is_finite_d(double x) { return std::isfinite(x); }
 int step_sparse(quapi_ctx* c, int n_steps) {
     quapi_dev::SparseArgs a;
     a.count = c->sp_count;
-    a.tkey = c->sp_tkey;
-    a.tq = c->sp_tq;
+    a.slot = c->sp_slot;
+    a.tsize = c->sp_tsize;
     a.tT = c->sp_tT;
-    a.tw = c->sp_tw;
-    a.tmask = c->sp_tsize - 1;
     a.cslot = c->sp_cslot;
     a.cT = c->sp_cT;
     a.cq = c->sp_cq;
@@ -264,10 +261,15 @@ int step_sparse(quapi_ctx* c, int n_steps) {
     a.P = c->P;
     a.K = c->K;
     a.theta2 = c->theta * c->theta;
-    a.qmask = c->qbits >= 64 ? 0ull : ~((1ull << c->qbits) - 1ull);
+    a.qbits = c->qbits;
+    a.packed = c->sp_packed ? 1 : 0;
     a.tables = c->d_tables;
     a.nq = (int)c->qpos.size();
-    for (int k = 0; k < quapi_dev::kMaxK; ++k) a.qpos[k] = k < a.nq ? c->qpos[k] : 0;
+    a.nn = (int)c->npos.size();
+    for (int k = 0; k < quapi_dev::kMaxK; ++k) {
+        a.qpos[k] = k < a.nq ? c->qpos[k] : 0;
+        a.npos[k] = k < a.nn ? c->npos[k] : 0;
+    }
     a.partials = c->sp_partials;
     a.grid = c->sp_grid;
     a.rho_hist = c->d_rho;
@@ -402,6 +404,13 @@ int quapi_create(const quapi_params* p, quapi_ctx** out) {
     c->theta = p->theta;
     c->sparse = !contiguous;
     c->qpos = pos;
+    if (c->sparse) {
+        // the other positions, oldest first; the representative word packs
+        // them below the quantised |w|^2 when they fit in its qbits+1 low bits
+        for (int j = K - 1; j >= 0; --j)
+            if (std::find(pos.begin(), pos.end(), j) == pos.end()) c->npos.push_back(j);
+        c->sp_packed = c->qbits <= 62 && (int)c->npos.size() * bits <= c->qbits + 1;
+    }
 
     // buckets: the top D points of the key, D-1 the most points with at most
     // max_super super-buckets (bounded by what the planner is built for); a
@@ -517,7 +526,7 @@ int quapi_create(const quapi_params* p, quapi_ctx** out) {
         long long scap = p->max_groups > 0 ? p->max_groups : std::min(ipow(P, std::min(L, 12)), 1ll << 21);
         scap = std::max((long long)c->init_pair.size(), std::min(scap, ((1ll << 31) - 1) / P));
         c->sp_cap = scap;
-        unsigned long long ts = 1024;
+        unsigned long long ts = quapi_dev::kMinTable;
         while (ts < 2ull * (unsigned long long)P * (unsigned long long)scap) ts <<= 1;
         c->sp_tsize = ts;
         for (int b = 0; b < 2 && !rc; ++b) {
@@ -525,13 +534,13 @@ int quapi_create(const quapi_params* p, quapi_ctx** out) {
             if (!rc) rc = dev_alloc(c, &c->sp_w[b], (size_t)scap);
         }
         if (!rc) rc = dev_alloc(c, &c->sp_count, 2);
-        if (!rc) rc = dev_alloc(c, &c->sp_tkey, (size_t)ts);
-        if (!rc) rc = dev_alloc(c, &c->sp_tq, (size_t)ts);
-        if (!rc) rc = dev_alloc(c, &c->sp_tT, (size_t)ts);
-        if (!rc) rc = dev_alloc(c, &c->sp_tw, (size_t)ts);
-        if (!rc) rc = dev_alloc(c, &c->sp_cslot, (size_t)scap * P);
-        if (!rc) rc = dev_alloc(c, &c->sp_cT, (size_t)scap * P);
-        if (!rc) rc = dev_alloc(c, &c->sp_cq, (size_t)scap * P);
+        if (!rc) rc = dev_alloc(c, &c->sp_slot, (size_t)ts);
+        if (!c->sp_packed) {
+            if (!rc) rc = dev_alloc(c, &c->sp_tT, (size_t)ts);
+            if (!rc) rc = dev_alloc(c, &c->sp_cslot, (size_t)scap * P);
+            if (!rc) rc = dev_alloc(c, &c->sp_cT, (size_t)scap * P);
+            if (!rc) rc = dev_alloc(c, &c->sp_cq, (size_t)scap * P);
+        }
     }
     c->hist_cap = p->max_steps > 0 ? p->max_steps : 1024;
     if (!rc) rc = dev_alloc(c, &c->d_rho, (size_t)(c->hist_cap + 1) * P);

@@ -92,7 +92,19 @@ struct PlanArgs {
 // the newest point lowest) in no particular order, merged through an
 // open-addressing hash table keyed on the gathered merge positions.
 constexpr int kSparseThreads = 256;
-constexpr unsigned long long kEmptyKey = ~0ull;
+constexpr unsigned long long kMinTable = 1024;   // smallest table a step uses (slots)
+
+// One hash-table slot.  key holds the merge key plus one, so that an all-zero
+// slot is free.  best is the largest "representative word" of the key's
+// children: in the packed form the quantised |w|^2 above the complement of the
+// child's points at the other positions (the largest word is then the largest
+// quantised |w|^2 and, among those, the smallest history); otherwise the
+// quantised |w|^2 alone, with the history settled by a second pass.
+struct __align__(32) SpSlot {
+    unsigned long long key;
+    unsigned long long best;
+    double wr, wi;                  // sum of the key's child weights
+};
 
 struct SparseArgs {
     const uint64_t* h_in;           // stored groups (state at t-1)
@@ -100,22 +112,23 @@ struct SparseArgs {
     uint64_t* h_out;                // groups after step t
     double2* w_out;
     unsigned int* count;            // [2] stored groups, by parity of the time step
-    unsigned long long* tkey;       // [table] merge key, kEmptyKey when free
-    unsigned long long* tq;         // [table] largest quantised |w|^2 of the key's children
-    unsigned long long* tT;         // [table] smallest history among those (the representative)
-    double2* tw;                    // [table] sum of the key's child weights
-    unsigned long long tmask;       // table size - 1 (a power of two)
-    unsigned int* cslot;            // [cap * P] table slot of each child, ~0u if filtered
-    unsigned long long* cT;         // [cap * P] its history
-    unsigned long long* cq;         // [cap * P] its quantised |w|^2
+    SpSlot* slot;                   // [tsize] the table, all zero between steps
+    unsigned long long tsize;       // allocated slots (a power of two >= kMinTable)
+    unsigned long long* tT;         // [tsize] unpacked form: smallest history of the best q, ~0 when free
+    unsigned int* cslot;            // [cap * P] unpacked form: table slot of each child, ~0u if filtered
+    unsigned long long* cT;         // [cap * P] unpacked form: its history
+    unsigned long long* cq;         // [cap * P] unpacked form: its quantised |w|^2
     long long cap;                  // group capacity
     int P, K, t;
     double theta2;
-    unsigned long long qmask;
+    int qbits;                      // low bits of |w|^2 cleared by the quantisation
+    int packed;                     // 1: representative word packs the other positions
     const double* tables;
     const double* coef;
     int nq;                         // merge positions, most significant first
+    int nn;                         // the other positions, oldest (most significant) first
     int qpos[kMaxK];
+    int npos[kMaxK];
     double* partials;               // [partial_stride(P)][grid] per expand workgroup
     int grid;
     double2* rho_hist;

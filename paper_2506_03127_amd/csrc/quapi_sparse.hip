@@ -6,23 +6,30 @@
 //
 // State between steps: groups as full histories (point j = lag j at bits
 // [BP*j, BP*j+BP), the newest point lowest) with their amplitudes, in no
-// particular order.  One step is four kernels:
+// particular order.  One step is three kernels (four in the unpacked form):
 //   expand  - extend every group by every pair: weight times the propagator
 //             element (eq. SysP) times the influence factor of the new point
 //             (eq. inf_fun); drop children below theta (Sec. 2.1); add the
 //             survivors to this workgroup's rho(t) sums with the end-point
 //             correction of the final point (Sec. 3.2.1); insert each
-//             survivor's merge key into the table, keep the key's largest
-//             quantised |w|^2 and add the weight to the key's sum (the group
-//             amplitude is the sum of all its members, Sec. 3.1.2);
-//   resolve - among the children of a key with its largest quantised |w|^2,
-//             keep the history that is smallest read from the oldest point
-//             (the representative; with the newest point in the low bits the
-//             packed history is that number);
-//   compact - write one group per used slot and clear the slot;
+//             survivor's merge key into the table, raise the slot's
+//             representative word to the child's and add the weight to the
+//             key's sum (the group amplitude is the sum of all its members,
+//             Sec. 3.1.2);
+//   resolve - unpacked form only: among the children of a key with its
+//             largest quantised |w|^2, keep the smallest history;
+//   compact - write one group per used slot, its history rebuilt from the key
+//             and the representative word, and clear the slot;
 //   reduce  - add up the workgroups' rho(t) and counters in workgroup order.
-// The weight sums of the table are atomic and so in no fixed order; rho(t) is
-// summed in a fixed order.
+// The representative is the child with the largest quantised |w|^2 and, among
+// those, the history that is smallest read from the oldest point.  Children
+// of one key agree at the merge positions, so that order is the order of
+// their points at the other positions, packed oldest first; when those fit
+// below the quantised |w|^2 in one 64-bit word a single atomic max selects the
+// representative (the packed form).
+// The table in use has the next power of two above twice the children of the
+// step, read from the stored count on the device.  The weight sums of the
+// table are atomic and so in no fixed order; rho(t) is summed in a fixed order.
 
 #include <hip/hip_runtime.h>
 
@@ -35,6 +42,8 @@ namespace {
 
 constexpr int kSpWaves = kSparseThreads / 64;
 constexpr int kMaxProbe = 1 << 16;
+constexpr int kRows = 8;                                  // table rows per compact tile
+constexpr unsigned long long kTile = (unsigned long long)kRows * kSparseThreads;
 
 // 64-bit finaliser of the SplitMix64 generator (Steele, Lea, Flood 2014), as
 // the hash of a merge key
@@ -44,6 +53,27 @@ __device__ inline unsigned long long mix64(unsigned long long z) {
     return z ^ (z >> 31);
 }
 
+// groups stored at t-1 (the step's input), bounded by the capacity
+__device__ inline unsigned long long groups_in(const SparseArgs& a) {
+    const unsigned long long stored = a.count[(a.t - 1) & 1];
+    return stored < (unsigned long long)a.cap ? stored : (unsigned long long)a.cap;
+}
+
+// slots in use this step, minus one: the next power of two at or above twice
+// the children, at least kMinTable and at most the allocation
+__device__ inline unsigned long long table_mask(const SparseArgs& a, unsigned long long n_in) {
+    const unsigned long long need = 2ull * (unsigned long long)a.P * n_in;
+    unsigned long long ts = kMinTable;
+    if (need > ts) ts = 1ull << (64 - __clzll(need - 1ull));
+    return (ts < a.tsize ? ts : a.tsize) - 1ull;
+}
+
+// low bits of the packed representative word: the complement of the points
+// at the other positions
+__device__ inline unsigned long long other_mask(const SparseArgs& a) {
+    return (1ull << (a.qbits + 1)) - 1ull;
+}
+
 template <int P, int BP>
 __global__ __launch_bounds__(kSparseThreads) void sparse_expand(const SparseArgs a) {
     constexpr int S = partial_stride(P);
@@ -51,12 +81,21 @@ __global__ __launch_bounds__(kSparseThreads) void sparse_expand(const SparseArgs
     __shared__ double k4re[P * P], k4im[P * P], ds[P], ss[P];
     __shared__ double cre[kMaxK + 1], cim[kMaxK + 1], dre[kMaxK + 1], dim[kMaxK + 1];
     __shared__ double wpart[kSpWaves][S];
-    __shared__ int qpos[kMaxK];
+    // for each merge (other) position, the shift of the parent's point that
+    // the child holds there; -1 for position 0, the new point
+    __shared__ int qsh[kMaxK], nsh[kMaxK];
     const int i = threadIdx.x;
     const int wave = i >> 6;
     const unsigned int lane = lane_id();
-    const int K = a.K, t = a.t, nq = a.nq;
-    if (i < nq) qpos[i] = a.qpos[i];
+    const int K = a.K, t = a.t, nq = a.nq, nn = a.nn;
+    if (i < nq) qsh[i] = a.qpos[i] == 0 ? -1 : BP * (a.qpos[i] - 1);
+    if (i < nn) nsh[i] = a.npos[i] == 0 ? -1 : BP * (a.npos[i] - 1);
+    // where the new point goes: its shift in the key, else in the other word
+    int kshift = -1, nshift = -1;
+    for (int k = 0; k < nq; ++k)
+        if (a.qpos[k] == 0) kshift = BP * (nq - 1 - k);
+    for (int k = 0; k < nn; ++k)
+        if (a.npos[k] == 0) nshift = BP * (nn - 1 - k);
 
     for (int k = i; k < P * P; k += kSparseThreads) {
         k4re[k] = a.tables[2 * k];
@@ -77,13 +116,17 @@ __global__ __launch_bounds__(kSparseThreads) void sparse_expand(const SparseArgs
 #pragma unroll
     for (int k = 0; k < S; ++k) acc[k] = 0.0;
     const bool failed = error_word(a.error) != 0u;
-    const unsigned int stored = a.count[(t - 1) & 1];
-    const unsigned int N = failed ? 0u : (stored < (unsigned long long)a.cap ? stored : (unsigned int)a.cap);
+    const unsigned long long n_in = groups_in(a);
+    const unsigned long long N = failed ? 0ull : n_in;
+    const unsigned long long tm = table_mask(a, n_in);
     const int dmax = t < K ? t : K;
     const unsigned long long kmask = K * BP >= 64 ? ~0ull : ((1ull << (K * BP)) - 1ull);
-    const unsigned int stride = gridDim.x * kSparseThreads;
+    const bool packed = a.packed != 0;
+    const unsigned long long omask = packed ? other_mask(a) : 0ull;
+    const unsigned long long qmask = ~((1ull << a.qbits) - 1ull);
+    const unsigned long long stride = (unsigned long long)gridDim.x * kSparseThreads;
 
-    for (unsigned int g = blockIdx.x * kSparseThreads + i; g < N; g += stride) {
+    for (unsigned long long g = (unsigned long long)blockIdx.x * kSparseThreads + i; g < N; g += stride) {
         const unsigned long long h = a.h_in[g];
         const double2 W = a.w_in[g];
         double A = 0.0, B = 0.0, Ac = 0.0, Bc = 0.0;
@@ -94,6 +137,17 @@ __global__ __launch_bounds__(kSparseThreads) void sparse_expand(const SparseArgs
             Ac = __builtin_fma(dre[d], ds[x], Ac);
             Bc = __builtin_fma(dim[d], ss[x], Bc);
         }
+        // the children's key and other points, but for the new point
+        unsigned long long kb = 0ull, nb = 0ull;
+        for (int k = 0; k < nq; ++k) {
+            const int sh = qsh[k];
+            kb = (kb << BP) | (sh < 0 ? 0ull : (h >> sh) & DM);
+        }
+        if (packed)
+            for (int k = 0; k < nn; ++k) {
+                const int sh = nsh[k];
+                nb = (nb << BP) | (sh < 0 ? 0ull : (h >> sh) & DM);
+            }
         const int h0 = (int)(h & DM);
 #pragma unroll
         for (int p = 0; p < P; ++p) {
@@ -117,40 +171,45 @@ __global__ __launch_bounds__(kSparseThreads) void sparse_expand(const SparseArgs
             const double wr = br * er - bi * ei;
             const double wi = br * ei + bi * er;
             const double n2 = norm2_nocontract(wr, wi);
-            const size_t ci = (size_t)g * P + p;
+            const unsigned long long ci = g * P + p;
             if (!((a.theta2 == 0.0) || !(n2 < a.theta2))) {
                 acc[2 * P] += sqrt(n2);
-                a.cslot[ci] = ~0u;
+                if (!packed) a.cslot[ci] = ~0u;
                 continue;
             }
             acc[2 * p] += wr * fr - wi * fi;
             acc[2 * p + 1] += wr * fi + wi * fr;
             acc[2 * P + 1] += 1.0;
-            const unsigned long long child = ((h << BP) | (unsigned long long)p) & kmask;
-            unsigned long long key = 0;
-            for (int k = 0; k < nq; ++k) key = (key << BP) | ((child >> (BP * qpos[k])) & DM);
-            unsigned long long slot = mix64(key) & a.tmask;
+            const unsigned long long key = kb | (kshift < 0 ? 0ull : (unsigned long long)p << kshift);
+            const unsigned long long kk = key + 1ull;     // stored form: zero is a free slot
+            unsigned long long s = mix64(key) & tm;
             bool placed = false;
             for (int probe = 0; probe < kMaxProbe; ++probe) {
-                const unsigned long long prev = atomicCAS(a.tkey + slot, kEmptyKey, key);
-                if (prev == kEmptyKey || prev == key) {
+                const unsigned long long prev = atomicCAS(&a.slot[s].key, 0ull, kk);
+                if (prev == 0ull || prev == kk) {
                     placed = true;
                     break;
                 }
-                slot = (slot + 1) & a.tmask;
+                s = (s + 1ull) & tm;
             }
             if (!placed) {
                 raise_error(a.error, t, kErrOverflow);
-                a.cslot[ci] = ~0u;
+                if (!packed) a.cslot[ci] = ~0u;
                 continue;
             }
-            const unsigned long long q = (unsigned long long)__double_as_longlong(n2) & a.qmask;
-            atomicMax(a.tq + slot, q);
-            atomicAdd(&a.tw[slot].x, wr);
-            atomicAdd(&a.tw[slot].y, wi);
-            a.cslot[ci] = (unsigned int)slot;
-            a.cT[ci] = child;   // point j at bits BP*j: as a number it reads from the oldest point
-            a.cq[ci] = q;
+            const unsigned long long n2b = (unsigned long long)__double_as_longlong(n2);
+            if (packed) {
+                const unsigned long long nk = nb | (nshift < 0 ? 0ull : (unsigned long long)p << nshift);
+                atomicMax(&a.slot[s].best, ((n2b >> a.qbits) << (a.qbits + 1)) | (omask ^ nk));
+            } else {
+                const unsigned long long q = n2b & qmask;
+                atomicMax(&a.slot[s].best, q);
+                a.cslot[ci] = (unsigned int)s;
+                a.cT[ci] = ((h << BP) | (unsigned long long)p) & kmask;   // reads from the oldest point
+                a.cq[ci] = q;
+            }
+            unsafeAtomicAdd(&a.slot[s].wr, wr);
+            unsafeAtomicAdd(&a.slot[s].wi, wi);
         }
     }
 
@@ -168,46 +227,93 @@ __global__ __launch_bounds__(kSparseThreads) void sparse_expand(const SparseArgs
     }
 }
 
+// unpacked form: the smallest history among the children with the key's
+// largest quantised |w|^2
 template <int P>
 __global__ __launch_bounds__(kSparseThreads) void sparse_resolve(const SparseArgs a) {
     if (error_word(a.error) != 0u) return;
-    const unsigned int stored = a.count[(a.t - 1) & 1];
-    const unsigned long long n =
-        (unsigned long long)(stored < (unsigned long long)a.cap ? stored : (unsigned int)a.cap) * P;
+    const unsigned long long n = groups_in(a) * P;
     for (unsigned long long ci = (unsigned long long)blockIdx.x * kSparseThreads + threadIdx.x; ci < n;
          ci += (unsigned long long)gridDim.x * kSparseThreads) {
-        const unsigned int slot = a.cslot[ci];
-        if (slot == ~0u) continue;
-        if (a.cq[ci] == a.tq[slot]) atomicMin(a.tT + slot, a.cT[ci]);
+        const unsigned int s = a.cslot[ci];
+        if (s == ~0u) continue;
+        if (a.cq[ci] == a.slot[s].best) atomicMin(a.tT + s, a.cT[ci]);
     }
 }
 
+// Tiles of kRows x kSparseThreads slots: each tile takes its place in the
+// output with one counter update and writes its used slots in slot order.
+template <int BP>
 __global__ __launch_bounds__(kSparseThreads) void sparse_compact(const SparseArgs a) {
+    constexpr unsigned long long DM = (1ull << BP) - 1;
+    __shared__ unsigned int wcnt[kRows][kSpWaves];
+    __shared__ unsigned int tile_base;
+    const int i = threadIdx.x;
+    const int wave = i >> 6;
     const bool failed = error_word(a.error) != 0u;
     const unsigned int lane = lane_id();
     unsigned int* const out_count = a.count + (a.t & 1);
-    for (unsigned long long s0 = (unsigned long long)blockIdx.x * kSparseThreads;; s0 += (unsigned long long)gridDim.x * kSparseThreads) {
-        if (s0 > a.tmask) break;                                   // uniform over the workgroup
-        const unsigned long long sl = s0 + threadIdx.x;
-        const bool used = sl <= a.tmask && a.tkey[sl] != kEmptyKey;
-        // one counter update per wave
-        const unsigned long long bal = __ballot(used);
-        unsigned int base = 0u;
-        if (lane == 0u && bal) base = atomicAdd(out_count, (unsigned int)__popcll(bal));
-        base = __shfl(base, 0, 64);
-        if (used) {
-            const unsigned int idx = base + rank_below(bal);
-            if (!failed && (long long)idx < a.cap) {
-                a.h_out[idx] = a.tT[sl];                      // the representative's history
-                a.w_out[idx] = a.tw[sl];
-            } else if (!failed) {
-                raise_error(a.error, a.t, kErrOverflow);
-            }
-            a.tkey[sl] = kEmptyKey;
-            a.tq[sl] = 0ull;
-            a.tT[sl] = ~0ull;
-            a.tw[sl] = make_double2(0.0, 0.0);
+    const unsigned long long tm = table_mask(a, groups_in(a));
+    const unsigned long long n_tiles = (tm + kTile) / kTile;
+    const bool packed = a.packed != 0;
+    const unsigned long long omask = packed ? other_mask(a) : 0ull;
+    const int nq = a.nq, nn = a.nn;
+    for (unsigned long long tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        const unsigned long long s0 = tile * kTile + (unsigned long long)i;
+        unsigned long long kk[kRows], bal[kRows];
+#pragma unroll
+        for (int r = 0; r < kRows; ++r) {
+            const unsigned long long sl = s0 + (unsigned long long)r * kSparseThreads;
+            kk[r] = sl <= tm ? a.slot[sl].key : 0ull;
+            bal[r] = __ballot(kk[r] != 0ull);
+            if (lane == 0u) wcnt[r][wave] = (unsigned int)__popcll(bal[r]);
         }
+        __syncthreads();
+        if (i == 0) {
+            unsigned int tot = 0u;
+            for (int r = 0; r < kRows; ++r)
+                for (int w = 0; w < kSpWaves; ++w) {
+                    const unsigned int c = wcnt[r][w];
+                    wcnt[r][w] = tot;
+                    tot += c;
+                }
+            tile_base = tot ? atomicAdd(out_count, tot) : 0u;
+        }
+        __syncthreads();
+        const unsigned int base = tile_base;
+#pragma unroll
+        for (int r = 0; r < kRows; ++r) {
+            if (kk[r] == 0ull) continue;
+            const unsigned long long sl = s0 + (unsigned long long)r * kSparseThreads;
+            const unsigned long long idx = (unsigned long long)base + wcnt[r][wave] + rank_below(bal[r]);
+            SpSlot* const e = a.slot + sl;
+            if (!failed && idx < (unsigned long long)a.cap) {
+                unsigned long long hist;
+                if (packed) {
+                    // the key's points at the merge positions, the representative's elsewhere
+                    const unsigned long long key = kk[r] - 1ull;
+                    const unsigned long long nk = (e->best & omask) ^ omask;
+                    hist = 0ull;
+                    for (int k = 0; k < nq; ++k)
+                        hist |= ((key >> (BP * (nq - 1 - k))) & DM) << (BP * a.qpos[k]);
+                    for (int k = 0; k < nn; ++k)
+                        hist |= ((nk >> (BP * (nn - 1 - k))) & DM) << (BP * a.npos[k]);
+                } else {
+                    hist = a.tT[sl];
+                    a.tT[sl] = ~0ull;
+                }
+                a.h_out[idx] = hist;
+                a.w_out[idx] = make_double2(e->wr, e->wi);
+            } else {
+                if (!failed) raise_error(a.error, a.t, kErrOverflow);
+                if (!packed) a.tT[sl] = ~0ull;
+            }
+            e->key = 0ull;
+            e->best = 0ull;
+            e->wr = 0.0;
+            e->wi = 0.0;
+        }
+        __syncthreads();   // wcnt and tile_base are rewritten by the next tile
     }
 }
 
@@ -266,14 +372,14 @@ int launch_sparse_step(const SparseArgs& a, void* stream) {
     switch (a.P) {
         case 4:
             hipLaunchKernelGGL((sparse_expand<4, 2>), dim3(g), dim3(kSparseThreads), 0, st, a);
-            hipLaunchKernelGGL((sparse_resolve<4>), dim3(g), dim3(kSparseThreads), 0, st, a);
-            hipLaunchKernelGGL(sparse_compact, dim3(g), dim3(kSparseThreads), 0, st, a);
+            if (!a.packed) hipLaunchKernelGGL((sparse_resolve<4>), dim3(g), dim3(kSparseThreads), 0, st, a);
+            hipLaunchKernelGGL((sparse_compact<2>), dim3(g), dim3(kSparseThreads), 0, st, a);
             hipLaunchKernelGGL((sparse_reduce<4>), dim3(1), dim3(kSparseThreads), 0, st, a);
             break;
         case 9:
             hipLaunchKernelGGL((sparse_expand<9, 4>), dim3(g), dim3(kSparseThreads), 0, st, a);
-            hipLaunchKernelGGL((sparse_resolve<9>), dim3(g), dim3(kSparseThreads), 0, st, a);
-            hipLaunchKernelGGL(sparse_compact, dim3(g), dim3(kSparseThreads), 0, st, a);
+            if (!a.packed) hipLaunchKernelGGL((sparse_resolve<9>), dim3(g), dim3(kSparseThreads), 0, st, a);
+            hipLaunchKernelGGL((sparse_compact<4>), dim3(g), dim3(kSparseThreads), 0, st, a);
             hipLaunchKernelGGL((sparse_reduce<9>), dim3(1), dim3(kSparseThreads), 0, st, a);
             break;
         default:

@@ -191,7 +191,15 @@ def test_other_shapes(Q, eta_cache, make, mode, K, mask, theta, n):
     (W.three_level, "pre", 8, (0, 1, 2, 5, 7), 1e-7, 25),
     # the structured bath with distant lags kept exact: ~1e6 groups by step 16
     (W.structured_bath, "pre", 24, tuple(range(12)) + (15, 19, 23), 1e-8, 16),
-], ids=["K12-pre", "K16-pre", "K8-post", "K6-newest-only", "three-level-K8", "K24-tail-15-19-23"])
+    # 16 other points (32 bits): the representative word's last packed form
+    (W.structured_bath, "pre", 24, (0, 1, 2, 3, 4, 5, 6, 7, 23), 1e-7, 26),
+    # 17 other points (34 bits) and 9 three-level ones (36 bits): the unpacked
+    # form, representative settled in a second pass
+    (W.structured_bath, "pre", 24, (0, 1, 2, 3, 4, 5, 6, 23), 1e-7, 26),
+    (W.structured_bath, "pre", 20, (0, 1, 2, 3), 1e-8, 30),
+    (W.three_level, "pre", 12, (0, 1, 2, 3), 1e-7, 25),
+], ids=["K12-pre", "K16-pre", "K8-post", "K6-newest-only", "three-level-K8", "K24-tail-15-19-23",
+        "K24-packed-32bit", "K24-unpacked-34bit", "K20-unpacked-first4", "three-level-K12-unpacked"])
 def test_sparse_masks(Q, eta_cache, make, mode, K, mask, theta, n):
     """Masks whose merge positions are not a contiguous run from 0: the children a
     group receives are not neighbours in key order and merge through a hash table."""
