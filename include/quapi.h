@@ -69,8 +69,9 @@ typedef struct {
     const int* mask;          /* MACGIC mask (Sec. 2.1): n_mask sorted lags, mask[0]=0, mask[1]=1,      */
                               /* mask[n_mask-1] <= K-1; NULL: every lag 0..K-1.  Merge positions       */
                               /* 0..L-1 (L >= 2) run on the bucketed store; any other set merges       */
-                              /* through a hash table and needs the whole history in 64 bits           */
-                              /* (K <= 32 for M = 2, K <= 16 for M = 3)                                 */
+                              /* through a hash table and needs the history in 128 bits, the merge     */
+                              /* positions in 62 and the other positions in 64 (M = 2: K <= 63,        */
+                              /* at most 31 merge and 32 other positions; M = 3: half of each)          */
     int n_mask;
     double theta;             /* filter: drop a child when |w|^2 < theta^2; 0 disables                  */
     const quapi_c64* rho0;    /* M*M initial reduced density matrix                                     */
@@ -101,7 +102,7 @@ typedef struct {
     int M, P, K, L;           /* P = M*M pairs; L = key length in points (merge positions 0..L-1)     */
     int bits_per_point;       /* history bits per point                                                 */
     int record_bytes;         /* bytes of one stored group: 8 key + 8 history tail + 16 weight (32),    */
-                              /* or 8 history + 16 weight (24) on the hash-table merge                  */
+                              /* or 8 or 16 history + 16 weight (24 or 32) on the hash-table merge      */
     long long capacity;       /* maximum number of stored groups                                        */
     size_t device_bytes;      /* device memory held by the context                                      */
 } quapi_info_t;
@@ -110,7 +111,8 @@ typedef struct {
  * element of rho0, weighted by the initial point's self term).
  * Errors: EINVAL (bad argument), EUNSUPPORTED (M > 3; merge positions 0..L-1
  * with L bits-per-point > 62 bits or a tail over 64 bits; other merge positions
- * with a history over 64 bits), ENOMEM, EDEVICE.  *out is NULL on error. */
+ * with a history over 128 bits, a key over 62 bits or other positions over 64
+ * bits), ENOMEM, EDEVICE.  *out is NULL on error. */
 int quapi_create(const quapi_params* p, quapi_ctx** out);
 
 /* Enqueue n_steps time steps on the context's stream; returns without waiting.

@@ -39,15 +39,16 @@ struct quapi_ctx {
     std::vector<int> qpos;       // merge positions, most significant first
     std::vector<int> npos;       // the other positions, oldest first
     bool sp_packed = false;      // representative word holds the other positions
+    int sp_hw = 1;               // 64-bit words per stored history
     long long sp_cap = 0;        // group capacity
     uint64_t* sp_h[2] = {nullptr, nullptr};
     double2* sp_w[2] = {nullptr, nullptr};
     unsigned int* sp_count = nullptr;            // [2] by step parity
     quapi_dev::SpSlot* sp_slot = nullptr;        // [sp_tsize] hash table
     unsigned long long sp_tsize = 0;
-    unsigned long long* sp_tT = nullptr;         // unpacked form only
+    unsigned long long* sp_tN = nullptr;         // unpacked form only
     unsigned int* sp_cslot = nullptr;
-    unsigned long long* sp_cT = nullptr;
+    unsigned long long* sp_cN = nullptr;
     unsigned long long* sp_cq = nullptr;
     double* sp_partials = nullptr;
     int sp_grid = 0;
@@ -119,20 +120,21 @@ int launch_planner(quapi_ctx* c, int t);
 
 int upload_initial_sparse(quapi_ctx* c) {
     const size_t n0 = c->init_pair.size();
-    std::vector<uint64_t> h(n0);
-    for (size_t k = 0; k < n0; ++k) h[k] = (uint64_t)c->init_pair[k];
+    const size_t hw = (size_t)c->sp_hw;
+    std::vector<uint64_t> h(n0 * hw, 0ull);
+    for (size_t k = 0; k < n0; ++k) h[k * hw] = (uint64_t)c->init_pair[k];
     const unsigned int cnt[2] = {(unsigned int)n0, 0u};
     const size_t ts = (size_t)c->sp_tsize;
     hipError_t e = hipSuccess;
     if (n0) {
-        e = hipMemcpyAsync(c->sp_h[0], h.data(), n0 * sizeof(uint64_t), hipMemcpyHostToDevice, c->stream);
+        e = hipMemcpyAsync(c->sp_h[0], h.data(), h.size() * sizeof(uint64_t), hipMemcpyHostToDevice, c->stream);
         if (e == hipSuccess)
             e = hipMemcpyAsync(c->sp_w[0], c->init_w.data(), n0 * sizeof(double2), hipMemcpyHostToDevice, c->stream);
     }
     if (e == hipSuccess) e = hipMemcpyAsync(c->sp_count, cnt, sizeof cnt, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(c->sp_slot, 0, ts * sizeof(quapi_dev::SpSlot), c->stream);
-    if (e == hipSuccess && c->sp_tT)
-        e = hipMemsetAsync(c->sp_tT, 0xff, ts * sizeof(unsigned long long), c->stream);
+    if (e == hipSuccess && c->sp_tN)
+        e = hipMemsetAsync(c->sp_tN, 0xff, ts * sizeof(unsigned long long), c->stream);
     // the copies read host vectors of this frame: complete them before returning
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     return hip_to_code(e);
@@ -253,9 +255,10 @@ int step_sparse(quapi_ctx* c, int n_steps) {
     a.count = c->sp_count;
     a.slot = c->sp_slot;
     a.tsize = c->sp_tsize;
-    a.tT = c->sp_tT;
+    a.tN = c->sp_tN;
+    a.hw = c->sp_hw;
     a.cslot = c->sp_cslot;
-    a.cT = c->sp_cT;
+    a.cN = c->sp_cN;
     a.cq = c->sp_cq;
     a.cap = c->sp_cap;
     a.P = c->P;
@@ -378,7 +381,8 @@ int quapi_create(const quapi_params* p, quapi_ctx** out) {
         pos = mask;
     }
     // merge positions 0..L-1 (L >= 2) take the bucketed path; any other set the
-    // hash-table path, which keeps each history in one 64-bit word
+    // hash-table path, which keeps each history in one or two 64-bit words, the
+    // key in 62 bits and the points at the other positions in one 64-bit word
     bool contiguous = pos.size() >= 2;
     for (size_t i = 0; i < pos.size(); ++i)
         if (pos[i] != (int)i) contiguous = false;
@@ -388,7 +392,7 @@ int quapi_create(const quapi_params* p, quapi_ctx** out) {
     if (contiguous) {
         if (L * bits > 62 || (K - L) * bits > 64) return QUAPI_EUNSUPPORTED;
     } else {
-        if (K * bits > 64 || L * bits > 62) return QUAPI_EUNSUPPORTED;
+        if (K * bits > 128 || L * bits > 62 || (K - L) * bits > 64) return QUAPI_EUNSUPPORTED;
     }
 
     quapi_ctx* c = new (std::nothrow) quapi_ctx();
@@ -410,6 +414,7 @@ int quapi_create(const quapi_params* p, quapi_ctx** out) {
         for (int j = K - 1; j >= 0; --j)
             if (std::find(pos.begin(), pos.end(), j) == pos.end()) c->npos.push_back(j);
         c->sp_packed = c->qbits <= 62 && (int)c->npos.size() * bits <= c->qbits + 1;
+        c->sp_hw = K * bits <= 64 ? 1 : 2;
     }
 
     // buckets: the top D points of the key, D-1 the most points with at most
@@ -530,15 +535,15 @@ int quapi_create(const quapi_params* p, quapi_ctx** out) {
         while (ts < 2ull * (unsigned long long)P * (unsigned long long)scap) ts <<= 1;
         c->sp_tsize = ts;
         for (int b = 0; b < 2 && !rc; ++b) {
-            rc = dev_alloc(c, &c->sp_h[b], (size_t)scap);
+            rc = dev_alloc(c, &c->sp_h[b], (size_t)scap * c->sp_hw);
             if (!rc) rc = dev_alloc(c, &c->sp_w[b], (size_t)scap);
         }
         if (!rc) rc = dev_alloc(c, &c->sp_count, 2);
         if (!rc) rc = dev_alloc(c, &c->sp_slot, (size_t)ts);
         if (!c->sp_packed) {
-            if (!rc) rc = dev_alloc(c, &c->sp_tT, (size_t)ts);
+            if (!rc) rc = dev_alloc(c, &c->sp_tN, (size_t)ts);
             if (!rc) rc = dev_alloc(c, &c->sp_cslot, (size_t)scap * P);
-            if (!rc) rc = dev_alloc(c, &c->sp_cT, (size_t)scap * P);
+            if (!rc) rc = dev_alloc(c, &c->sp_cN, (size_t)scap * P);
             if (!rc) rc = dev_alloc(c, &c->sp_cq, (size_t)scap * P);
         }
     }
@@ -703,15 +708,19 @@ int quapi_groups(quapi_ctx* c, long long cap, unsigned char* hist, quapi_c64* w,
         const long long n = cnt2[c->t & 1];
         *n_out = n;
         if (cap == 0 || n == 0) return QUAPI_OK;
-        std::vector<uint64_t> hh((size_t)n);
+        const int hw = c->sp_hw;
+        std::vector<uint64_t> hh((size_t)n * hw);
         std::vector<double2> ww((size_t)n);
-        e = hipMemcpy(hh.data(), c->sp_h[c->cur], (size_t)n * 8, hipMemcpyDeviceToHost);
+        e = hipMemcpy(hh.data(), c->sp_h[c->cur], hh.size() * 8, hipMemcpyDeviceToHost);
         if (e == hipSuccess) e = hipMemcpy(ww.data(), c->sp_w[c->cur], (size_t)n * 16, hipMemcpyDeviceToHost);
         if (e != hipSuccess) return hip_to_code(e);
         const unsigned long long dm = (1ull << c->bits) - 1;
         for (long long r = 0; r < n && r < cap; ++r) {
             unsigned char* row = hist + (size_t)r * c->K;
-            for (int j = 0; j < c->K; ++j) row[j] = (unsigned char)((hh[r] >> (c->bits * j)) & dm);
+            for (int j = 0; j < c->K; ++j) {
+                const int bit = c->bits * j;
+                row[j] = (unsigned char)((hh[(size_t)r * hw + bit / 64] >> (bit % 64)) & dm);
+            }
             w[r].re = ww[r].x;
             w[r].im = ww[r].y;
         }
@@ -765,7 +774,7 @@ int quapi_info(quapi_ctx* c, quapi_info_t* out) {
     out->K = c->K;
     out->L = c->L;
     out->bits_per_point = c->bits;
-    out->record_bytes = c->sparse ? 24 : 32;
+    out->record_bytes = c->sparse ? 16 + 8 * c->sp_hw : 32;
     out->capacity = c->sparse ? c->sp_cap : c->n_buckets * c->cap;
     out->device_bytes = c->device_bytes;
     return QUAPI_OK;

@@ -88,8 +88,9 @@ struct PlanArgs {
     const unsigned int* error;
 };
 
-// Sparse-mask path: groups as full histories (point j at bits [BP*j, BP*j+BP),
-// the newest point lowest) in no particular order, merged through an
+// Sparse-mask path: groups as full histories of one or two 64-bit words
+// (point j at bits [BP*j, BP*j+BP) of the number, the newest point lowest) in
+// no particular order, merged through an
 // open-addressing hash table keyed on the gathered merge positions.
 constexpr int kSparseThreads = 256;
 constexpr unsigned long long kMinTable = 1024;   // smallest table a step uses (slots)
@@ -107,16 +108,17 @@ struct __align__(32) SpSlot {
 };
 
 struct SparseArgs {
-    const uint64_t* h_in;           // stored groups (state at t-1)
+    const uint64_t* h_in;           // [cap * hw] stored groups (state at t-1)
     const double2* w_in;
-    uint64_t* h_out;                // groups after step t
+    uint64_t* h_out;                // [cap * hw] groups after step t
     double2* w_out;
+    int hw;                         // 64-bit words per history (1 or 2)
     unsigned int* count;            // [2] stored groups, by parity of the time step
     SpSlot* slot;                   // [tsize] the table, all zero between steps
     unsigned long long tsize;       // allocated slots (a power of two >= kMinTable)
-    unsigned long long* tT;         // [tsize] unpacked form: smallest history of the best q, ~0 when free
+    unsigned long long* tN;         // [tsize] unpacked form: smallest other points at the best q, ~0 when free
     unsigned int* cslot;            // [cap * P] unpacked form: table slot of each child, ~0u if filtered
-    unsigned long long* cT;         // [cap * P] unpacked form: its history
+    unsigned long long* cN;         // [cap * P] unpacked form: its points at the other positions
     unsigned long long* cq;         // [cap * P] unpacked form: its quantised |w|^2
     long long cap;                  // group capacity
     int P, K, t;
@@ -135,6 +137,7 @@ struct SparseArgs {
     StepStatsDev* stats_hist;
     unsigned int* error;
 };
+
 
 // Device table layout (doubles): K4 re/im [2*P*P], ds[P], ss[P], eta [2*3*(K+1)]
 struct TableLayout {

@@ -74,15 +74,39 @@ __device__ inline unsigned long long other_mask(const SparseArgs& a) {
     return (1ull << (a.qbits + 1)) - 1ull;
 }
 
-template <int P, int BP>
+// A history of W 64-bit words: point j at bit BP*j of the W*64-bit number
+// (word j*BP/64), the newest point lowest.  BP divides 64, so no point
+// straddles two words.
+template <int W>
+struct Hist {
+    unsigned long long w[W];
+};
+
+template <int BP, int W>
+__device__ inline unsigned long long point_at(const Hist<W>& h, int bit) {
+    constexpr unsigned long long DM = (1ull << BP) - 1;
+    if (W == 1) return (h.w[0] >> bit) & DM;
+    const unsigned long long word = (bit >> 6) == 0 ? h.w[0] : h.w[W - 1];
+    return (word >> (bit & 63)) & DM;
+}
+
+template <int W>
+__device__ inline Hist<W> load_hist(const uint64_t* p, unsigned long long g) {
+    Hist<W> h;
+#pragma unroll
+    for (int k = 0; k < W; ++k) h.w[k] = p[g * W + k];
+    return h;
+}
+
+template <int P, int BP, int W>
 __global__ __launch_bounds__(kSparseThreads) void sparse_expand(const SparseArgs a) {
     constexpr int S = partial_stride(P);
     constexpr unsigned long long DM = (1ull << BP) - 1;
     __shared__ double k4re[P * P], k4im[P * P], ds[P], ss[P];
     __shared__ double cre[kMaxK + 1], cim[kMaxK + 1], dre[kMaxK + 1], dim[kMaxK + 1];
     __shared__ double wpart[kSpWaves][S];
-    // for each merge (other) position, the shift of the parent's point that
-    // the child holds there; -1 for position 0, the new point
+    // for each merge (other) position, the bit of the parent's point that the
+    // child holds there; -1 for position 0, the new point
     __shared__ int qsh[kMaxK], nsh[kMaxK];
     const int i = threadIdx.x;
     const int wave = i >> 6;
@@ -120,18 +144,17 @@ __global__ __launch_bounds__(kSparseThreads) void sparse_expand(const SparseArgs
     const unsigned long long N = failed ? 0ull : n_in;
     const unsigned long long tm = table_mask(a, n_in);
     const int dmax = t < K ? t : K;
-    const unsigned long long kmask = K * BP >= 64 ? ~0ull : ((1ull << (K * BP)) - 1ull);
     const bool packed = a.packed != 0;
     const unsigned long long omask = packed ? other_mask(a) : 0ull;
     const unsigned long long qmask = ~((1ull << a.qbits) - 1ull);
     const unsigned long long stride = (unsigned long long)gridDim.x * kSparseThreads;
 
     for (unsigned long long g = (unsigned long long)blockIdx.x * kSparseThreads + i; g < N; g += stride) {
-        const unsigned long long h = a.h_in[g];
-        const double2 W = a.w_in[g];
+        const Hist<W> h = load_hist<W>(a.h_in, g);
+        const double2 Wt = a.w_in[g];
         double A = 0.0, B = 0.0, Ac = 0.0, Bc = 0.0;
         for (int d = 1; d <= dmax; ++d) {
-            const unsigned int x = (unsigned int)((h >> (BP * (d - 1))) & DM);
+            const unsigned int x = (unsigned int)point_at<BP, W>(h, BP * (d - 1));
             A = __builtin_fma(cre[d], ds[x], A);
             B = __builtin_fma(cim[d], ss[x], B);
             Ac = __builtin_fma(dre[d], ds[x], Ac);
@@ -141,14 +164,13 @@ __global__ __launch_bounds__(kSparseThreads) void sparse_expand(const SparseArgs
         unsigned long long kb = 0ull, nb = 0ull;
         for (int k = 0; k < nq; ++k) {
             const int sh = qsh[k];
-            kb = (kb << BP) | (sh < 0 ? 0ull : (h >> sh) & DM);
+            kb = (kb << BP) | (sh < 0 ? 0ull : point_at<BP, W>(h, sh));
         }
-        if (packed)
-            for (int k = 0; k < nn; ++k) {
-                const int sh = nsh[k];
-                nb = (nb << BP) | (sh < 0 ? 0ull : (h >> sh) & DM);
-            }
-        const int h0 = (int)(h & DM);
+        for (int k = 0; k < nn; ++k) {
+            const int sh = nsh[k];
+            nb = (nb << BP) | (sh < 0 ? 0ull : point_at<BP, W>(h, sh));
+        }
+        const int h0 = (int)(h.w[0] & DM);
 #pragma unroll
         for (int p = 0; p < P; ++p) {
             double er = 1.0, ei = 0.0, fr = 1.0, fi = 0.0;
@@ -166,8 +188,8 @@ __global__ __launch_bounds__(kSparseThreads) void sparse_expand(const SparseArgs
                 fi = f * fs;
             }
             const double k4r = k4re[p * P + h0], k4i = k4im[p * P + h0];
-            const double br = W.x * k4r - W.y * k4i;
-            const double bi = W.x * k4i + W.y * k4r;
+            const double br = Wt.x * k4r - Wt.y * k4i;
+            const double bi = Wt.x * k4i + Wt.y * k4r;
             const double wr = br * er - bi * ei;
             const double wi = br * ei + bi * er;
             const double n2 = norm2_nocontract(wr, wi);
@@ -198,14 +220,14 @@ __global__ __launch_bounds__(kSparseThreads) void sparse_expand(const SparseArgs
                 continue;
             }
             const unsigned long long n2b = (unsigned long long)__double_as_longlong(n2);
+            const unsigned long long nk = nb | (nshift < 0 ? 0ull : (unsigned long long)p << nshift);
             if (packed) {
-                const unsigned long long nk = nb | (nshift < 0 ? 0ull : (unsigned long long)p << nshift);
                 atomicMax(&a.slot[s].best, ((n2b >> a.qbits) << (a.qbits + 1)) | (omask ^ nk));
             } else {
                 const unsigned long long q = n2b & qmask;
                 atomicMax(&a.slot[s].best, q);
                 a.cslot[ci] = (unsigned int)s;
-                a.cT[ci] = ((h << BP) | (unsigned long long)p) & kmask;   // reads from the oldest point
+                a.cN[ci] = nk;
                 a.cq[ci] = q;
             }
             unsafeAtomicAdd(&a.slot[s].wr, wr);
@@ -227,8 +249,8 @@ __global__ __launch_bounds__(kSparseThreads) void sparse_expand(const SparseArgs
     }
 }
 
-// unpacked form: the smallest history among the children with the key's
-// largest quantised |w|^2
+// unpacked form: among the children with the key's largest quantised |w|^2,
+// the smallest points at the other positions (oldest first)
 template <int P>
 __global__ __launch_bounds__(kSparseThreads) void sparse_resolve(const SparseArgs a) {
     if (error_word(a.error) != 0u) return;
@@ -237,13 +259,13 @@ __global__ __launch_bounds__(kSparseThreads) void sparse_resolve(const SparseArg
          ci += (unsigned long long)gridDim.x * kSparseThreads) {
         const unsigned int s = a.cslot[ci];
         if (s == ~0u) continue;
-        if (a.cq[ci] == a.slot[s].best) atomicMin(a.tT + s, a.cT[ci]);
+        if (a.cq[ci] == a.slot[s].best) atomicMin(a.tN + s, a.cN[ci]);
     }
 }
 
 // Tiles of kRows x kSparseThreads slots: each tile takes its place in the
 // output with one counter update and writes its used slots in slot order.
-template <int BP>
+template <int BP, int W>
 __global__ __launch_bounds__(kSparseThreads) void sparse_compact(const SparseArgs a) {
     constexpr unsigned long long DM = (1ull << BP) - 1;
     __shared__ unsigned int wcnt[kRows][kSpWaves];
@@ -287,26 +309,36 @@ __global__ __launch_bounds__(kSparseThreads) void sparse_compact(const SparseArg
             const unsigned long long sl = s0 + (unsigned long long)r * kSparseThreads;
             const unsigned long long idx = (unsigned long long)base + wcnt[r][wave] + rank_below(bal[r]);
             SpSlot* const e = a.slot + sl;
-            if (!failed && idx < (unsigned long long)a.cap) {
-                unsigned long long hist;
-                if (packed) {
-                    // the key's points at the merge positions, the representative's elsewhere
-                    const unsigned long long key = kk[r] - 1ull;
-                    const unsigned long long nk = (e->best & omask) ^ omask;
-                    hist = 0ull;
-                    for (int k = 0; k < nq; ++k)
-                        hist |= ((key >> (BP * (nq - 1 - k))) & DM) << (BP * a.qpos[k]);
-                    for (int k = 0; k < nn; ++k)
-                        hist |= ((nk >> (BP * (nn - 1 - k))) & DM) << (BP * a.npos[k]);
-                } else {
-                    hist = a.tT[sl];
-                    a.tT[sl] = ~0ull;
-                }
-                a.h_out[idx] = hist;
-                a.w_out[idx] = make_double2(e->wr, e->wi);
+            unsigned long long nk = 0ull;
+            if (packed) {
+                nk = (e->best & omask) ^ omask;
             } else {
-                if (!failed) raise_error(a.error, a.t, kErrOverflow);
-                if (!packed) a.tT[sl] = ~0ull;
+                nk = a.tN[sl];
+                a.tN[sl] = ~0ull;
+            }
+            if (!failed && idx < (unsigned long long)a.cap) {
+                // the key's points at the merge positions, the representative's elsewhere
+                const unsigned long long key = kk[r] - 1ull;
+                Hist<W> hist;
+#pragma unroll
+                for (int w = 0; w < W; ++w) hist.w[w] = 0ull;
+                for (int k = 0; k < nq; ++k) {
+                    const int bit = BP * a.qpos[k];
+                    const unsigned long long pt = (key >> (BP * (nq - 1 - k))) & DM;
+                    if (W == 1 || bit < 64) hist.w[0] |= pt << (bit & 63);
+                    else hist.w[W - 1] |= pt << (bit & 63);
+                }
+                for (int k = 0; k < nn; ++k) {
+                    const int bit = BP * a.npos[k];
+                    const unsigned long long pt = (nk >> (BP * (nn - 1 - k))) & DM;
+                    if (W == 1 || bit < 64) hist.w[0] |= pt << (bit & 63);
+                    else hist.w[W - 1] |= pt << (bit & 63);
+                }
+#pragma unroll
+                for (int w = 0; w < W; ++w) a.h_out[idx * W + w] = hist.w[w];
+                a.w_out[idx] = make_double2(e->wr, e->wi);
+            } else if (!failed) {
+                raise_error(a.error, a.t, kErrOverflow);
             }
             e->key = 0ull;
             e->best = 0ull;
@@ -366,25 +398,22 @@ __global__ __launch_bounds__(kSparseThreads) void sparse_reduce(const SparseArgs
 
 }  // namespace
 
+template <int P, int BP, int W>
+void launch_sparse(const SparseArgs& a, hipStream_t st) {
+    const int g = a.grid;
+    hipLaunchKernelGGL((sparse_expand<P, BP, W>), dim3(g), dim3(kSparseThreads), 0, st, a);
+    if (!a.packed) hipLaunchKernelGGL((sparse_resolve<P>), dim3(g), dim3(kSparseThreads), 0, st, a);
+    hipLaunchKernelGGL((sparse_compact<BP, W>), dim3(g), dim3(kSparseThreads), 0, st, a);
+    hipLaunchKernelGGL((sparse_reduce<P>), dim3(1), dim3(kSparseThreads), 0, st, a);
+}
+
 int launch_sparse_step(const SparseArgs& a, void* stream) {
     hipStream_t st = (hipStream_t)stream;
-    const int g = a.grid;
-    switch (a.P) {
-        case 4:
-            hipLaunchKernelGGL((sparse_expand<4, 2>), dim3(g), dim3(kSparseThreads), 0, st, a);
-            if (!a.packed) hipLaunchKernelGGL((sparse_resolve<4>), dim3(g), dim3(kSparseThreads), 0, st, a);
-            hipLaunchKernelGGL((sparse_compact<2>), dim3(g), dim3(kSparseThreads), 0, st, a);
-            hipLaunchKernelGGL((sparse_reduce<4>), dim3(1), dim3(kSparseThreads), 0, st, a);
-            break;
-        case 9:
-            hipLaunchKernelGGL((sparse_expand<9, 4>), dim3(g), dim3(kSparseThreads), 0, st, a);
-            if (!a.packed) hipLaunchKernelGGL((sparse_resolve<9>), dim3(g), dim3(kSparseThreads), 0, st, a);
-            hipLaunchKernelGGL((sparse_compact<4>), dim3(g), dim3(kSparseThreads), 0, st, a);
-            hipLaunchKernelGGL((sparse_reduce<9>), dim3(1), dim3(kSparseThreads), 0, st, a);
-            break;
-        default:
-            return (int)hipErrorInvalidValue;
-    }
+    if (a.P == 4 && a.hw == 1) launch_sparse<4, 2, 1>(a, st);
+    else if (a.P == 4 && a.hw == 2) launch_sparse<4, 2, 2>(a, st);
+    else if (a.P == 9 && a.hw == 1) launch_sparse<9, 4, 1>(a, st);
+    else if (a.P == 9 && a.hw == 2) launch_sparse<9, 4, 2>(a, st);
+    else return (int)hipErrorInvalidValue;
     return (int)hipGetLastError();
 }
 

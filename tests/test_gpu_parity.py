@@ -212,6 +212,30 @@ def test_sparse_masks(Q, eta_cache, make, mode, K, mask, theta, n):
     assert_groups(o, g)
 
 
+@pytest.mark.parametrize("make,K,mask,theta,n", [
+    # the long-memory mask: lags 0..11 exact, 16, 24 and 32 kept (80-bit
+    # histories, 26 other points: the representative in a second pass)
+    (W.structured_bath, 40, tuple(range(12)) + (16, 24, 32), 1e-9, 12),
+    # 32 other points: their word at its 64-bit limit
+    (W.structured_bath, 40, (0, 1, 2, 3, 4, 5, 20, 30, 39), 1e-8, 30),
+    # 16 other points: the packed representative word with two-word histories
+    (W.structured_bath, 40, tuple(range(24)) + (39,), 1e-5, 26),
+    # three-level, 96-bit histories, unpacked and packed
+    (W.three_level, 24, (0, 1, 2, 3, 4, 5, 6, 7, 12, 23), 1e-7, 13),
+    (W.three_level, 20, tuple(range(13)) + (19,), 1e-5, 16),
+], ids=["K40-lags-16-24-32", "K40-other-64bit", "K40-packed", "three-level-K24", "three-level-K20-packed"])
+def test_sparse_long_histories(Q, eta_cache, make, K, mask, theta, n):
+    """Hash-table merge with histories longer than one 64-bit word."""
+    wl = make(K=K)
+    eta = eta_cache(wl, K)
+    o, g = run_both(Q, wl.H, wl.q, wl.dt, K, eta, wl.rho0, n, mode="pre", mask=mask, theta=theta)
+    assert Q.quapi_info(g.ctx)["record_bytes"] == 32
+    assert ambiguous(o, n) == 0
+    assert_rho(o, g, n)
+    assert_stats(o, g, n)
+    assert_groups(o, g)
+
+
 def test_sparse_mask_capacity_overflow(Q, eta_cache):
     wl = W.structured_bath(K=10)
     eta = eta_cache(wl, 10)

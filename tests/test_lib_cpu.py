@@ -90,9 +90,12 @@ def test_create_rejects_invalid_input_without_device(Q):
     eta_nan = np.zeros((3, 9), dtype=complex)
     eta_nan[0, 3] = np.nan
     assert _create_code(Q, eta=eta_nan) == Q.QUAPI_EINVAL
-    # valid but outside this build: merge positions that are not 0..L-1 with a history
-    # longer than one 64-bit word (40 two-bit points), M = 4
+    # valid but outside this build: merge positions that are not 0..L-1 with more
+    # other points than one 64-bit word holds (38 two-bit points), a key over 62
+    # bits (32 two-bit merge positions), M = 4
     assert _create_code(Q, dk_max=40, eta=np.zeros((3, 41)), mask=[0, 1, 3]) == Q.QUAPI_EUNSUPPORTED
+    mask64 = list(range(31)) + [40, 63]
+    assert _create_code(Q, dk_max=64, eta=np.zeros((3, 65)), mask=mask64) == Q.QUAPI_EUNSUPPORTED
     H4 = W.random_hermitian(4, 0.5, 1)
     assert _create_code(Q, H=H4, q=[1, 0.5, -0.5, -1], rho0=W.ground_projector(4)) == Q.QUAPI_EUNSUPPORTED
 
