@@ -49,6 +49,15 @@ typedef struct { double re, im; } quapi_c64;
 #define QUAPI_PRE   0           /* pre-merging (Sec. 3.1): merge on {mask[i]-1 : i>=1} before extending */
 #define QUAPI_POST  1           /* post-merging (Sec. 2.1): merge the children on the mask              */
 
+#define QUAPI_FP64      0       /* amplitudes and influence exponents in FP64                           */
+#define QUAPI_FP32_LOG  1       /* precision form: stored amplitudes as FP32 (ln|w|, arg w); each       */
+                                /* child's influence exponent (eq. inf_fun) and amplitude formed in     */
+                                /* FP32 in that log domain; the merge sums (Sec. 3.1.2), the eta table  */
+                                /* and the rho(t) sums stay FP64.  Every mask takes the hash-table      */
+                                /* merge in this form.  Results differ from the FP64 form by the FP32   */
+                                /* rounding of each child, and the filter and representative decisions */
+                                /* near their thresholds may differ too                                 */
+
 typedef struct quapi_ctx quapi_ctx;
 
 /* Problem definition, copied by quapi_create (the caller keeps ownership of
@@ -79,12 +88,14 @@ typedef struct {
     int qbits;                /* representative choice compares |w|^2 = re*re + im*im (no fused         */
                               /* multiply-add) with its low qbits mantissa bits cleared; equal values    */
                               /* go to the history that is smaller read from the oldest point.          */
-                              /* < 0: default 32                                                        */
+                              /* < 0: default 32, or 40 in the FP32 precision form (whose rounding of    */
+                              /* |w|^2, ~1e-6 relative, must stay well below the compared quantum)      */
     long long max_groups;     /* stored groups to allocate for, spread evenly over the key buckets     */
                               /* (at least one each; an uneven fill reports ENOMEM first); 0: room   */
                               /* for every key of the merge positions (hash-table merge: up to 2^21) */
     int max_steps;            /* initial capacity of the rho(t) history; grows on demand; <= 0: 1024    */
     void* stream;             /* hipStream_t to run on (e.g. a torch stream); NULL: a library stream   */
+    int precision;            /* QUAPI_FP64 (0) or QUAPI_FP32_LOG                                       */
 } quapi_params;
 
 /* Per-step counters, available for every step t >= 1 that has completed. */
@@ -102,9 +113,12 @@ typedef struct {
     int M, P, K, L;           /* P = M*M pairs; L = key length in points (merge positions 0..L-1)     */
     int bits_per_point;       /* history bits per point                                                 */
     int record_bytes;         /* bytes of one stored group: 8 key + 8 history tail + 16 weight (32),    */
-                              /* or 8 or 16 history + 16 weight (24 or 32) on the hash-table merge      */
+                              /* or 8 or 16 history + 16 weight (24 or 32) on the hash-table merge,     */
+                              /* with an 8-byte weight in the FP32 precision form                       */
     long long capacity;       /* maximum number of stored groups                                        */
     size_t device_bytes;      /* device memory held by the context                                      */
+    int precision;            /* QUAPI_FP64 or QUAPI_FP32_LOG                                           */
+    int hash_merge;           /* 1: the hash-table merge, 0: the bucketed store                         */
 } quapi_info_t;
 
 /* Create a context and its initial state t = 0 (one path per nonzero

@@ -40,6 +40,8 @@ struct quapi_ctx {
     std::vector<int> npos;       // the other positions, oldest first
     bool sp_packed = false;      // representative word holds the other positions
     int sp_hw = 1;               // 64-bit words per stored history
+    bool f32 = false;            // FP32 precision form: amplitudes as FP32 (ln|w|, arg w)
+    float2* sp_wf[2] = {nullptr, nullptr};
     long long sp_cap = 0;        // group capacity
     uint64_t* sp_h[2] = {nullptr, nullptr};
     double2* sp_w[2] = {nullptr, nullptr};
@@ -126,9 +128,17 @@ int upload_initial_sparse(quapi_ctx* c) {
     const unsigned int cnt[2] = {(unsigned int)n0, 0u};
     const size_t ts = (size_t)c->sp_tsize;
     hipError_t e = hipSuccess;
+    // the FP32 precision form stores (ln|w|, arg w)
+    std::vector<float2> wl(c->f32 ? n0 : 0);
+    for (size_t k = 0; k < wl.size(); ++k) {
+        const double re = c->init_w[k].x, im = c->init_w[k].y;
+        wl[k] = make_float2((float)(0.5 * std::log(re * re + im * im)), (float)std::atan2(im, re));
+    }
     if (n0) {
         e = hipMemcpyAsync(c->sp_h[0], h.data(), h.size() * sizeof(uint64_t), hipMemcpyHostToDevice, c->stream);
-        if (e == hipSuccess)
+        if (e == hipSuccess && c->f32)
+            e = hipMemcpyAsync(c->sp_wf[0], wl.data(), n0 * sizeof(float2), hipMemcpyHostToDevice, c->stream);
+        else if (e == hipSuccess)
             e = hipMemcpyAsync(c->sp_w[0], c->init_w.data(), n0 * sizeof(double2), hipMemcpyHostToDevice, c->stream);
     }
     if (e == hipSuccess) e = hipMemcpyAsync(c->sp_count, cnt, sizeof cnt, hipMemcpyHostToDevice, c->stream);
@@ -283,8 +293,10 @@ int step_sparse(quapi_ctx* c, int n_steps) {
         const int t = c->t + 1;
         a.h_in = c->sp_h[c->cur];
         a.w_in = c->sp_w[c->cur];
+        a.wf_in = c->sp_wf[c->cur];
         a.h_out = c->sp_h[1 - c->cur];
         a.w_out = c->sp_w[1 - c->cur];
+        a.wf_out = c->sp_wf[1 - c->cur];
         a.t = t;
         a.coef = c->d_coef + (size_t)(std::min(t, c->K + 1) - 1) * 4 * n;
         hipEvent_t* ev = (c->prof_on && c->prof_n < c->prof_cap) ? &c->prof_ev[3 * (size_t)c->prof_n++] : nullptr;
@@ -352,6 +364,7 @@ int quapi_create(const quapi_params* p, quapi_ctx** out) {
     if (M < 2 || K < 1 || K > quapi_dev::kMaxK || !(p->dt > 0) || !is_finite_d(p->dt)) return QUAPI_EINVAL;
     if (!(p->theta >= 0) || !is_finite_d(p->theta)) return QUAPI_EINVAL;
     if (p->mode != QUAPI_PRE && p->mode != QUAPI_POST) return QUAPI_EINVAL;
+    if (p->precision != QUAPI_FP64 && p->precision != QUAPI_FP32_LOG) return QUAPI_EINVAL;
     if (M > 3) return QUAPI_EUNSUPPORTED;
     if (!quapi_host::hermitian_ok(M, (const double*)p->H)) return QUAPI_EINVAL;
     for (int i = 0; i < M; ++i)
@@ -383,7 +396,8 @@ int quapi_create(const quapi_params* p, quapi_ctx** out) {
     // merge positions 0..L-1 (L >= 2) take the bucketed path; any other set the
     // hash-table path, which keeps each history in one or two 64-bit words, the
     // key in 62 bits and the points at the other positions in one 64-bit word
-    bool contiguous = pos.size() >= 2;
+    // (the FP32 precision form is built on the hash-table merge only)
+    bool contiguous = pos.size() >= 2 && p->precision == QUAPI_FP64;
     for (size_t i = 0; i < pos.size(); ++i)
         if (pos[i] != (int)i) contiguous = false;
     const int L = (int)pos.size();
@@ -403,10 +417,13 @@ int quapi_create(const quapi_params* p, quapi_ctx** out) {
     c->L = L;
     c->bits = bits;
     c->mode = p->mode;
-    c->qbits = p->qbits < 0 ? 32 : std::min(p->qbits, 63);
+    // the FP32 form's rounding of |w|^2 (~1e-6 relative) would split values the
+    // FP64 form sees as equal across 2^-20 quanta: it compares 12 mantissa bits
+    c->qbits = p->qbits < 0 ? (p->precision == QUAPI_FP32_LOG ? 40 : 32) : std::min(p->qbits, 63);
     c->dt = p->dt;
     c->theta = p->theta;
     c->sparse = !contiguous;
+    c->f32 = p->precision == QUAPI_FP32_LOG;
     c->qpos = pos;
     if (c->sparse) {
         // the other positions, oldest first; the representative word packs
@@ -536,7 +553,8 @@ int quapi_create(const quapi_params* p, quapi_ctx** out) {
         c->sp_tsize = ts;
         for (int b = 0; b < 2 && !rc; ++b) {
             rc = dev_alloc(c, &c->sp_h[b], (size_t)scap * c->sp_hw);
-            if (!rc) rc = dev_alloc(c, &c->sp_w[b], (size_t)scap);
+            if (!rc && c->f32) rc = dev_alloc(c, &c->sp_wf[b], (size_t)scap);
+            if (!rc && !c->f32) rc = dev_alloc(c, &c->sp_w[b], (size_t)scap);
         }
         if (!rc) rc = dev_alloc(c, &c->sp_count, 2);
         if (!rc) rc = dev_alloc(c, &c->sp_slot, (size_t)ts);
@@ -712,7 +730,16 @@ int quapi_groups(quapi_ctx* c, long long cap, unsigned char* hist, quapi_c64* w,
         std::vector<uint64_t> hh((size_t)n * hw);
         std::vector<double2> ww((size_t)n);
         e = hipMemcpy(hh.data(), c->sp_h[c->cur], hh.size() * 8, hipMemcpyDeviceToHost);
-        if (e == hipSuccess) e = hipMemcpy(ww.data(), c->sp_w[c->cur], (size_t)n * 16, hipMemcpyDeviceToHost);
+        if (e == hipSuccess && c->f32) {
+            std::vector<float2> wl((size_t)n);
+            e = hipMemcpy(wl.data(), c->sp_wf[c->cur], (size_t)n * sizeof(float2), hipMemcpyDeviceToHost);
+            for (long long r = 0; r < n; ++r) {
+                const double m = std::exp((double)wl[r].x);
+                ww[r] = make_double2(m * std::cos((double)wl[r].y), m * std::sin((double)wl[r].y));
+            }
+        } else if (e == hipSuccess) {
+            e = hipMemcpy(ww.data(), c->sp_w[c->cur], (size_t)n * 16, hipMemcpyDeviceToHost);
+        }
         if (e != hipSuccess) return hip_to_code(e);
         const unsigned long long dm = (1ull << c->bits) - 1;
         for (long long r = 0; r < n && r < cap; ++r) {
@@ -774,9 +801,11 @@ int quapi_info(quapi_ctx* c, quapi_info_t* out) {
     out->K = c->K;
     out->L = c->L;
     out->bits_per_point = c->bits;
-    out->record_bytes = c->sparse ? 16 + 8 * c->sp_hw : 32;
+    out->record_bytes = c->sparse ? (c->f32 ? 8 : 16) + 8 * c->sp_hw : 32;
     out->capacity = c->sparse ? c->sp_cap : c->n_buckets * c->cap;
     out->device_bytes = c->device_bytes;
+    out->precision = c->f32 ? QUAPI_FP32_LOG : QUAPI_FP64;
+    out->hash_merge = c->sparse ? 1 : 0;
     return QUAPI_OK;
 }
 

@@ -109,9 +109,11 @@ struct __align__(32) SpSlot {
 
 struct SparseArgs {
     const uint64_t* h_in;           // [cap * hw] stored groups (state at t-1)
-    const double2* w_in;
+    const double2* w_in;            // FP64 form: amplitudes
     uint64_t* h_out;                // [cap * hw] groups after step t
     double2* w_out;
+    const float2* wf_in;            // FP32 precision form: (ln|w|, arg w)
+    float2* wf_out;
     int hw;                         // 64-bit words per history (1 or 2)
     unsigned int* count;            // [2] stored groups, by parity of the time step
     SpSlot* slot;                   // [tsize] the table, all zero between steps

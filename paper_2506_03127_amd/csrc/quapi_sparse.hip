@@ -98,12 +98,20 @@ __device__ inline Hist<W> load_hist(const uint64_t* p, unsigned long long g) {
     return h;
 }
 
-template <int P, int BP, int W>
+// F32: the precision form.  A group's amplitude is read as (ln|w|, arg w) in
+// FP32; each child adds ln K4 and its influence exponent in FP32, leaves the
+// log domain with FP32 exp and sin/cos, and enters the filter, the merge sums
+// and rho(t) in FP64.
+template <int P, int BP, int W, bool F32>
 __global__ __launch_bounds__(kSparseThreads) void sparse_expand(const SparseArgs a) {
     constexpr int S = partial_stride(P);
     constexpr unsigned long long DM = (1ull << BP) - 1;
     __shared__ double k4re[P * P], k4im[P * P], ds[P], ss[P];
     __shared__ double cre[kMaxK + 1], cim[kMaxK + 1], dre[kMaxK + 1], dim[kMaxK + 1];
+    // FP32 precision form: ln|K4|, arg K4 and the exponent tables in FP32
+    __shared__ float lk4[F32 ? P * P : 1], ak4[F32 ? P * P : 1], dsf[F32 ? P : 1], ssf[F32 ? P : 1];
+    __shared__ float cref[F32 ? kMaxK + 1 : 1], cimf[F32 ? kMaxK + 1 : 1];
+    __shared__ float dref[F32 ? kMaxK + 1 : 1], dimf[F32 ? kMaxK + 1 : 1];
     __shared__ double wpart[kSpWaves][S];
     // for each merge (other) position, the bit of the parent's point that the
     // child holds there; -1 for position 0, the new point
@@ -133,6 +141,21 @@ __global__ __launch_bounds__(kSparseThreads) void sparse_expand(const SparseArgs
         const int r = k / (K + 1), d = k - r * (K + 1);
         double* dst = r == 0 ? cre : r == 1 ? cim : r == 2 ? dre : dim;
         dst[d] = a.coef[k];
+        if (F32) {
+            float* dstf = r == 0 ? cref : r == 1 ? cimf : r == 2 ? dref : dimf;
+            dstf[d] = (float)a.coef[k];
+        }
+    }
+    if (F32) {
+        for (int k = i; k < P * P; k += kSparseThreads) {
+            const double re = a.tables[2 * k], im = a.tables[2 * k + 1];
+            lk4[k] = (float)(0.5 * log(re * re + im * im));
+            ak4[k] = (float)atan2(im, re);
+        }
+        if (i < P) {
+            dsf[i] = (float)a.tables[TableLayout::ds(P) + i];
+            ssf[i] = (float)a.tables[TableLayout::ss(P) + i];
+        }
     }
     __syncthreads();
 
@@ -151,14 +174,25 @@ __global__ __launch_bounds__(kSparseThreads) void sparse_expand(const SparseArgs
 
     for (unsigned long long g = (unsigned long long)blockIdx.x * kSparseThreads + i; g < N; g += stride) {
         const Hist<W> h = load_hist<W>(a.h_in, g);
-        const double2 Wt = a.w_in[g];
+        double2 Wt = make_double2(0.0, 0.0);
+        float2 Wl = make_float2(0.0f, 0.0f);
+        if (F32) Wl = a.wf_in[g];
+        else Wt = a.w_in[g];
         double A = 0.0, B = 0.0, Ac = 0.0, Bc = 0.0;
+        float Af = 0.0f, Bf = 0.0f, Acf = 0.0f, Bcf = 0.0f;
         for (int d = 1; d <= dmax; ++d) {
             const unsigned int x = (unsigned int)point_at<BP, W>(h, BP * (d - 1));
-            A = __builtin_fma(cre[d], ds[x], A);
-            B = __builtin_fma(cim[d], ss[x], B);
-            Ac = __builtin_fma(dre[d], ds[x], Ac);
-            Bc = __builtin_fma(dim[d], ss[x], Bc);
+            if (F32) {
+                Af = __builtin_fmaf(cref[d], dsf[x], Af);
+                Bf = __builtin_fmaf(cimf[d], ssf[x], Bf);
+                Acf = __builtin_fmaf(dref[d], dsf[x], Acf);
+                Bcf = __builtin_fmaf(dimf[d], ssf[x], Bcf);
+            } else {
+                A = __builtin_fma(cre[d], ds[x], A);
+                B = __builtin_fma(cim[d], ss[x], B);
+                Ac = __builtin_fma(dre[d], ds[x], Ac);
+                Bc = __builtin_fma(dim[d], ss[x], Bc);
+            }
         }
         // the children's key and other points, but for the new point
         unsigned long long kb = 0ull, nb = 0ull;
@@ -173,25 +207,48 @@ __global__ __launch_bounds__(kSparseThreads) void sparse_expand(const SparseArgs
         const int h0 = (int)(h.w[0] & DM);
 #pragma unroll
         for (int p = 0; p < P; ++p) {
-            double er = 1.0, ei = 0.0, fr = 1.0, fi = 0.0;
-            const double dsp = ds[p], ssp = ss[p];
-            if (dsp != 0.0) {
-                const double e = exp(-dsp * (cre[0] * dsp + A));
-                double sn, cs;
-                sincos(-dsp * (cim[0] * ssp + B), &sn, &cs);
-                er = e * cs;
-                ei = e * sn;
-                const double f = exp(-dsp * (dre[0] * dsp + Ac));
-                double fs, fc;
-                sincos(-dsp * (dim[0] * ssp + Bc), &fs, &fc);
-                fr = f * fc;
-                fi = f * fs;
+            double wr, wi, rr, ri;   // the child's amplitude; its rho(t) term
+            if (F32) {
+                float lr = Wl.x + lk4[p * P + h0], ph = Wl.y + ak4[p * P + h0];
+                float lc = lr, pc = ph;
+                const float dsp = dsf[p], ssp = ssf[p];
+                if (dsp != 0.0f) {
+                    lr += -dsp * (cref[0] * dsp + Af);
+                    ph += -dsp * (cimf[0] * ssp + Bf);
+                    lc = lr - dsp * (dref[0] * dsp + Acf);
+                    pc = ph - dsp * (dimf[0] * ssp + Bcf);
+                }
+                const float m = expf(lr), mc = expf(lc);
+                float sn, cs, snc, csc;
+                sincosf(ph, &sn, &cs);
+                sincosf(pc, &snc, &csc);
+                wr = (double)(m * cs);
+                wi = (double)(m * sn);
+                rr = (double)(mc * csc);
+                ri = (double)(mc * snc);
+            } else {
+                double er = 1.0, ei = 0.0, fr = 1.0, fi = 0.0;
+                const double dsp = ds[p], ssp = ss[p];
+                if (dsp != 0.0) {
+                    const double e = exp(-dsp * (cre[0] * dsp + A));
+                    double sn, cs;
+                    sincos(-dsp * (cim[0] * ssp + B), &sn, &cs);
+                    er = e * cs;
+                    ei = e * sn;
+                    const double f = exp(-dsp * (dre[0] * dsp + Ac));
+                    double fs, fc;
+                    sincos(-dsp * (dim[0] * ssp + Bc), &fs, &fc);
+                    fr = f * fc;
+                    fi = f * fs;
+                }
+                const double k4r = k4re[p * P + h0], k4i = k4im[p * P + h0];
+                const double br = Wt.x * k4r - Wt.y * k4i;
+                const double bi = Wt.x * k4i + Wt.y * k4r;
+                wr = br * er - bi * ei;
+                wi = br * ei + bi * er;
+                rr = wr * fr - wi * fi;
+                ri = wr * fi + wi * fr;
             }
-            const double k4r = k4re[p * P + h0], k4i = k4im[p * P + h0];
-            const double br = Wt.x * k4r - Wt.y * k4i;
-            const double bi = Wt.x * k4i + Wt.y * k4r;
-            const double wr = br * er - bi * ei;
-            const double wi = br * ei + bi * er;
             const double n2 = norm2_nocontract(wr, wi);
             const unsigned long long ci = g * P + p;
             if (!((a.theta2 == 0.0) || !(n2 < a.theta2))) {
@@ -199,8 +256,8 @@ __global__ __launch_bounds__(kSparseThreads) void sparse_expand(const SparseArgs
                 if (!packed) a.cslot[ci] = ~0u;
                 continue;
             }
-            acc[2 * p] += wr * fr - wi * fi;
-            acc[2 * p + 1] += wr * fi + wi * fr;
+            acc[2 * p] += rr;
+            acc[2 * p + 1] += ri;
             acc[2 * P + 1] += 1.0;
             const unsigned long long key = kb | (kshift < 0 ? 0ull : (unsigned long long)p << kshift);
             const unsigned long long kk = key + 1ull;     // stored form: zero is a free slot
@@ -249,6 +306,13 @@ __global__ __launch_bounds__(kSparseThreads) void sparse_expand(const SparseArgs
     }
 }
 
+// The FP64 sum w of a group back to FP32 (ln|w|, arg w): FP64 log and atan2,
+// rounded once.  Not inlined, so that the unrolled rows of the compact loop do
+// not each hold the registers of the two functions.
+__device__ __noinline__ float2 to_log_domain(double wr, double wi) {
+    return make_float2((float)(0.5 * log(norm2_nocontract(wr, wi))), (float)atan2(wi, wr));
+}
+
 // unpacked form: among the children with the key's largest quantised |w|^2,
 // the smallest points at the other positions (oldest first)
 template <int P>
@@ -265,7 +329,7 @@ __global__ __launch_bounds__(kSparseThreads) void sparse_resolve(const SparseArg
 
 // Tiles of kRows x kSparseThreads slots: each tile takes its place in the
 // output with one counter update and writes its used slots in slot order.
-template <int BP, int W>
+template <int BP, int W, bool F32>
 __global__ __launch_bounds__(kSparseThreads) void sparse_compact(const SparseArgs a) {
     constexpr unsigned long long DM = (1ull << BP) - 1;
     __shared__ unsigned int wcnt[kRows][kSpWaves];
@@ -336,7 +400,11 @@ __global__ __launch_bounds__(kSparseThreads) void sparse_compact(const SparseArg
                 }
 #pragma unroll
                 for (int w = 0; w < W; ++w) a.h_out[idx * W + w] = hist.w[w];
-                a.w_out[idx] = make_double2(e->wr, e->wi);
+                if (F32) {
+                    a.wf_out[idx] = to_log_domain(e->wr, e->wi);
+                } else {
+                    a.w_out[idx] = make_double2(e->wr, e->wi);
+                }
             } else if (!failed) {
                 raise_error(a.error, a.t, kErrOverflow);
             }
@@ -398,23 +466,28 @@ __global__ __launch_bounds__(kSparseThreads) void sparse_reduce(const SparseArgs
 
 }  // namespace
 
-template <int P, int BP, int W>
+template <int P, int BP, int W, bool F32>
 void launch_sparse(const SparseArgs& a, hipStream_t st) {
     const int g = a.grid;
-    hipLaunchKernelGGL((sparse_expand<P, BP, W>), dim3(g), dim3(kSparseThreads), 0, st, a);
+    hipLaunchKernelGGL((sparse_expand<P, BP, W, F32>), dim3(g), dim3(kSparseThreads), 0, st, a);
     if (!a.packed) hipLaunchKernelGGL((sparse_resolve<P>), dim3(g), dim3(kSparseThreads), 0, st, a);
-    hipLaunchKernelGGL((sparse_compact<BP, W>), dim3(g), dim3(kSparseThreads), 0, st, a);
+    hipLaunchKernelGGL((sparse_compact<BP, W, F32>), dim3(g), dim3(kSparseThreads), 0, st, a);
     hipLaunchKernelGGL((sparse_reduce<P>), dim3(1), dim3(kSparseThreads), 0, st, a);
+}
+
+template <bool F32>
+int launch_sparse_form(const SparseArgs& a, hipStream_t st) {
+    if (a.P == 4 && a.hw == 1) launch_sparse<4, 2, 1, F32>(a, st);
+    else if (a.P == 4 && a.hw == 2) launch_sparse<4, 2, 2, F32>(a, st);
+    else if (a.P == 9 && a.hw == 1) launch_sparse<9, 4, 1, F32>(a, st);
+    else if (a.P == 9 && a.hw == 2) launch_sparse<9, 4, 2, F32>(a, st);
+    else return (int)hipErrorInvalidValue;
+    return (int)hipGetLastError();
 }
 
 int launch_sparse_step(const SparseArgs& a, void* stream) {
     hipStream_t st = (hipStream_t)stream;
-    if (a.P == 4 && a.hw == 1) launch_sparse<4, 2, 1>(a, st);
-    else if (a.P == 4 && a.hw == 2) launch_sparse<4, 2, 2>(a, st);
-    else if (a.P == 9 && a.hw == 1) launch_sparse<9, 4, 1>(a, st);
-    else if (a.P == 9 && a.hw == 2) launch_sparse<9, 4, 2>(a, st);
-    else return (int)hipErrorInvalidValue;
-    return (int)hipGetLastError();
+    return a.wf_in ? launch_sparse_form<true>(a, st) : launch_sparse_form<false>(a, st);
 }
 
 }  // namespace quapi_dev

@@ -25,6 +25,8 @@ QUAPI_ESTATE = -4
 QUAPI_EUNSUPPORTED = -5
 QUAPI_PRE = 0
 QUAPI_POST = 1
+QUAPI_FP64 = 0
+QUAPI_FP32_LOG = 1
 
 
 class c64(ctypes.Structure):
@@ -37,7 +39,7 @@ class quapi_params(ctypes.Structure):
                 ("mask", ctypes.c_void_p), ("n_mask", ctypes.c_int), ("theta", ctypes.c_double),
                 ("rho0", ctypes.c_void_p), ("mode", ctypes.c_int), ("qbits", ctypes.c_int),
                 ("max_groups", ctypes.c_longlong), ("max_steps", ctypes.c_int),
-                ("stream", ctypes.c_void_p)]
+                ("stream", ctypes.c_void_p), ("precision", ctypes.c_int)]
 
 
 class quapi_stepstat_t(ctypes.Structure):
@@ -49,7 +51,8 @@ class quapi_stepstat_t(ctypes.Structure):
 class quapi_info_t(ctypes.Structure):
     _fields_ = [("M", ctypes.c_int), ("P", ctypes.c_int), ("K", ctypes.c_int), ("L", ctypes.c_int),
                 ("bits_per_point", ctypes.c_int), ("record_bytes", ctypes.c_int),
-                ("capacity", ctypes.c_longlong), ("device_bytes", ctypes.c_size_t)]
+                ("capacity", ctypes.c_longlong), ("device_bytes", ctypes.c_size_t),
+                ("precision", ctypes.c_int), ("hash_merge", ctypes.c_int)]
 
 
 class quapi_bath(ctypes.Structure):
@@ -121,7 +124,7 @@ def _c128(a, shape=None):
 
 # ------------------------------------------------------------------ C ABI, one to one
 def quapi_create(H, q, dt, dk_max, eta, rho0, mask=None, theta=0.0, mode=QUAPI_PRE, qbits=-1,
-                 max_groups=0, max_steps=0, stream=None) -> int:
+                 max_groups=0, max_steps=0, stream=None, precision=QUAPI_FP64) -> int:
     H = _c128(H)
     M = H.shape[0]
     q = np.ascontiguousarray(np.asarray(q, dtype=np.float64))
@@ -144,6 +147,7 @@ def quapi_create(H, q, dt, dk_max, eta, rho0, mask=None, theta=0.0, mode=QUAPI_P
     p.max_groups = int(max_groups)
     p.max_steps = int(max_steps)
     p.stream = None if stream is None else int(stream)
+    p.precision = int(precision)
     h = ctypes.c_void_p()
     _check(lib().quapi_create(ctypes.byref(p), ctypes.byref(h)), "quapi_create")
     return h.value

@@ -1,0 +1,104 @@
+"""The FP32 precision form (QUAPI_FP32_LOG) against the FP64 oracle.
+
+The form stores each group amplitude as FP32 (ln|w|, arg w) and forms each
+child's influence exponent and amplitude in FP32; the merge sums, eta and the
+rho(t) sums stay FP64.  It is not bit-exact: each child carries FP32 rounding
+(relative ~1e-7, times |ln|w|| for the magnitude), and the filter and
+representative decisions that sit within that rounding of their thresholds may
+go the other way.  The form therefore compares 12 mantissa bits of |w|^2 by
+default (qbits = 40): with the FP64 form's 20 (qbits = 32), values that tie
+exactly split across quanta under FP32 rounding and change the representative.
+The reference here is the oracle at the same qbits.  The bar is 1e-5 absolute
+on every rho(t) element, the target the precision form is built to; the
+measured error of each case is printed.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2506_03127_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FP32_RHO_TOL = 1e-5
+FP32_QBITS = 40
+
+
+@pytest.fixture(scope="module")
+def Q():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2506_03127_amd import quapi
+    quapi.lib()
+    return quapi
+
+
+@pytest.mark.parametrize("make,mode,K,mask,theta,n", [
+    # the plain method: no mask, no filter
+    (lambda K: W.spin_boson_ohmic(), "pre", 8, None, 0.0, 100),
+    # contiguous masks (the FP64 form runs these on the bucketed store)
+    (W.structured_bath, "pre", 12, tuple(range(6)), 1e-7, 60),
+    (W.structured_bath, "post", 10, tuple(range(5)), 1e-7, 40),
+    # masks that keep distant lags, one- and two-word histories
+    (W.structured_bath, "pre", 24, tuple(range(12)) + (15, 19, 23), 1e-8, 16),
+    (W.structured_bath, "pre", 40, tuple(range(12)) + (16, 24, 32), 1e-9, 12),
+    (W.three_level, "pre", 8, (0, 1, 2, 5, 7), 1e-7, 25),
+], ids=["spin-boson-K8", "structured-K12-E6", "structured-K10-post", "K24-tail", "K40-lags-16-24-32",
+        "three-level-K8"])
+def test_fp32_form_against_oracle(Q, eta_cache, make, mode, K, mask, theta, n):
+    wl = make(K=K)
+    eta = eta_cache(wl, K)
+    mo = oracle.PRE if mode == "pre" else oracle.POST
+    mq = Q.QUAPI_PRE if mode == "pre" else Q.QUAPI_POST
+    print(f"[fp32] M={wl.H.shape[0]} K={K} mode={mode} mask={mask} theta={theta} n={n}", flush=True)
+    o = oracle.Oracle(wl.H, wl.q, wl.dt, K, eta, wl.rho0, mask=mask, theta=theta, mode=mo,
+                      qbits=FP32_QBITS)
+    g = Q.Propagator(wl.H, wl.q, wl.dt, K, eta, wl.rho0, mask=mask, theta=theta, mode=mq,
+                     precision=Q.QUAPI_FP32_LOG)
+    info = g.info()
+    assert info["precision"] == Q.QUAPI_FP32_LOG and info["hash_merge"] == 1
+    o.step(n)
+    g.step(n)
+    got = g.rho_history(0, n + 1)
+    want = o.rho_history()
+    err = np.abs(got - want).max()
+    print(f"[fp32] max |drho| = {err:.3e}", flush=True)
+    assert err < FP32_RHO_TOL
+    # group counts: only decisions within FP32 rounding of a threshold may differ
+    gs = g.stats(1, n)
+    for t in range(1, n + 1):
+        a, b = gs[t - 1]["n_groups"], o.stats(t)["n_groups"]
+        assert abs(a - b) <= max(2, 1e-3 * b), (t, a, b)
+    # stored amplitudes against the oracle's, matched by history
+    ho, wo = o.groups()
+    hg, wg = g.groups()
+    ref = {bytes(h): w for h, w in zip(ho, wo)}
+    common = [(ref[bytes(h)], w) for h, w in zip(hg, wg) if bytes(h) in ref]
+    assert len(common) >= 0.999 * len(ho)
+    d = np.array([abs(a - b) / max(abs(a), 1e-300) for a, b in common])
+    print(f"[fp32] groups {len(hg)} vs {len(ho)}, median rel |dw| = {np.median(d):.2e}", flush=True)
+    assert np.median(d) < 1e-5
+
+
+def test_fp32_form_against_fp64_form(Q, eta_cache):
+    """Both forms on the same GPU, on the structured bath at dk_max = 24 with lags
+    0..11 kept (the FP64 form on the bucketed store), 200 steps, both comparing
+    12 mantissa bits for the representative."""
+    wl = W.structured_bath()
+    eta = eta_cache(wl, wl.K)
+    n = 200
+    kw = dict(mask=wl.mask, theta=wl.theta, max_steps=n)
+    g64 = Q.Propagator(wl.H, wl.q, wl.dt, wl.K, eta, wl.rho0, qbits=FP32_QBITS, **kw)
+    g32 = Q.Propagator(wl.H, wl.q, wl.dt, wl.K, eta, wl.rho0, precision=Q.QUAPI_FP32_LOG,
+                       max_groups=4 << 20, **kw)
+    assert g64.info()["hash_merge"] == 0 and g32.info()["hash_merge"] == 1
+    g64.step(n)
+    g32.step(n)
+    r64 = g64.rho_history(0, n + 1)
+    r32 = g32.rho_history(0, n + 1)
+    err = np.abs(r32 - r64).max()
+    print(f"[fp32] 200 steps, max |drho| FP32 form vs FP64 form = {err:.3e}", flush=True)
+    assert err < FP32_RHO_TOL
+    s64, s32 = g64.stats(1, n), g32.stats(1, n)
+    assert all(abs(a["n_groups"] - b["n_groups"]) <= max(2, 1e-3 * a["n_groups"]) for a, b in zip(s64, s32))
