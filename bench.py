@@ -17,6 +17,14 @@ and the CPU oracle timed on a bounded sample of the same workload.
 --copy-mib N adds one plain device-to-device copy of N MiB after the timed
 work: a kernel of known traffic against which the PMC byte counters of a
 profiled run are scaled.
+
+--workload long-memory measures the long-memory configuration instead: the
+same structured bath with dk_max = 40, theta = 1e-9, the mask keeping lags
+0..11 exact and lags 16, 24 and 32 of the tail (80-bit histories, hash-table
+merge), 1000 time steps.  Its roofline object covers the expand kernel, the
+largest share of that step (algorithmic bytes = one stored group read per
+group extended + one written per group stored).  --precision fp32 runs the
+FP32 log-domain form on either workload.
 """
 from __future__ import annotations
 
@@ -35,27 +43,51 @@ sys.path.insert(0, ROOT)
 
 METRIC = "path-steps/sec + HBM roofline fraction at dk_max=24, theta=1e-8; time per rho(t)"
 HBM_PEAK_GBS = 8000.0
-RECORD_BYTES = 32
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_traffic.json")
-KERNEL_SOURCES = ["paper_2506_03127_amd/csrc/quapi_step.hip", "paper_2506_03127_amd/csrc/quapi_device.h",
-                  "paper_2506_03127_amd/csrc/quapi_host.h"]
+CSRC = "paper_2506_03127_amd/csrc/"
+
+# per workload: the kernel the roofline object covers, the sources it is built
+# from, the committed PMC traffic record, and the oracle sample for the CPU baseline
+WORKLOADS = {
+    "structured-bath": {
+        "kernel": "step_kernel", "kernel_label": "step_kernel<4,2>",
+        "sources": [CSRC + "quapi_step.hip", CSRC + "quapi_device.h", CSRC + "quapi_host.h"],
+        "traffic": "step_kernel_traffic.json", "cpu_steps": 22, "max_groups": 0},
+    "long-memory": {
+        "kernel": "sparse_expand", "kernel_label": "sparse_expand<4,2,2>",
+        "sources": [CSRC + "quapi_sparse.hip", CSRC + "quapi_sparse.h", CSRC + "quapi_device.h",
+                    CSRC + "quapi_host.h"],
+        "traffic": "sparse_expand_long_memory_traffic.json", "cpu_steps": 15, "max_groups": 48 << 20},
+}
 
 
-def kernel_source_hash() -> str:
+def workload_spec(name: str, precision: str) -> dict:
+    spec = dict(WORKLOADS[name])
+    if precision == "fp32":
+        # the FP32 form runs every mask on the hash-table merge
+        spec.update({"kernel": "sparse_expand", "kernel_label": "sparse_expand (FP32 form)",
+                     "sources": WORKLOADS["long-memory"]["sources"],
+                     "traffic": spec["traffic"].replace(".json", "_fp32.json").replace(
+                         "step_kernel", "sparse_expand_structured_bath")})
+        if name == "structured-bath":
+            spec["max_groups"] = 8 << 20
+    return spec
+
+
+def kernel_source_hash(spec: dict) -> str:
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in spec["sources"]:
         h.update(open(os.path.join(ROOT, f), "rb").read())
     return h.hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per step-kernel launch from the committed PMC measurement, or None when
-    the kernel sources changed since the counters were taken."""
+def measured_traffic(spec: dict):
+    """HBM bytes per launch of the roofline kernel from the committed PMC measurement,
+    or None when the kernel sources changed since the counters were taken."""
     try:
-        rec = json.load(open(TRAFFIC_FILE))
+        rec = json.load(open(os.path.join(ROOT, "profiles", spec["traffic"])))
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_source_sha256") != kernel_source_hash():
+    if rec.get("kernel_source_sha256") != kernel_source_hash(spec):
         return None
     return rec.get("bytes_per_launch")
 
@@ -87,24 +119,27 @@ def cpu_baseline(wl, steps: int) -> dict:
                       f"{el:.1f} s, single thread, {cpu_model()})"}
 
 
-def traffic_from_counters(fetch_csv: str, write_csv: str, out_path: str, copy_mib: int) -> dict:
-    """HBM bytes per step-kernel launch from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE,
-    KiB per dispatch) of ``bench.py --copy-mib N``: each counter is scaled by what it reads for
-    that plain N-MiB device copy, whose true traffic is N MiB read and N MiB written."""
+def traffic_from_counters(fetch_csv: str, write_csv: str, spec: dict, copy_mib: int) -> dict:
+    """HBM bytes per launch of the roofline kernel from two rocprofv3 --pmc runs (FETCH_SIZE,
+    WRITE_SIZE, KiB per dispatch) of ``bench.py --copy-mib N``: each counter is scaled by what it
+    reads for that plain N-MiB device copy, whose true traffic is N MiB read and N MiB written."""
     import csv
 
     def read(path, counter):
-        step, other = [], []
+        # the calibration copy is the largest dispatch of the runtime's copy kernel (a
+        # device-to-device tensor copy runs as one); fills, such as the clearing of the
+        # hash table, are not copies
+        step, copies = [], []
         for r in csv.DictReader(open(path)):
             if r["Counter_Name"] != counter:
                 continue
             v = float(r["Counter_Value"])
             name = r.get("Kernel_Name", "")
-            if "step_kernel" in name:
+            if spec["kernel"] in name:
                 step.append(v)
-            elif "plan_kernel" not in name:
-                other.append(v)
-        return step, max(other)
+            elif "copyBuffer" in name:
+                copies.append(v)
+        return step, max(copies)
 
     f_step, f_copy = read(fetch_csv, "FETCH_SIZE")
     w_step, w_copy = read(write_csv, "WRITE_SIZE")
@@ -113,7 +148,7 @@ def traffic_from_counters(fetch_csv: str, write_csv: str, out_path: str, copy_mi
     ff, fw = copy_kib / f_copy, copy_kib / w_copy
     fetch_b = float(np.mean(f_step)) * 1024.0 * ff
     write_b = float(np.mean(w_step)) * 1024.0 * fw
-    rec.update({"kernel_source_sha256": kernel_source_hash(),
+    rec.update({"kernel": spec["kernel_label"], "kernel_source_sha256": kernel_source_hash(spec),
                 "launches": len(f_step),
                 "fetch_kib_per_launch_raw": float(np.mean(f_step)),
                 "write_kib_per_launch_raw": float(np.mean(w_step)),
@@ -121,7 +156,7 @@ def traffic_from_counters(fetch_csv: str, write_csv: str, out_path: str, copy_mi
                 "fetch_scale": ff, "write_scale": fw,
                 "fetch_bytes_per_launch": fetch_b, "write_bytes_per_launch": write_b,
                 "bytes_per_launch": fetch_b + write_b})
-    json.dump(rec, open(out_path, "w"), indent=1)
+    json.dump(rec, open(os.path.join(ROOT, "profiles", spec["traffic"]), "w"), indent=1)
     return rec
 
 
@@ -130,17 +165,24 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5, help="timed propagations")
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--cpu-steps", type=int, default=22,
-                    help="time steps of the oracle sample for the CPU baseline (0: skip)")
+    ap.add_argument("--cpu-steps", type=int, default=-1,
+                    help="time steps of the oracle sample for the CPU baseline (0: skip; "
+                         "default: 22 for the structured bath, 15 for the long-memory workload)")
     ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="structured-bath")
+    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64",
+                    help="fp32: the FP32 log-domain form (hash-table merge)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="one plain device copy of this size after the timed work (PMC calibration)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the step kernel's HBM traffic per launch from the counter files of "
                          "two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of bench.py --copy-mib; no GPU")
     args = ap.parse_args()
+    spec = workload_spec(args.workload, args.precision)
+    if args.cpu_steps < 0:
+        args.cpu_steps = spec["cpu_steps"]
     if args.traffic_from:
-        print(json.dumps(traffic_from_counters(args.traffic_from[0], args.traffic_from[1], TRAFFIC_FILE,
+        print(json.dumps(traffic_from_counters(args.traffic_from[0], args.traffic_from[1], spec,
                                                args.copy_mib or 256)))
         return
     if args.gpus != 1:
@@ -153,13 +195,17 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    wl = workloads.structured_bath()
+    wl = workloads.structured_bath() if args.workload == "structured-bath" else workloads.long_memory()
     b = wl.bath
     peaks = [x for pk in b.peaks for x in pk]
     eta = quapi.quapi_eta(b.ohmic_alpha, b.ohmic_wc, peaks, wl.beta, wl.dt, wl.K)
     stream = torch.cuda.Stream()
+    precision = quapi.QUAPI_FP32_LOG if args.precision == "fp32" else quapi.QUAPI_FP64
     prop = quapi.Propagator(wl.H, wl.q, wl.dt, wl.K, eta, wl.rho0, mask=wl.mask, theta=wl.theta,
-                            mode=quapi.QUAPI_PRE, max_steps=wl.n_steps, stream=stream.cuda_stream)
+                            mode=quapi.QUAPI_PRE, max_steps=wl.n_steps, stream=stream.cuda_stream,
+                            max_groups=spec["max_groups"], precision=precision)
+    info = prop.info()
+    record_bytes = info["record_bytes"]
     n_t = wl.n_steps
 
     def run_once():
@@ -185,7 +231,7 @@ def main():
     total = sum(times)
     ms_per_step = 1e3 * total / len(times)
     value = children * len(times) / total
-    alg_bytes = RECORD_BYTES * (groups_in + groups_out)
+    alg_bytes = record_bytes * (groups_in + groups_out)
 
     out = {
         "metric": METRIC,
@@ -198,7 +244,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.precision == "fp64" else "f32 (log domain) + f64 sums",
         "data": "synthetic (model Hamiltonian and spectral density; no dataset)",
         "config": {
             "workload": wl.name, "M": wl.M, "dk_max": wl.K, "mask": list(wl.mask),
@@ -206,6 +252,8 @@ def main():
             "bath": {"ohmic_alpha": b.ohmic_alpha, "ohmic_wc": b.ohmic_wc,
                      "peaks_w0_gamma_lambda": [list(p) for p in b.peaks]},
             "beta": wl.beta, "dt": wl.dt, "eps": 0.5, "Delta": 1.0,
+            "precision": args.precision, "merge": "hash table" if info["hash_merge"] else "bucketed store",
+            "record_bytes": record_bytes,
         },
         "time_per_rho_us": 1e3 * ms_per_step / n_t,
         "path_steps_per_propagation": children,
@@ -215,8 +263,8 @@ def main():
     }
 
     if not args.no_roofline:
-        # per-launch durations of the step kernel: HIP events recorded by the library on its
-        # stream right before and after each step-kernel launch
+        # per-launch durations of the roofline kernel: HIP events recorded by the library on
+        # its stream right before and after each launch of it
         prop.reset()
         quapi.quapi_profile_begin(prop.ctx, n_t)
         quapi.quapi_step(prop.ctx, n_t)
@@ -225,10 +273,11 @@ def main():
         per_launch_bytes = float(alg_bytes.mean())
         achieved = per_launch_bytes / mean_s / 1e9
         out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                           "kernel": "step_kernel<4,2>", "launches": n_t,
+                           "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(spec),
+                           "kernel": spec["kernel_label"], "launches": n_t,
                            "mean_launch_us": mean_s * 1e6,
-                           "planner_mean_launch_us": float(plan_ms.mean()) * 1e3,
+                           ("rest_of_step_mean_us" if info["hash_merge"] else "planner_mean_launch_us"):
+                               float(plan_ms.mean()) * 1e3,
                            "alg_bytes_per_launch": per_launch_bytes}
 
     if args.copy_mib > 0:

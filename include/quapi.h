@@ -170,12 +170,15 @@ const char* quapi_strerror(int code);
 /* Launch timing, for measurement.  quapi_profile_begin clears the record and
  * makes the next quapi_step calls record HIP events on the context's stream
  * around each of the next max_launches steps: one before the step kernel, one
- * between it and the planner that follows it, one after the planner.
+ * between it and the planner that follows it, one after the planner.  On the
+ * hash-table merge: one before the expand kernel, one after it, one after the
+ * rest of the step.
  * Errors: EINVAL (max_launches < 1), ENOMEM, EDEVICE. */
 int quapi_profile_begin(quapi_ctx* c, int max_launches);
 
 /* Durations in milliseconds of the recorded steps, oldest first: step_ms[k] of
- * the step kernel, plan_ms[k] of the planner after it (either array may be NULL).
+ * the step kernel, plan_ms[k] of the planner after it (either array may be NULL);
+ * on the hash-table merge, of the expand kernel and of the rest of the step.
  * Writes min(cap, n) entries, *n_out = n; synchronises and stops recording.
  * Errors: EINVAL, ESTATE (no recording began), EDEVICE. */
 int quapi_profile_end(quapi_ctx* c, int cap, double* step_ms, double* plan_ms, int* n_out);

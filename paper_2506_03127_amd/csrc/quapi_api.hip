@@ -13,6 +13,7 @@
 
 #include "../../include/quapi.h"
 #include "quapi_host.h"
+#include "quapi_sparse.h"
 
 using quapi_dev::GroupBuf;
 using quapi_dev::StepArgs;
@@ -301,14 +302,12 @@ int step_sparse(quapi_ctx* c, int n_steps) {
         a.coef = c->d_coef + (size_t)(std::min(t, c->K + 1) - 1) * 4 * n;
         hipEvent_t* ev = (c->prof_on && c->prof_n < c->prof_cap) ? &c->prof_ev[3 * (size_t)c->prof_n++] : nullptr;
         if (ev && hipEventRecord(ev[0], c->stream) != hipSuccess) ev = nullptr;
-        if (quapi_dev::launch_sparse_step(a, c->stream) != (int)hipSuccess) {
+        // profiled: ev[0]..ev[1] brackets expand, ev[1]..ev[2] the rest of the step
+        if (quapi_dev::launch_sparse_step(a, c->stream, ev ? (void*)ev[1] : nullptr) != (int)hipSuccess) {
             c->err = QUAPI_EDEVICE;
             return c->err;
         }
-        if (ev) {
-            (void)hipEventRecord(ev[1], c->stream);
-            (void)hipEventRecord(ev[2], c->stream);
-        }
+        if (ev) (void)hipEventRecord(ev[2], c->stream);
         c->t = t;
         c->cur = 1 - c->cur;
     }

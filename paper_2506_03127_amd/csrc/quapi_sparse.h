@@ -1,0 +1,66 @@
+// Host/device interface of the hash-table merge (masks whose merge positions
+// are not a contiguous run 0..L-1): argument block and launcher.
+#pragma once
+
+#include "quapi_host.h"
+
+namespace quapi_dev {
+
+// Groups are full histories of one or two 64-bit words (point j at bits
+// [BP*j, BP*j+BP) of the number, the newest point lowest) in no particular
+// order, merged through an open-addressing hash table keyed on the gathered
+// merge positions.
+constexpr int kSparseThreads = 256;
+constexpr unsigned long long kMinTable = 1024;   // smallest table a step uses (slots)
+
+// One hash-table slot.  key holds the merge key plus one, so that an all-zero
+// slot is free.  best is the largest "representative word" of the key's
+// children: in the packed form the quantised |w|^2 above the complement of the
+// child's points at the other positions (the largest word is then the largest
+// quantised |w|^2 and, among those, the smallest history); otherwise the
+// quantised |w|^2 alone, with the history settled by a second pass.
+struct __align__(32) SpSlot {
+    unsigned long long key;
+    unsigned long long best;
+    double wr, wi;                  // sum of the key's child weights
+};
+
+struct SparseArgs {
+    const uint64_t* h_in;           // [cap * hw] stored groups (state at t-1)
+    const double2* w_in;            // FP64 form: amplitudes
+    uint64_t* h_out;                // [cap * hw] groups after step t
+    double2* w_out;
+    const float2* wf_in;            // FP32 precision form: (ln|w|, arg w)
+    float2* wf_out;
+    int hw;                         // 64-bit words per history (1 or 2)
+    unsigned int* count;            // [2] stored groups, by parity of the time step
+    SpSlot* slot;                   // [tsize] the table, all zero between steps
+    unsigned long long tsize;       // allocated slots (a power of two >= kMinTable)
+    unsigned long long* tN;         // [tsize] unpacked form: smallest other points at the best q, ~0 when free
+    unsigned int* cslot;            // [cap * P] unpacked form: table slot of each child, ~0u if filtered
+    unsigned long long* cN;         // [cap * P] unpacked form: its points at the other positions
+    unsigned long long* cq;         // [cap * P] unpacked form: its quantised |w|^2
+    long long cap;                  // group capacity
+    int P, K, t;
+    double theta2;
+    int qbits;                      // low bits of |w|^2 cleared by the quantisation
+    int packed;                     // 1: representative word packs the other positions
+    const double* tables;
+    const double* coef;
+    int nq;                         // merge positions, most significant first
+    int nn;                         // the other positions, oldest (most significant) first
+    int qpos[kMaxK];
+    int npos[kMaxK];
+    double* partials;               // [partial_stride(P)][grid] per expand workgroup
+    int grid;
+    double2* rho_hist;
+    StepStatsDev* stats_hist;
+    unsigned int* error;
+};
+
+
+// expand, resolve, compact, reduce; records after_expand (a hipEvent_t, may be
+// null) on the stream between expand and the rest
+int launch_sparse_step(const SparseArgs& a, void* stream, void* after_expand);
+
+}  // namespace quapi_dev

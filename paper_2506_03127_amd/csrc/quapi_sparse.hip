@@ -35,6 +35,7 @@
 
 #include "quapi_device.h"
 #include "quapi_host.h"
+#include "quapi_sparse.h"
 
 namespace quapi_dev {
 
@@ -467,27 +468,29 @@ __global__ __launch_bounds__(kSparseThreads) void sparse_reduce(const SparseArgs
 }  // namespace
 
 template <int P, int BP, int W, bool F32>
-void launch_sparse(const SparseArgs& a, hipStream_t st) {
+void launch_sparse(const SparseArgs& a, hipStream_t st, hipEvent_t after_expand) {
     const int g = a.grid;
     hipLaunchKernelGGL((sparse_expand<P, BP, W, F32>), dim3(g), dim3(kSparseThreads), 0, st, a);
+    if (after_expand) (void)hipEventRecord(after_expand, st);
     if (!a.packed) hipLaunchKernelGGL((sparse_resolve<P>), dim3(g), dim3(kSparseThreads), 0, st, a);
     hipLaunchKernelGGL((sparse_compact<BP, W, F32>), dim3(g), dim3(kSparseThreads), 0, st, a);
     hipLaunchKernelGGL((sparse_reduce<P>), dim3(1), dim3(kSparseThreads), 0, st, a);
 }
 
 template <bool F32>
-int launch_sparse_form(const SparseArgs& a, hipStream_t st) {
-    if (a.P == 4 && a.hw == 1) launch_sparse<4, 2, 1, F32>(a, st);
-    else if (a.P == 4 && a.hw == 2) launch_sparse<4, 2, 2, F32>(a, st);
-    else if (a.P == 9 && a.hw == 1) launch_sparse<9, 4, 1, F32>(a, st);
-    else if (a.P == 9 && a.hw == 2) launch_sparse<9, 4, 2, F32>(a, st);
+int launch_sparse_form(const SparseArgs& a, hipStream_t st, hipEvent_t ev) {
+    if (a.P == 4 && a.hw == 1) launch_sparse<4, 2, 1, F32>(a, st, ev);
+    else if (a.P == 4 && a.hw == 2) launch_sparse<4, 2, 2, F32>(a, st, ev);
+    else if (a.P == 9 && a.hw == 1) launch_sparse<9, 4, 1, F32>(a, st, ev);
+    else if (a.P == 9 && a.hw == 2) launch_sparse<9, 4, 2, F32>(a, st, ev);
     else return (int)hipErrorInvalidValue;
     return (int)hipGetLastError();
 }
 
-int launch_sparse_step(const SparseArgs& a, void* stream) {
+int launch_sparse_step(const SparseArgs& a, void* stream, void* after_expand) {
     hipStream_t st = (hipStream_t)stream;
-    return a.wf_in ? launch_sparse_form<true>(a, st) : launch_sparse_form<false>(a, st);
+    hipEvent_t ev = (hipEvent_t)after_expand;
+    return a.wf_in ? launch_sparse_form<true>(a, st, ev) : launch_sparse_form<false>(a, st, ev);
 }
 
 }  // namespace quapi_dev

@@ -88,6 +88,16 @@ def structured_bath(n_steps: int = 1000, K: int = 24, n_exact: int = 12,
                     n_steps=n_steps, mode="pre")
 
 
+def long_memory(n_steps: int = 1000) -> Workload:
+    """The structured bath with memory K = 40 and theta = 1e-9; the mask keeps lags
+    0..11 exact and lags 16, 24 and 32 of the tail (80-bit histories; the merge
+    positions are not a contiguous run, so it takes the hash-table merge)."""
+    w = structured_bath(n_steps=n_steps, K=40, theta=1e-9)
+    return Workload(name="long_memory_K40_E12_16_24_32", H=w.H, q=w.q, bath=w.bath, beta=w.beta,
+                    dt=w.dt, K=40, mask=tuple(range(12)) + (16, 24, 32), theta=1e-9, rho0=w.rho0,
+                    n_steps=n_steps, mode="pre")
+
+
 def three_level(seed: int = 7, K: int = 16, n_exact: int = 6, theta: float = 1e-8,
                 n_steps: int = 200) -> Workload:
     """Three-level system with a seeded random Hermitian H_S (entries ~ N(0, 0.5))."""
