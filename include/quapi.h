@@ -115,10 +115,11 @@ typedef struct {
     int record_bytes;         /* bytes of one stored group: 8 key + 8 history tail + 16 weight (32),    */
                               /* or 8 or 16 history + 16 weight (24 or 32) on the hash-table merge,     */
                               /* with an 8-byte weight in the FP32 precision form                       */
-    long long capacity;       /* maximum number of stored groups                                        */
+    long long capacity;       /* maximum number of stored groups (of one instance)                      */
     size_t device_bytes;      /* device memory held by the context                                      */
     int precision;            /* QUAPI_FP64 or QUAPI_FP32_LOG                                           */
     int hash_merge;           /* 1: the hash-table merge, 0: the bucketed store                         */
+    int n_instances;          /* instances of a batched context, else 1                                 */
 } quapi_info_t;
 
 /* Create a context and its initial state t = 0 (one path per nonzero
@@ -128,6 +129,20 @@ typedef struct {
  * with a history over 128 bits, a key over 62 bits or other positions over 64
  * bits), ENOMEM, EDEVICE.  *out is NULL on error. */
 int quapi_create(const quapi_params* p, quapi_ctx** out);
+
+/* Batched form: n_inst instances of the method (for instance bath parameter
+ * points of eq. SD) that share every field of p but the influence
+ * coefficients (p->eta is not read), propagated together: each step is one
+ * launch of the step kernel over the groups of all instances.  Instance j's
+ * coefficients are eta_batch[3*(K+1)*j .. 3*(K+1)*(j+1)-1], laid out as
+ * quapi_params.eta; the caller keeps ownership.  Each instance's results
+ * (rho(t), counters, groups) are those of a context created with quapi_create
+ * on its own coefficients and the same bucket layout.  p->max_groups counts
+ * one instance.  The functions without "batch" in their name address
+ * instance 0.  Merge positions 0..L-1 (the bucketed store), FP64 only.
+ * Errors: as quapi_create; EINVAL (n_inst < 1 or > 1024, eta_batch NULL or not
+ * finite), EUNSUPPORTED (the hash-table merge or the FP32 form). */
+int quapi_create_batch(const quapi_params* p, int n_inst, const quapi_c64* eta_batch, quapi_ctx** out);
 
 /* Enqueue n_steps time steps on the context's stream; returns without waiting.
  * Errors: EINVAL (n_steps < 0), ESTATE (a previous step failed), ENOMEM
@@ -156,6 +171,14 @@ int quapi_step_stats(quapi_ctx* c, int t0, int n, quapi_stepstat_t* out);
  * hist or w may be NULL with cap = 0 to query n (synchronises). */
 int quapi_groups(quapi_ctx* c, long long cap, unsigned char* hist, quapi_c64* w,
                  long long* n_out);
+
+/* As quapi_rho_history, quapi_step_stats and quapi_groups, for instance inst
+ * (0 <= inst < n_instances) of a batched context.  Errors: EINVAL (inst out of
+ * range), as the instance-0 forms otherwise. */
+int quapi_batch_rho_history(quapi_ctx* c, int inst, int t0, int n, quapi_c64* out);
+int quapi_batch_step_stats(quapi_ctx* c, int inst, int t0, int n, quapi_stepstat_t* out);
+int quapi_batch_groups(quapi_ctx* c, int inst, long long cap, unsigned char* hist, quapi_c64* w,
+                       long long* n_out);
 
 /* Return to t = 0 with the initial state (tables and buffers are kept). */
 int quapi_reset(quapi_ctx* c);

@@ -31,8 +31,8 @@ struct quapi_ctx {
     std::vector<double> coef;    // per-step coefficient sets, t = 1..K+1 (t > K uses set K+1)
     std::vector<double> rho0;    // 2*P
     std::vector<unsigned long long> init_key;
-    std::vector<double2> init_w;
-    std::vector<long long> init_bucket;
+    std::vector<double2> init_w;           // [n_inst][initial groups]
+    std::vector<long long> init_bucket;    // bucket inside an instance
     std::vector<int> init_pair;
 
     // sparse-mask path (merge positions not 0..L-1): hash-table merge
@@ -55,6 +55,13 @@ struct quapi_ctx {
     unsigned long long* sp_cq = nullptr;
     double* sp_partials = nullptr;
     int sp_grid = 0;
+
+    // batched form: n_inst instances (bath parameter points) in one store
+    int n_inst = 1;
+    bool batch = false;
+    long long inst_buckets = 0;              // P^D, buckets of one instance
+    unsigned long long* d_totals = nullptr;  // [n_inst]
+    unsigned int* d_inst = nullptr;          // [2][n_inst][2] first chunk and groups, by step parity
 
     hipStream_t stream = nullptr;
     bool own_stream = false;
@@ -87,6 +94,8 @@ struct quapi_ctx {
 };
 
 namespace {
+
+constexpr int kMaxInstances = 1024;   // instances of one batched context
 
 int hip_to_code(hipError_t e) {
     if (e == hipSuccess) return QUAPI_OK;
@@ -158,26 +167,35 @@ int upload_initial(quapi_ctx* c) {
     } else {
         e = hipMemsetAsync(c->counts[0], 0, (size_t)c->n_buckets * sizeof(unsigned int), c->stream);
     }
-    for (size_t k = 0; !c->sparse && k < c->init_key.size() && e == hipSuccess; ++k) {
-        const size_t o = (size_t)c->init_bucket[k] * (size_t)c->cap;
-        const unsigned long long zero = 0;
-        const unsigned int one = 1;
-        e = hipMemcpyAsync(c->buf[0].key + o, &c->init_key[k], 8, hipMemcpyHostToDevice, c->stream);
-        if (e == hipSuccess) e = hipMemcpyAsync(c->buf[0].tail + o, &zero, 8, hipMemcpyHostToDevice, c->stream);
-        if (e == hipSuccess) e = hipMemcpyAsync(c->buf[0].w + o, &c->init_w[k], 16, hipMemcpyHostToDevice, c->stream);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(c->counts[0] + c->init_bucket[k], &one, 4, hipMemcpyHostToDevice, c->stream);
-        // the copies read host stack values: complete them before the next iteration reuses them
-        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    }
+    const size_t n0 = c->init_key.size();
+    for (size_t j = 0; !c->sparse && j < (size_t)c->n_inst && e == hipSuccess; ++j)
+        for (size_t k = 0; k < n0 && e == hipSuccess; ++k) {
+            const long long b = (long long)j * c->inst_buckets + c->init_bucket[k];
+            const size_t o = (size_t)b * (size_t)c->cap;
+            const unsigned long long zero = 0;
+            const unsigned int one = 1;
+            e = hipMemcpyAsync(c->buf[0].key + o, &c->init_key[k], 8, hipMemcpyHostToDevice, c->stream);
+            if (e == hipSuccess) e = hipMemcpyAsync(c->buf[0].tail + o, &zero, 8, hipMemcpyHostToDevice, c->stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(c->buf[0].w + o, &c->init_w[j * n0 + k], 16, hipMemcpyHostToDevice, c->stream);
+            if (e == hipSuccess) e = hipMemcpyAsync(c->counts[0] + b, &one, 4, hipMemcpyHostToDevice, c->stream);
+            // the copies read host stack values: complete them before the next iteration reuses them
+            if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        }
     if (e == hipSuccess) e = hipMemsetAsync(c->d_error, 0, sizeof(unsigned int), c->stream);
-    std::vector<double2> r0(c->P);
-    for (int p = 0; p < c->P; ++p) r0[p] = make_double2(c->rho0[2 * p], c->rho0[2 * p + 1]);
-    StepStatsDev s0 = {};
-    s0.n_stored = c->init_key.size();
+    // t = 0 of every instance
+    std::vector<double2> r0((size_t)c->n_inst * c->P);
+    for (size_t j = 0; j < (size_t)c->n_inst; ++j)
+        for (int p = 0; p < c->P; ++p) r0[j * c->P + p] = make_double2(c->rho0[2 * p], c->rho0[2 * p + 1]);
+    std::vector<StepStatsDev> s0((size_t)c->n_inst);
+    for (auto& x : s0) {
+        x = StepStatsDev{};
+        x.n_stored = n0;
+    }
     if (e == hipSuccess)
-        e = hipMemcpyAsync(c->d_rho, r0.data(), c->P * sizeof(double2), hipMemcpyHostToDevice, c->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(c->d_stats, &s0, sizeof s0, hipMemcpyHostToDevice, c->stream);
+        e = hipMemcpyAsync(c->d_rho, r0.data(), r0.size() * sizeof(double2), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->d_stats, s0.data(), s0.size() * sizeof(StepStatsDev), hipMemcpyHostToDevice, c->stream);
     c->t = 0;
     c->cur = 0;
     c->err = QUAPI_OK;
@@ -204,31 +222,38 @@ int launch_planner(quapi_ctx* c, int t) {
     pa.rho_hist = c->d_rho;
     pa.stats_hist = c->d_stats;
     pa.error = c->d_error;
-    return quapi_dev::launch_plan(pa, c->stream) == (int)hipSuccess ? QUAPI_OK : QUAPI_EDEVICE;
+    pa.n_inst = c->n_inst;
+    pa.inst_buckets = (int)c->inst_buckets;
+    pa.totals = c->d_totals;
+    pa.inst_next = c->d_inst ? c->d_inst + (size_t)((t + 1) & 1) * 2 * c->n_inst : nullptr;
+    pa.inst_prev = c->d_inst ? c->d_inst + (size_t)(t & 1) * 2 * c->n_inst : nullptr;
+    const int e = c->batch ? quapi_dev::launch_plan_batch(pa, c->stream) : quapi_dev::launch_plan(pa, c->stream);
+    return e == (int)hipSuccess ? QUAPI_OK : QUAPI_EDEVICE;
 }
 
 int grow_history(quapi_ctx* c, int need) {
     if (need <= c->hist_cap) return QUAPI_OK;
     const int ncap = std::max(need, 2 * c->hist_cap);
+    const size_t B = (size_t)c->n_inst;             // history rows hold every instance
     double2* nr = nullptr;
     StepStatsDev* ns = nullptr;
-    int rc = dev_alloc(c, &nr, (size_t)(ncap + 1) * c->P);
+    int rc = dev_alloc(c, &nr, (size_t)(ncap + 1) * B * c->P);
     if (rc) return rc;
-    rc = dev_alloc(c, &ns, (size_t)(ncap + 1));
-    if (rc) { dev_free(c, nr, (size_t)(ncap + 1) * c->P * sizeof(double2)); return rc; }
-    hipError_t e = hipMemcpyAsync(nr, c->d_rho, (size_t)(c->hist_cap + 1) * c->P * sizeof(double2),
+    rc = dev_alloc(c, &ns, (size_t)(ncap + 1) * B);
+    if (rc) { dev_free(c, nr, (size_t)(ncap + 1) * B * c->P * sizeof(double2)); return rc; }
+    hipError_t e = hipMemcpyAsync(nr, c->d_rho, (size_t)(c->hist_cap + 1) * B * c->P * sizeof(double2),
                                   hipMemcpyDeviceToDevice, c->stream);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(ns, c->d_stats, (size_t)(c->hist_cap + 1) * sizeof(StepStatsDev),
+        e = hipMemcpyAsync(ns, c->d_stats, (size_t)(c->hist_cap + 1) * B * sizeof(StepStatsDev),
                            hipMemcpyDeviceToDevice, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
-        dev_free(c, nr, (size_t)(ncap + 1) * c->P * sizeof(double2));
-        dev_free(c, ns, (size_t)(ncap + 1) * sizeof(StepStatsDev));
+        dev_free(c, nr, (size_t)(ncap + 1) * B * c->P * sizeof(double2));
+        dev_free(c, ns, (size_t)(ncap + 1) * B * sizeof(StepStatsDev));
         return hip_to_code(e);
     }
-    dev_free(c, c->d_rho, (size_t)(c->hist_cap + 1) * c->P * sizeof(double2));
-    dev_free(c, c->d_stats, (size_t)(c->hist_cap + 1) * sizeof(StepStatsDev));
+    dev_free(c, c->d_rho, (size_t)(c->hist_cap + 1) * B * c->P * sizeof(double2));
+    dev_free(c, c->d_stats, (size_t)(c->hist_cap + 1) * B * sizeof(StepStatsDev));
     c->d_rho = nr;
     c->d_stats = ns;
     c->hist_cap = ncap;
@@ -355,10 +380,12 @@ int quapi_eta(const quapi_bath* bath, double beta, double dt, int dk_max, quapi_
                                    dt, dk_max, (double*)eta_out) == 0 ? QUAPI_OK : QUAPI_EINVAL;
 }
 
-int quapi_create(const quapi_params* p, quapi_ctx** out) {
+// A context of n_inst instances that share p but for the eta tables (instance
+// j's at eta_all + 3*(K+1)*j); batch: the batched form (its planner and layout).
+static int create_ctx(const quapi_params* p, int n_inst, const quapi_c64* eta_all, bool batch, quapi_ctx** out) {
     if (!out) return QUAPI_EINVAL;
     *out = nullptr;
-    if (!p || !p->H || !p->q || !p->eta || !p->rho0) return QUAPI_EINVAL;
+    if (!p || !p->H || !p->q || !eta_all || !p->rho0 || n_inst < 1 || n_inst > kMaxInstances) return QUAPI_EINVAL;
     const int M = p->M, K = p->dk_max;
     if (M < 2 || K < 1 || K > quapi_dev::kMaxK || !(p->dt > 0) || !is_finite_d(p->dt)) return QUAPI_EINVAL;
     if (!(p->theta >= 0) || !is_finite_d(p->theta)) return QUAPI_EINVAL;
@@ -368,8 +395,8 @@ int quapi_create(const quapi_params* p, quapi_ctx** out) {
     if (!quapi_host::hermitian_ok(M, (const double*)p->H)) return QUAPI_EINVAL;
     for (int i = 0; i < M; ++i)
         if (!is_finite_d(p->q[i])) return QUAPI_EINVAL;
-    for (int i = 0; i < 3 * (K + 1); ++i)
-        if (!is_finite_d(p->eta[i].re) || !is_finite_d(p->eta[i].im)) return QUAPI_EINVAL;
+    for (long long i = 0; i < 3ll * (K + 1) * n_inst; ++i)
+        if (!is_finite_d(eta_all[i].re) || !is_finite_d(eta_all[i].im)) return QUAPI_EINVAL;
     for (int i = 0; i < M * M; ++i)
         if (!is_finite_d(p->rho0[i].re) || !is_finite_d(p->rho0[i].im)) return QUAPI_EINVAL;
 
@@ -407,6 +434,9 @@ int quapi_create(const quapi_params* p, quapi_ctx** out) {
     } else {
         if (K * bits > 128 || L * bits > 62 || (K - L) * bits > 64) return QUAPI_EUNSUPPORTED;
     }
+    // the batched form is built on the bucketed store (FP64, merge positions 0..L-1)
+    if (batch && !contiguous) return QUAPI_EUNSUPPORTED;
+    const quapi_c64* const eta0 = eta_all;                // instance 0
 
     quapi_ctx* c = new (std::nothrow) quapi_ctx();
     if (!c) return QUAPI_ENOMEM;
@@ -440,13 +470,19 @@ int quapi_create(const quapi_params* p, quapi_ctx** out) {
     long long max_super = 8192;   // tuning knob: upper bound on the number of super-buckets
     if (const char* env = std::getenv("QUAPI_MAX_SUPER")) max_super = std::max(1ll, std::atoll(env));
     max_super = std::min(max_super, plan_super);
+    // batched form: one planner workgroup per instance takes all of its buckets
+    if (batch) max_super = std::min(max_super, (long long)quapi_dev::plan_batch_max_buckets() / P);
     int dm1 = 0;
     while (!c->sparse && dm1 + 1 <= L - 1 && ipow(P, dm1 + 1) <= max_super) ++dm1;
     c->D = dm1 + 1;
     c->n_super = (int)ipow(P, dm1);
-    c->n_buckets = ipow(P, c->D);
+    c->n_inst = n_inst;
+    c->batch = batch;
+    c->inst_buckets = ipow(P, c->D);
+    c->n_buckets = c->inst_buckets * n_inst;
     long long cap = c->sparse ? 1 : ipow(P, L - c->D);
-    if (p->max_groups > 0) cap = std::max(1ll, std::min(cap, (p->max_groups + c->n_buckets - 1) / c->n_buckets));
+    // (max_groups counts one instance)
+    if (p->max_groups > 0) cap = std::max(1ll, std::min(cap, (p->max_groups + c->inst_buckets - 1) / c->inst_buckets));
     // group indices are 32-bit: keep the whole store below 2^31 groups
     cap = std::min(cap, ((1ll << 31) - 1) / c->n_buckets);
     if (cap < 1) {
@@ -472,19 +508,22 @@ int quapi_create(const quapi_params* p, quapi_ctx** out) {
         c->tables[TableLayout::ss(P) + pp] = p->q[pp / M] + p->q[pp % M];
     }
     for (int i = 0; i < 3 * (K + 1); ++i) {
-        c->tables[TableLayout::eta(P) + 2 * i] = p->eta[i].re;
-        c->tables[TableLayout::eta(P) + 2 * i + 1] = p->eta[i].im;
+        c->tables[TableLayout::eta(P) + 2 * i] = eta0[i].re;
+        c->tables[TableLayout::eta(P) + 2 * i + 1] = eta0[i].im;
     }
     // coefficients of the new point at step t with the point at lag d (eq. inf_fun
     // windows): interior partners use the interior column, the time-0 partner
     // (d == t) the half-window column; the end-point correction of rho(t) swaps
     // the final point's interior coefficients for its half-window ones
+    // (one set per instance: [t-1][instance][4][K+1])
     const int n = K + 1;
-    c->coef.assign((size_t)(K + 1) * 4 * n, 0.0);
-    for (int t = 1; t <= K + 1; ++t) {
-        double* cs = c->coef.data() + (size_t)(t - 1) * 4 * n;
+    c->coef.assign((size_t)(K + 1) * n_inst * 4 * n, 0.0);
+    for (int t = 1; t <= K + 1; ++t)
+    for (int j = 0; j < n_inst; ++j) {
+        const quapi_c64* const eta = eta_all + (size_t)3 * n * j;
+        double* cs = c->coef.data() + ((size_t)(t - 1) * n_inst + j) * 4 * n;
         for (int d = 0; d <= K && d <= t; ++d) {
-            const quapi_c64 in = p->eta[d], hf = p->eta[n + d], hh = p->eta[2 * n + d];
+            const quapi_c64 in = eta[d], hf = eta[n + d], hh = eta[2 * n + d];
             const quapi_c64 cc = (d == t) ? hf : in;
             quapi_c64 dd;
             if (d == 0) dd = {hf.re - in.re, hf.im - in.im};
@@ -499,18 +538,24 @@ int quapi_create(const quapi_params* p, quapi_ctx** out) {
 
     // t = 0: one group per nonzero element of rho0 with the initial point's self term
     c->rho0.resize(2 * P);
-    const std::complex<double> e0(p->eta[n].re, p->eta[n].im);   // end-point self term
     for (int pp = 0; pp < P; ++pp) {
         const std::complex<double> r(p->rho0[pp].re, p->rho0[pp].im);
         c->rho0[2 * pp] = r.real();
         c->rho0[2 * pp + 1] = r.imag();
         if (r == std::complex<double>(0, 0)) continue;
-        const double ds = c->tables[TableLayout::ds(P) + pp], ss = c->tables[TableLayout::ss(P) + pp];
-        const std::complex<double> w = r * std::exp(std::complex<double>(-ds * e0.real() * ds, -ds * e0.imag() * ss));
         c->init_key.push_back(c->sparse ? 0ull : (unsigned long long)pp << (bits * (L - 1)));
         c->init_pair.push_back(pp);
-        c->init_w.push_back(make_double2(w.real(), w.imag()));
         c->init_bucket.push_back((long long)pp * c->n_super);   // top D points (pp, 0, ..., 0)
+    }
+    for (int j = 0; j < n_inst; ++j) {
+        const quapi_c64 e0c = eta_all[(size_t)3 * n * j + n];     // end-point self term
+        const std::complex<double> e0(e0c.re, e0c.im);
+        for (int pp : c->init_pair) {
+            const std::complex<double> r(p->rho0[pp].re, p->rho0[pp].im);
+            const double ds = c->tables[TableLayout::ds(P) + pp], ss = c->tables[TableLayout::ss(P) + pp];
+            const std::complex<double> w = r * std::exp(std::complex<double>(-ds * e0.real() * ds, -ds * e0.imag() * ss));
+            c->init_w.push_back(make_double2(w.real(), w.imag()));
+        }
     }
 
     int rc = QUAPI_OK;
@@ -533,10 +578,13 @@ int quapi_create(const quapi_params* p, quapi_ctx** out) {
     }
     if (!rc) rc = dev_alloc(c, &c->d_tables, c->tables.size());
     if (!rc) rc = dev_alloc(c, &c->d_coef, c->coef.size());
-    c->max_chunks = (int)std::min<long long>((long long)nrec / quapi_dev::chunk_heads(P) + 2, 1ll << 30);
+    // (each instance of the batched form starts a chunk: one partial chunk more each)
+    c->max_chunks = (int)std::min<long long>((long long)nrec / quapi_dev::chunk_heads(P) + n_inst + 2, 1ll << 30);
     if (!rc) rc = dev_alloc(c, &c->d_partials, (size_t)c->max_chunks * quapi_dev::partial_stride(P));
-    if (!rc) rc = dev_alloc(c, &c->d_nz_bucket, (size_t)c->n_buckets);
-    if (!rc) rc = dev_alloc(c, &c->d_nz_prefix, (size_t)c->n_buckets);
+    if (!rc) rc = dev_alloc(c, &c->d_nz_bucket, (size_t)c->n_buckets + n_inst);
+    if (!rc) rc = dev_alloc(c, &c->d_nz_prefix, (size_t)c->n_buckets + n_inst);
+    if (!rc && batch) rc = dev_alloc(c, &c->d_totals, (size_t)n_inst);
+    if (!rc && batch) rc = dev_alloc(c, &c->d_inst, (size_t)4 * n_inst);
     if (!rc) rc = dev_alloc(c, &c->d_desc, (size_t)c->max_chunks);
     if (!rc) rc = dev_alloc(c, &c->d_plan, 2);
     if (!rc) rc = dev_alloc(c, &c->d_chain, (size_t)P * c->max_chunks);
@@ -565,8 +613,8 @@ int quapi_create(const quapi_params* p, quapi_ctx** out) {
         }
     }
     c->hist_cap = p->max_steps > 0 ? p->max_steps : 1024;
-    if (!rc) rc = dev_alloc(c, &c->d_rho, (size_t)(c->hist_cap + 1) * P);
-    if (!rc) rc = dev_alloc(c, &c->d_stats, (size_t)(c->hist_cap + 1));
+    if (!rc) rc = dev_alloc(c, &c->d_rho, (size_t)(c->hist_cap + 1) * n_inst * P);
+    if (!rc) rc = dev_alloc(c, &c->d_stats, (size_t)(c->hist_cap + 1) * n_inst);
     if (rc) {
         quapi_destroy(c);
         return rc;
@@ -579,6 +627,7 @@ int quapi_create(const quapi_params* p, quapi_ctx** out) {
     if (e == hipSuccess)
         e = hipMemsetAsync(c->d_chain, 0, (size_t)P * c->max_chunks * sizeof(unsigned long long), c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(c->d_plan, 0, 2 * sizeof(quapi_dev::Plan), c->stream);
+    if (e == hipSuccess && c->d_inst) e = hipMemsetAsync(c->d_inst, 0, (size_t)4 * n_inst * sizeof(unsigned int), c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
         quapi_destroy(c);
@@ -594,7 +643,7 @@ int quapi_create(const quapi_params* p, quapi_ctx** out) {
     // chunks needs every workgroup of the grid resident); QUAPI_BLOCKS_PER_CU lowers it
     int per_cu = 0;
     if (const char* env = std::getenv("QUAPI_BLOCKS_PER_CU")) per_cu = std::max(1, std::min(16, std::atoi(env)));
-    c->grid = quapi_dev::step_grid(P, std::max(ncu, 1), per_cu);
+    c->grid = quapi_dev::step_grid(P, std::max(ncu, 1), per_cu, n_inst > 1);
     if (c->grid < 1) {
         quapi_destroy(c);
         return QUAPI_EDEVICE;
@@ -615,6 +664,18 @@ int quapi_create(const quapi_params* p, quapi_ctx** out) {
     return QUAPI_OK;
 }
 
+int quapi_create(const quapi_params* p, quapi_ctx** out) {
+    if (!p) {
+        if (out) *out = nullptr;
+        return QUAPI_EINVAL;
+    }
+    return create_ctx(p, 1, p->eta, false, out);
+}
+
+int quapi_create_batch(const quapi_params* p, int n_inst, const quapi_c64* eta_batch, quapi_ctx** out) {
+    return create_ctx(p, n_inst, eta_batch, true, out);
+}
+
 int quapi_step(quapi_ctx* c, int n_steps) {
     if (!c || n_steps < 0) return QUAPI_EINVAL;
     if (c->err) return QUAPI_ESTATE;
@@ -628,6 +689,7 @@ int quapi_step(quapi_ctx* c, int n_steps) {
     a.L = c->L;
     a.K = c->K;
     a.n_super = c->n_super;
+    a.n_inst = c->n_inst;
     a.theta2 = c->theta * c->theta;
     a.qmask = c->qbits >= 64 ? 0ull : ~((1ull << c->qbits) - 1ull);
     a.tables = c->d_tables;
@@ -647,7 +709,7 @@ int quapi_step(quapi_ctx* c, int n_steps) {
         a.plan = c->d_plan + (t & 1);
         a.t = t;
         a.epoch = ++c->epoch;
-        a.coef = c->d_coef + (size_t)(std::min(t, c->K + 1) - 1) * 4 * n;
+        a.coef = c->d_coef + (size_t)(std::min(t, c->K + 1) - 1) * c->n_inst * 4 * n;
         hipEvent_t* ev = (c->prof_on && c->prof_n < c->prof_cap) ? &c->prof_ev[3 * (size_t)c->prof_n++] : nullptr;
         if (ev && hipEventRecord(ev[0], c->stream) != hipSuccess) ev = nullptr;
         if (quapi_dev::launch_step(a, c->grid, c->stream) != (int)hipSuccess) {
@@ -679,28 +741,34 @@ int quapi_time(quapi_ctx* c, int* t_out) {
     return rc == QUAPI_EDEVICE ? rc : QUAPI_OK;
 }
 
-int quapi_rho_history(quapi_ctx* c, int t0, int n, quapi_c64* out) {
-    if (!c || !out || t0 < 0 || n < 0) return QUAPI_EINVAL;
+int quapi_batch_rho_history(quapi_ctx* c, int inst, int t0, int n, quapi_c64* out) {
+    if (!c || !out || t0 < 0 || n < 0 || inst < 0 || inst >= c->n_inst) return QUAPI_EINVAL;
     const int rc = sync_ctx(c);
     if (rc == QUAPI_EDEVICE) return rc;
     if (t0 + n - 1 > c->t) return QUAPI_EINVAL;
     if (n == 0) return QUAPI_OK;
-    const hipError_t e = hipMemcpy(out, c->d_rho + (size_t)t0 * c->P, (size_t)n * c->P * sizeof(double2),
-                                   hipMemcpyDeviceToHost);
+    // history rows hold every instance: [t][instance][P]
+    const size_t row = (size_t)c->n_inst * c->P;
+    const hipError_t e = hipMemcpy2D(out, (size_t)c->P * sizeof(double2), c->d_rho + (size_t)t0 * row + (size_t)inst * c->P,
+                                     row * sizeof(double2), (size_t)c->P * sizeof(double2), (size_t)n,
+                                     hipMemcpyDeviceToHost);
     return hip_to_code(e);
 }
 
+int quapi_rho_history(quapi_ctx* c, int t0, int n, quapi_c64* out) { return quapi_batch_rho_history(c, 0, t0, n, out); }
+
 int quapi_rho(quapi_ctx* c, int t, quapi_c64* rho_out) { return quapi_rho_history(c, t, 1, rho_out); }
 
-int quapi_step_stats(quapi_ctx* c, int t0, int n, quapi_stepstat_t* out) {
-    if (!c || !out || t0 < 1 || n < 0) return QUAPI_EINVAL;
+int quapi_batch_step_stats(quapi_ctx* c, int inst, int t0, int n, quapi_stepstat_t* out) {
+    if (!c || !out || t0 < 1 || n < 0 || inst < 0 || inst >= c->n_inst) return QUAPI_EINVAL;
     const int rc = sync_ctx(c);
     if (rc == QUAPI_EDEVICE) return rc;
     if (t0 + n - 1 > c->t) return QUAPI_EINVAL;
     std::vector<StepStatsDev> h(n);
     if (n) {
-        const hipError_t e = hipMemcpy(h.data(), c->d_stats + t0, (size_t)n * sizeof(StepStatsDev),
-                                       hipMemcpyDeviceToHost);
+        const hipError_t e = hipMemcpy2D(h.data(), sizeof(StepStatsDev), c->d_stats + (size_t)t0 * c->n_inst + inst,
+                                         (size_t)c->n_inst * sizeof(StepStatsDev), sizeof(StepStatsDev), (size_t)n,
+                                         hipMemcpyDeviceToHost);
         if (e != hipSuccess) return hip_to_code(e);
     }
     for (int k = 0; k < n; ++k) {
@@ -714,8 +782,14 @@ int quapi_step_stats(quapi_ctx* c, int t0, int n, quapi_stepstat_t* out) {
     return QUAPI_OK;
 }
 
-int quapi_groups(quapi_ctx* c, long long cap, unsigned char* hist, quapi_c64* w, long long* n_out) {
-    if (!c || !n_out || cap < 0 || (cap > 0 && (!hist || !w))) return QUAPI_EINVAL;
+int quapi_step_stats(quapi_ctx* c, int t0, int n, quapi_stepstat_t* out) {
+    return quapi_batch_step_stats(c, 0, t0, n, out);
+}
+
+int quapi_batch_groups(quapi_ctx* c, int inst, long long cap, unsigned char* hist, quapi_c64* w,
+                       long long* n_out) {
+    if (!c || !n_out || cap < 0 || (cap > 0 && (!hist || !w)) || inst < 0 || inst >= c->n_inst)
+        return QUAPI_EINVAL;
     const int rc = sync_ctx(c);
     if (rc == QUAPI_EDEVICE) return rc;
     if (c->sparse) {
@@ -752,24 +826,25 @@ int quapi_groups(quapi_ctx* c, long long cap, unsigned char* hist, quapi_c64* w,
         }
         return QUAPI_OK;
     }
-    std::vector<unsigned int> cnt((size_t)c->n_buckets);
-    hipError_t e = hipMemcpy(cnt.data(), c->counts[c->cur], cnt.size() * sizeof(unsigned int),
-                             hipMemcpyDeviceToHost);
+    // the instance's buckets
+    const size_t nb = (size_t)c->inst_buckets, b0 = (size_t)inst * nb;
+    std::vector<unsigned int> cnt(nb);
+    hipError_t e = hipMemcpy(cnt.data(), c->counts[c->cur] + b0, nb * sizeof(unsigned int), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_to_code(e);
     long long n = 0;
     for (unsigned int x : cnt) n += x;
     *n_out = n;
     if (cap == 0) return QUAPI_OK;
-    const size_t nrec = (size_t)c->n_buckets * (size_t)c->cap;
+    const size_t nrec = nb * (size_t)c->cap, r0 = b0 * (size_t)c->cap;
     std::vector<unsigned long long> k(nrec), tl(nrec);
     std::vector<double2> ww(nrec);
-    e = hipMemcpy(k.data(), c->buf[c->cur].key, nrec * 8, hipMemcpyDeviceToHost);
-    if (e == hipSuccess) e = hipMemcpy(tl.data(), c->buf[c->cur].tail, nrec * 8, hipMemcpyDeviceToHost);
-    if (e == hipSuccess) e = hipMemcpy(ww.data(), c->buf[c->cur].w, nrec * 16, hipMemcpyDeviceToHost);
+    e = hipMemcpy(k.data(), c->buf[c->cur].key + r0, nrec * 8, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(tl.data(), c->buf[c->cur].tail + r0, nrec * 8, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(ww.data(), c->buf[c->cur].w + r0, nrec * 16, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_to_code(e);
     const unsigned long long dm = (1ull << c->bits) - 1;
     long long written = 0;
-    for (long long b = 0; b < c->n_buckets && written < cap; ++b) {
+    for (long long b = 0; b < (long long)nb && written < cap; ++b) {
         for (unsigned int r = 0; r < cnt[b] && written < cap; ++r) {
             const size_t o = (size_t)b * (size_t)c->cap + r;
             unsigned char* row = hist + (size_t)written * c->K;
@@ -787,6 +862,10 @@ int quapi_groups(quapi_ctx* c, long long cap, unsigned char* hist, quapi_c64* w,
     return QUAPI_OK;
 }
 
+int quapi_groups(quapi_ctx* c, long long cap, unsigned char* hist, quapi_c64* w, long long* n_out) {
+    return quapi_batch_groups(c, 0, cap, hist, w, n_out);
+}
+
 int quapi_reset(quapi_ctx* c) {
     if (!c) return QUAPI_EINVAL;
     (void)hipStreamSynchronize(c->stream);
@@ -801,10 +880,11 @@ int quapi_info(quapi_ctx* c, quapi_info_t* out) {
     out->L = c->L;
     out->bits_per_point = c->bits;
     out->record_bytes = c->sparse ? (c->f32 ? 8 : 16) + 8 * c->sp_hw : 32;
-    out->capacity = c->sparse ? c->sp_cap : c->n_buckets * c->cap;
+    out->capacity = c->sparse ? c->sp_cap : c->inst_buckets * c->cap;
     out->device_bytes = c->device_bytes;
     out->precision = c->f32 ? QUAPI_FP32_LOG : QUAPI_FP64;
     out->hash_merge = c->sparse ? 1 : 0;
+    out->n_instances = c->n_inst;
     return QUAPI_OK;
 }
 

@@ -49,21 +49,29 @@ struct Plan {
 // desc[c] is the index, in the list of nonempty buckets, of the bucket that
 // holds group c*C.
 
+// Batched form: n_inst instances (bath parameter points) share one store; the
+// buckets of instance j are [j*P^D, (j+1)*P^D).  Each instance's groups start
+// at a multiple of the chunk size in the global group order, so that a chunk
+// never holds two instances, and an entry kNoBucket closes each instance in
+// the nonempty-bucket list (its prefix is the instance's end).
+constexpr unsigned int kNoBucket = 0xffffffffu;
+
 struct StepArgs {
     GroupBuf in, out;
-    unsigned int* out_count;        // [P^D] output bucket sizes (zeroed by the planner)
-    const unsigned int* nz_bucket;  // [n_nonempty] nonempty input buckets, in key order
+    unsigned int* out_count;        // [n_inst * P^D] output bucket sizes (zeroed by the planner)
+    const unsigned int* nz_bucket;  // [n_nonempty] nonempty input buckets, in key order (kNoBucket: an instance's end)
     const unsigned int* nz_prefix;  // [n_nonempty] their first global group index
     const unsigned int* desc;       // [n_chunks]
     const Plan* plan;               // this step's plan
     long long cap;                  // capacity of one bucket
     int P, L, K, t;
-    int n_super;                    // P^(D-1)
+    int n_super;                    // P^(D-1), per instance
+    int n_inst;                     // instances (1 unless batched)
     unsigned int epoch;             // step number of the context, tags the look-back words
     double theta2;
     unsigned long long qmask;       // keep-mask of the |w|^2 bit pattern
     const double* tables;           // device tables, see TableLayout
-    const double* coef;             // this step's coefficients: cre, cim, dre, dim [4][K+1]
+    const double* coef;             // this step's coefficients: cre, cim, dre, dim [n_inst][4][K+1]
     unsigned long long* chain;      // [P * max_chunks] look-back words, one per chunk and pair
     int max_chunks;
     double* partials;               // [partial_stride(P)][max_chunks], component-major
@@ -73,8 +81,8 @@ struct StepArgs {
 struct PlanArgs {
     const unsigned int* counts;     // [n_buckets] bucket sizes of the stored groups
     unsigned int* counts_next;      // [n_buckets] output bucket sizes of the planned step: zeroed here
-    unsigned int* nz_bucket;        // [n_buckets]
-    unsigned int* nz_prefix;        // [n_buckets]
+    unsigned int* nz_bucket;        // [n_buckets + n_inst]
+    unsigned int* nz_prefix;        // [n_buckets + n_inst]
     unsigned int* desc;             // [max_chunks]
     Plan* plan;                     // plan of the step to plan
     const Plan* plan_prev;          // plan of the step just done (for its counters)
@@ -83,9 +91,15 @@ struct PlanArgs {
     int P;
     int reduce_t;                   // step whose partials to reduce, 0: none
     const double* partials;
-    double2* rho_hist;              // [history * P]
-    StepStatsDev* stats_hist;       // [history]
+    double2* rho_hist;              // [history][n_inst][P]
+    StepStatsDev* stats_hist;       // [history][n_inst]
     const unsigned int* error;
+    // batched form
+    int n_inst;
+    int inst_buckets;               // P^D, at most the buckets one planner workgroup takes
+    unsigned long long* totals;     // [n_inst] (groups << 32) | nonempty buckets of the stored groups
+    unsigned int* inst_next;        // [n_inst][2] first chunk and groups of each instance, planned step
+    const unsigned int* inst_prev;  // [n_inst][2] the same for the step just done
 };
 
 // Device table layout (doubles): K4 re/im [2*P*P], ds[P], ss[P], eta [2*3*(K+1)]
@@ -101,8 +115,10 @@ enum : unsigned int { kErrNone = 0, kErrOverflow = 1, kErrSpin = 2 };
 
 int launch_step(const StepArgs& a, int grid, void* stream);   // returns hipError_t
 int launch_plan(const PlanArgs& a, void* stream);
+int launch_plan_batch(const PlanArgs& a, void* stream);   // two kernels: totals and reduce, then lists
+int plan_batch_max_buckets();                            // P^D of one instance at most
 int chunk_heads(int P);
 int plan_max_buckets();              // bucket count the planner is built for
-int step_grid(int P, int n_cu, int per_cu);   // persistent workgroups that are co-resident
+int step_grid(int P, int n_cu, int per_cu, bool batch);   // persistent workgroups that are co-resident
 
 }  // namespace quapi_dev

@@ -50,7 +50,9 @@ namespace {
 constexpr int kWaves = kThreads / 64;
 constexpr int kPlanThreads = 1024;
 constexpr int kPlanWaves = kPlanThreads / 64;
-constexpr int kWin = kThreads + 3;    // nonempty buckets cached per chunk (covers the groups around it too)
+// nonempty-bucket entries cached per chunk: the groups around it lie in at most
+// kThreads + 2 buckets, plus the ends of up to two instances in the batched form
+constexpr int kWin = kThreads + 6;
 constexpr int kTabPts = 2;            // points per subset-sum table (two-level systems)
 constexpr int kTabEntries = 16;       // 4^2
 constexpr int kMaxTabs = 16;
@@ -197,6 +199,172 @@ __global__ __launch_bounds__(kPlanThreads) void plan_kernel(const PlanArgs a) {
     }
 }
 
+// ------------------------------------------------------------------ batched planner
+// Instance j owns the buckets [j*IB, (j+1)*IB), IB = P^D <= kRegion; one
+// workgroup plans one instance.  Its groups start at chunk
+// sum_{r<j} ceil(n_r / C) of the global order, and its nonempty buckets at rank
+// sum_{r<j} (nz_r + 1): each instance's list ends with an entry kNoBucket whose
+// prefix is the instance's end, so that the positions up to the next chunk
+// boundary hold no group.  Two kernels: (1) each instance's totals, and the
+// reduction of the finished step per instance; (2) the lists.
+
+// thread i's kPlanPer buckets of instance w (zero past the instance)
+__device__ inline void batch_counts(const PlanArgs& a, int w, int i, unsigned int cnt[kPlanPer]) {
+    const long long lo = (long long)w * a.inst_buckets + (long long)i * kPlanPer;
+    const long long hi = (long long)(w + 1) * a.inst_buckets;
+#pragma unroll
+    for (int k = 0; k < kPlanPer; ++k) cnt[k] = lo + k < hi ? a.counts[lo + k] : 0u;
+}
+
+template <int P>
+__global__ __launch_bounds__(kPlanThreads) void plan_batch_totals(const PlanArgs a) {
+    constexpr int S = partial_stride(P);
+    constexpr unsigned int C = kThreads - (P - 1);
+    __shared__ unsigned long long wsum[kPlanWaves];
+    __shared__ double wred[kPlanWaves][S];
+    const int i = threadIdx.x;
+    const int wave = i >> 6;
+    const unsigned int lane = lane_id();
+    const int B = a.n_inst;
+    const int w = (int)blockIdx.x;
+
+    if (w >= B) {
+        // ---- counters and rho(t) of instance w - B in the step just finished, in chunk
+        //      order from the instance's first chunk (the order a lone instance has)
+        const int j = w - B;
+        if (a.reduce_t <= 0) return;
+        const unsigned int err = error_word(a.error);
+        if (err != 0u && (int)(err >> 4) <= a.reduce_t) return;
+        const unsigned int c0 = a.inst_prev[2 * j], ng = a.inst_prev[2 * j + 1];
+        const unsigned int nc = (ng + C - 1) / C;
+        double acc[S];
+#pragma unroll
+        for (int k = 0; k < S; ++k) acc[k] = 0.0;
+#pragma unroll 2
+        for (unsigned int c = i; c < nc; c += kPlanThreads)
+#pragma unroll
+            for (int k = 0; k < S; ++k) acc[k] += a.partials[(size_t)k * a.max_chunks + c0 + c];
+#pragma unroll
+        for (int k = 0; k < S; ++k) {
+            const double v = wave_sum(acc[k]);
+            if (lane == 0) wred[wave][k] = v;
+        }
+        __syncthreads();
+        if (i < S) {
+            double v = 0.0;
+            for (int q = 0; q < kPlanWaves; ++q) v += wred[q][i];
+            wred[0][i] = v;
+        }
+        __syncthreads();
+        if (i == 0) {
+            const size_t h = (size_t)a.reduce_t * B + j;
+#pragma unroll
+            for (int p = 0; p < P; ++p) a.rho_hist[h * P + p] = make_double2(wred[0][2 * p], wred[0][2 * p + 1]);
+            StepStatsDev* st = a.stats_hist + h;          // n_stored comes from the lists kernel
+            st->n_groups = ng;
+            st->n_children = (unsigned long long)ng * (unsigned long long)P;
+            st->n_survivors = (unsigned long long)wred[0][2 * P + 1];
+            st->dropped_abs = wred[0][2 * P];
+            st->pad = 0.0;
+        }
+        return;
+    }
+
+    // ---- instance w's totals
+    unsigned int cnt[kPlanPer];
+    batch_counts(a, w, i, cnt);
+    unsigned long long v = pack_sizes(cnt[0], cnt[1], cnt[2], cnt[3]);
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (lane == 0) wsum[wave] = v;
+    __syncthreads();
+    if (i == 0) {
+        unsigned long long t = 0;
+        for (int q = 0; q < kPlanWaves; ++q) t += wsum[q];
+        a.totals[w] = t;
+    }
+}
+
+template <int P>
+__global__ __launch_bounds__(kPlanThreads) void plan_batch_lists(const PlanArgs a) {
+    constexpr unsigned int C = kThreads - (P - 1);
+    __shared__ unsigned long long wsum[kPlanWaves];
+    __shared__ unsigned long long wpre[kPlanWaves];
+    const int i = threadIdx.x;
+    const int wave = i >> 6;
+    const unsigned int lane = lane_id();
+    const int B = a.n_inst;
+    const int w = (int)blockIdx.x;
+
+    // ---- where instance w starts: chunks and list entries of the instances before it
+    unsigned long long before = 0;                     // (chunks << 32) | list entries
+    for (int r = i; r < w; r += kPlanThreads) {
+        const unsigned long long tr = a.totals[r];
+        const unsigned int n = (unsigned int)(tr >> 32), nz = (unsigned int)tr;
+        before += ((unsigned long long)((n + C - 1) / C) << 32) + nz + 1u;
+    }
+    for (int off = 32; off > 0; off >>= 1) before += __shfl_xor(before, off, 64);
+
+    // ---- this instance's buckets: exclusive scan of (groups, nonempty)
+    unsigned int cnt[kPlanPer];
+    batch_counts(a, w, i, cnt);
+    const unsigned long long mine = pack_sizes(cnt[0], cnt[1], cnt[2], cnt[3]);
+    unsigned long long incl = mine;
+    for (int off = 1; off < 64; off <<= 1) {
+        const unsigned long long x = __shfl_up(incl, off, 64);
+        if ((int)lane >= off) incl += x;
+    }
+    if (lane == 63) wsum[wave] = incl;
+    if (lane == 0) wpre[wave] = before;
+    __syncthreads();
+    unsigned long long base = incl - mine, total = 0, pre = 0;
+    for (int q = 0; q < kPlanWaves; ++q) {
+        if (q < wave) base += wsum[q];
+        total += wsum[q];
+        pre += wpre[q];
+    }
+    const unsigned int g_start = (unsigned int)(pre >> 32) * C;    // first global group index
+    const unsigned int r_start = (unsigned int)pre;                // first list entry
+    const unsigned int n_w = (unsigned int)(total >> 32), nz_w = (unsigned int)total;
+
+    // ---- nonempty buckets; each chunk's first group lies in the one of rank desc[c]
+    unsigned int run = g_start + (unsigned int)(base >> 32), rank = r_start + (unsigned int)base;
+    const long long b_lo = (long long)w * a.inst_buckets + (long long)i * kPlanPer;
+#pragma unroll
+    for (int k = 0; k < kPlanPer; ++k) {
+        const unsigned int n = cnt[k];
+        if (n == 0u) continue;
+        a.nz_bucket[rank] = (unsigned int)(b_lo + k);
+        a.nz_prefix[rank] = run;
+        for (unsigned int c = (run + C - 1) / C; c * C < run + n; ++c)
+            if ((int)c < a.max_chunks) a.desc[c] = rank;
+        ++rank;
+        run += n;
+    }
+
+    // ---- zero the next step's bucket sizes of this instance
+    const long long hi = (long long)(w + 1) * a.inst_buckets;
+#pragma unroll
+    for (int k = 0; k < kPlanPer; ++k)
+        if (b_lo + k < hi) a.counts_next[b_lo + k] = 0u;
+
+    if (i == 0) {
+        // the entry that closes the instance, its extent, and the groups stored
+        a.nz_bucket[r_start + nz_w] = kNoBucket;
+        a.nz_prefix[r_start + nz_w] = g_start + n_w;
+        a.inst_next[2 * w] = g_start / C;
+        a.inst_next[2 * w + 1] = n_w;
+        if (a.reduce_t > 0) a.stats_hist[(size_t)a.reduce_t * B + w].n_stored = n_w;
+        if (w == B - 1) {
+            Plan pl;
+            pl.n_groups = g_start + n_w;
+            pl.n_chunks = (g_start + n_w + C - 1) / C;
+            pl.pad = 0u;
+            pl.n_nonempty = r_start + nz_w + 1u;
+            *a.plan = pl;
+        }
+    }
+}
+
 // ------------------------------------------------------------------ step
 template <int P>
 struct Lds {
@@ -219,6 +387,7 @@ struct Lds {
     double wdrop[kWaves];
     unsigned int wsurv[kWaves];
     unsigned int sig0, prev_sig;           // super-bucket of the first parent and of the group before
+    unsigned int chunk_inst;               // instance of the chunk fetched last (batched form)
     double e0, f0;
 };
 
@@ -260,7 +429,7 @@ __device__ inline int window_search(const Lds<P>& s, unsigned int g) {
     return lo;
 }
 
-template <int P, int C>
+template <int P, int C, bool BATCH>
 __device__ inline Parent fetch_parent(const StepArgs& a, const Lds<P>& s, unsigned int c, unsigned int N,
                                       unsigned int nrec, int i, unsigned int lane) {
     Parent r;
@@ -272,8 +441,9 @@ __device__ inline Parent fetch_parent(const StepArgs& a, const Lds<P>& s, unsign
     r.psig = 0xffffffffu;
     r.nsig = 0xffffffffu;
     const unsigned int g = c * (unsigned int)C + (unsigned int)i;
-    if (g < N) {
-        const int k = window_search(s, g);
+    const int k = g < N ? window_search(s, g) : 0;
+    // a position past an instance's end (batched form) holds no group
+    if (g < N && (!BATCH || s.win_b[k] != kNoBucket)) {
         const unsigned int b = s.win_b[k];
         const unsigned int o = b * (unsigned int)a.cap + (g - s.win_p[k]);   // the store has < 2^31 records
         if (o < nrec) {
@@ -289,15 +459,17 @@ __device__ inline Parent fetch_parent(const StepArgs& a, const Lds<P>& s, unsign
         if (lane == 0u && g > 0u) {
             const int kn = (g - 1u >= s.win_p[k] || k == 0) ? k : k - 1;
             const unsigned int bn = s.win_b[kn];
-            const unsigned int op = bn * (unsigned int)a.cap + (g - 1u - s.win_p[kn]);
-            if (op < nrec) {
-                r.pkey = a.in.key[op];
-                r.psig = bn / P;
+            if (!BATCH || (bn != kNoBucket && g - 1u >= s.win_p[kn])) {
+                const unsigned int op = bn * (unsigned int)a.cap + (g - 1u - s.win_p[kn]);
+                if (op < nrec) {
+                    r.pkey = a.in.key[op];
+                    r.psig = bn / P;
+                }
             }
         }
         if (lane == 63u && g + 1u < N) {
             const int kn = (k + 1 < kWin && g + 1u >= s.win_p[k + 1]) ? k + 1 : k;
-            r.nsig = s.win_b[kn] / P;
+            r.nsig = (BATCH && s.win_b[kn] == kNoBucket) ? 0xffffffffu : s.win_b[kn] / P;
         }
     }
     return r;
@@ -327,54 +499,23 @@ __device__ inline unsigned long long shfl_up1_u64(unsigned long long v) {
     return (unsigned long long)__shfl_up((long long)v, 1, 64);
 }
 
-template <int P, int BP>
-__global__ __launch_bounds__(kThreads, P == 4 ? 4 : 1) void step_kernel(const StepArgs a) {
-    constexpr int C = kThreads - (P - 1);              // segment heads per chunk
-    constexpr int S = partial_stride(P);
-    constexpr unsigned long long DM = (1ull << BP) - 1;
-    __shared__ Lds<P> s;
-    const int i = threadIdx.x;
-    const int wave = i >> 6;
-    const unsigned int lane = lane_id();
-
-    if (error_word(a.error) != 0u) return;             // an earlier step failed: leave the state alone
-    const unsigned int N = a.plan->n_groups;
-    const unsigned int n_chunks = a.plan->n_chunks;
-    const unsigned int n_nz = a.plan->n_nonempty;
-    const unsigned int G = gridDim.x;
-    unsigned int c = blockIdx.x;
-    if (c >= n_chunks) return;
-
-    // ---- the first chunk's window and the next one's, in flight during the set-up
-    const unsigned int nrec = (unsigned int)((long long)a.n_super * P * a.cap);
-    WinRegs wr = load_window(a, a.desc[c], n_nz, N, i);
-    WinRegs wn = {0u, 0u, 0u, 0u};
-    if (c + G < n_chunks) wn = load_window(a, a.desc[c + G], n_nz, N, i);
-    unsigned int d_after = (c + 2 * G < n_chunks) ? a.desc[c + 2 * G] : 0u;
-
-    // ---- tables and coefficients of this step
-    const int K = a.K, L = a.L, t = a.t;
-    for (int k = i; k < P * P; k += kThreads) {
-        s.k4re[k] = a.tables[2 * k];
-        s.k4im[k] = a.tables[2 * k + 1];
-    }
-    if (i < P) {
-        s.ds[i] = a.tables[TableLayout::ds(P) + i];
-        s.ss[i] = a.tables[TableLayout::ss(P) + i];
-    }
+// One instance's coefficients of this step into the LDS.
+template <int P>
+__device__ inline void load_coefficients(Lds<P>& s, const double* coef, int K, int i) {
     for (int k = i; k < 4 * (K + 1); k += kThreads) {
         const int r = k / (K + 1), d = k - r * (K + 1);
         double* dst = r == 0 ? s.cre : r == 1 ? s.cim : r == 2 ? s.dre : s.dim;
-        dst[d] = a.coef[k];
+        dst[d] = coef[k];
     }
-    const int nk = (L + kTabPts - 1) / kTabPts, nt = (K - L + kTabPts - 1) / kTabPts;
-    const bool use_tabs = (P == 4) && (nk + nt <= kMaxTabs);
-    store_window(s, wr, i);
-    __syncthreads();
-    Parent cur = fetch_parent<P, C>(a, s, c, N, nrec, i, lane);
+}
+
+// Subset-sum tables of the coefficients in the LDS (two levels):
+// tab[q][v] = sum over the points of table q of coefficient(lag) * (ds, ss)(point).
+template <int P, int BP>
+__device__ inline void build_tables(Lds<P>& s, int K, int L, int nk, int nt, bool use_tabs, int i) {
+    constexpr unsigned long long DM = (1ull << BP) - 1;
     if constexpr (P == 4) {
         if (use_tabs) {
-            // tab[q][v] = sum over the points of table q of coefficient(lag) * (ds, ss)(point)
             for (int idx = i; idx < (nk + nt) * kTabEntries; idx += kThreads) {
                 const int q = idx / kTabEntries, v = idx - q * kTabEntries;
                 const bool in_key = q < nk;
@@ -404,6 +545,55 @@ __global__ __launch_bounds__(kThreads, P == 4 ? 4 : 1) void step_kernel(const St
             s.f0 = exp(-D * D * s.dre[0]);
         }
     }
+}
+
+// BATCH: the batched form (several instances; chunks reload the coefficients of
+// their instance, and positions past an instance's end hold no group)
+template <int P, int BP, bool BATCH>
+__global__ __launch_bounds__(kThreads, P == 4 ? 4 : 1) void step_kernel(const StepArgs a) {
+    constexpr int C = kThreads - (P - 1);              // segment heads per chunk
+    constexpr int S = partial_stride(P);
+    constexpr unsigned long long DM = (1ull << BP) - 1;
+    __shared__ Lds<P> s;
+    const int i = threadIdx.x;
+    const int wave = i >> 6;
+    const unsigned int lane = lane_id();
+
+    if (error_word(a.error) != 0u) return;             // an earlier step failed: leave the state alone
+    const unsigned int N = a.plan->n_groups;
+    const unsigned int n_chunks = a.plan->n_chunks;
+    const unsigned int n_nz = a.plan->n_nonempty;
+    const unsigned int G = gridDim.x;
+    unsigned int c = blockIdx.x;
+    if (c >= n_chunks) return;
+
+    // ---- the first chunk's window and the next one's, in flight during the set-up
+    const unsigned int nrec = (unsigned int)((long long)a.n_super * P * a.cap * a.n_inst);
+    WinRegs wr = load_window(a, a.desc[c], n_nz, N, i);
+    WinRegs wn = {0u, 0u, 0u, 0u};
+    if (c + G < n_chunks) wn = load_window(a, a.desc[c + G], n_nz, N, i);
+    unsigned int d_after = (c + 2 * G < n_chunks) ? a.desc[c + 2 * G] : 0u;
+
+    // ---- tables and coefficients of this step
+    const int K = a.K, L = a.L, t = a.t;
+    for (int k = i; k < P * P; k += kThreads) {
+        s.k4re[k] = a.tables[2 * k];
+        s.k4im[k] = a.tables[2 * k + 1];
+    }
+    if (i < P) {
+        s.ds[i] = a.tables[TableLayout::ds(P) + i];
+        s.ss[i] = a.tables[TableLayout::ss(P) + i];
+    }
+    load_coefficients(s, a.coef, K, i);              // instance 0; a chunk of another reloads
+    unsigned int loaded = 0u;
+    const int nk = (L + kTabPts - 1) / kTabPts, nt = (K - L + kTabPts - 1) / kTabPts;
+    const bool use_tabs = (P == 4) && (nk + nt <= kMaxTabs);
+    store_window(s, wr, i);
+    __syncthreads();
+    Parent cur = fetch_parent<P, C, BATCH>(a, s, c, N, nrec, i, lane);
+    // a chunk's first group is always one; its instance picks the coefficients
+    if (BATCH && i == 0) s.chunk_inst = cur.sig == 0xffffffffu ? 0u : cur.sig / (unsigned int)a.n_super;
+    build_tables<P, BP>(s, K, L, nk, nt, use_tabs, i);
 
     const int dmax = t < K ? t : K;
     const int tail_pts = K - L;
@@ -419,10 +609,23 @@ __global__ __launch_bounds__(kThreads, P == 4 ? 4 : 1) void step_kernel(const St
         const bool has_next = c + G < n_chunks;
         Parent nxt = cur;
         __syncthreads();                                   // the chunk before is done with the LDS
+        // this chunk's instance: its coefficients and tables unless they are in the LDS
+        unsigned int ob_base = 0u;                         // output bucket offset of the instance
+        if constexpr (BATCH) {
+            const unsigned int inst = s.chunk_inst;
+            if (inst != loaded) {
+                load_coefficients(s, a.coef + (size_t)inst * 4 * (K + 1), K, i);
+                __syncthreads();
+                build_tables<P, BP>(s, K, L, nk, nt, use_tabs, i);
+                loaded = inst;
+            }
+            ob_base = inst * (unsigned int)(P - 1) * (unsigned int)a.n_super;
+        }
         if (has_next) {
             store_window(s, wn, i);
-            __syncthreads();
-            nxt = fetch_parent<P, C>(a, s, c + G, N, nrec, i, lane);
+            __syncthreads();                               // (also publishes the tables)
+            nxt = fetch_parent<P, C, BATCH>(a, s, c + G, N, nrec, i, lane);
+            if (BATCH && i == 0) s.chunk_inst = nxt.sig == 0xffffffffu ? 0u : nxt.sig / (unsigned int)a.n_super;
             if (c + 2 * G < n_chunks) wn = load_window(a, d_after, n_nz, N, i);
             d_after = (c + 3 * G < n_chunks) ? a.desc[c + 3 * G] : 0u;
         }
@@ -442,7 +645,9 @@ __global__ __launch_bounds__(kThreads, P == 4 ? 4 : 1) void step_kernel(const St
         const unsigned long long pk = lane == 0u ? cur.pkey : up_key;
         const unsigned int psg = lane == 0u ? cur.psig : up_sig;
         const unsigned int nsg = lane == 63u ? cur.nsig : dn_sig;
-        const bool head = valid && (g0 + i == 0u || (key >> BP) != (pk >> BP));
+        // (parents with equal points 0..L-2 share the super-bucket; across
+        // instances of the batched form they do not)
+        const bool head = valid && (g0 + i == 0u || (key >> BP) != (pk >> BP) || (BATCH && my_sig != psg));
         const bool rstart = valid && (i == 0 || my_sig != psg);
         const unsigned long long hm = __ballot(head), vm = __ballot(valid), rsm = __ballot(rstart);
         if (lane == 0u) {
@@ -680,7 +885,7 @@ __global__ __launch_bounds__(kThreads, P == 4 ? 4 : 1) void step_kernel(const St
         // ---- publish the totals of the last run for the chunk after this one: inclusive
         //      now unless the last run is the continued first run
         const bool first_cont = g0 > 0u && s.prev_sig == s.sig0;
-        const bool next_cont = (i == H - 1) && (c + 1 < n_chunks) && nsg == my_sig;
+        const bool next_cont = (!BATCH || valid) && (i == H - 1) && (c + 1 < n_chunks) && nsg == my_sig;
         const bool from_prev = (start == 0) && first_cont;
         unsigned long long* const slot_c = a.chain + c;
         if (next_cont) {
@@ -746,6 +951,7 @@ __global__ __launch_bounds__(kThreads, P == 4 ? 4 : 1) void step_kernel(const St
         }
 
         // ---- write merged groups to the output buckets (p, sigma)
+        const unsigned int n_out_buckets = (unsigned int)a.n_inst * (unsigned int)P * (unsigned int)a.n_super;
         if (is_head) {
 #pragma unroll
             for (int p = 0; p < P; ++p) {
@@ -755,20 +961,26 @@ __global__ __launch_bounds__(kThreads, P == 4 ? 4 : 1) void step_kernel(const St
                     raise_error(a.error, t, kErrOverflow);
                     continue;
                 }
-                const unsigned int o = ((unsigned int)p * (unsigned int)a.n_super + my_sig) * (unsigned int)a.cap + idx;
+                const unsigned int ob = (unsigned int)p * (unsigned int)a.n_super + my_sig + ob_base;
+                if (BATCH && ob >= n_out_buckets) {              // a head outside its chunk's instance
+                    raise_error(a.error, t, kErrSpin);
+                    continue;
+                }
+                const unsigned int o = ob * (unsigned int)a.cap + idx;
                 a.out.key[o] = ((unsigned long long)p << top_shift) | (key >> BP);
                 a.out.tail[o] = otail[p];
                 a.out.w[o] = ow[p];
             }
         }
         // bucket sizes: the last parent of each run that ends in this chunk records the totals
-        if (i < H && ((i == H - 1) ? !next_cont : (nsg != my_sig))) {
+        if ((!BATCH || valid) && i < H && ((i == H - 1) ? !next_cont : (nsg != my_sig))) {
 #pragma unroll
             for (int p = 0; p < P; ++p) {
                 const unsigned int tot = my_excl[p] + (ov[p] ? 1u : 0u) - run_base[p] +
                                          (from_prev ? s.base[p] : 0u);
-                if (tot) a.out_count[(unsigned int)p * (unsigned int)a.n_super + my_sig] =
-                             tot > (unsigned int)a.cap ? (unsigned int)a.cap : tot;
+                const unsigned int ob = (unsigned int)p * (unsigned int)a.n_super + my_sig + ob_base;
+                if (tot && (!BATCH || ob < n_out_buckets))
+                    a.out_count[ob] = tot > (unsigned int)a.cap ? (unsigned int)a.cap : tot;
             }
         }
         if (!has_next) break;
@@ -783,11 +995,13 @@ int chunk_heads(int P) { return kThreads - (P - 1); }
 
 int plan_max_buckets() { return 64 * kRegion; }
 
-int step_grid(int P, int n_cu, int per_cu) {
+int step_grid(int P, int n_cu, int per_cu, bool batch) {
     int nb = 0;
     hipError_t e = hipErrorInvalidValue;
-    if (P == 4) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_kernel<4, 2>, kThreads, 0);
-    if (P == 9) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_kernel<9, 4>, kThreads, 0);
+    if (P == 4 && !batch) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_kernel<4, 2, false>, kThreads, 0);
+    if (P == 4 && batch) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_kernel<4, 2, true>, kThreads, 0);
+    if (P == 9 && !batch) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_kernel<9, 4, false>, kThreads, 0);
+    if (P == 9 && batch) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_kernel<9, 4, true>, kThreads, 0);
     if (e != hipSuccess || nb < 1) return 0;
     // the look-back waits on other workgroups: every workgroup of the grid must be resident
     return (per_cu > 0 ? (per_cu < nb ? per_cu : nb) : nb) * n_cu;
@@ -796,9 +1010,35 @@ int step_grid(int P, int n_cu, int per_cu) {
 int launch_step(const StepArgs& a, int grid, void* stream) {
 
     hipStream_t st = (hipStream_t)stream;
+    const bool batch = a.n_inst > 1;
     switch (a.P) {
-        case 4: hipLaunchKernelGGL((step_kernel<4, 2>), dim3(grid), dim3(kThreads), 0, st, a); break;
-        case 9: hipLaunchKernelGGL((step_kernel<9, 4>), dim3(grid), dim3(kThreads), 0, st, a); break;
+        case 4:
+            if (batch) hipLaunchKernelGGL((step_kernel<4, 2, true>), dim3(grid), dim3(kThreads), 0, st, a);
+            else hipLaunchKernelGGL((step_kernel<4, 2, false>), dim3(grid), dim3(kThreads), 0, st, a);
+            break;
+        case 9:
+            if (batch) hipLaunchKernelGGL((step_kernel<9, 4, true>), dim3(grid), dim3(kThreads), 0, st, a);
+            else hipLaunchKernelGGL((step_kernel<9, 4, false>), dim3(grid), dim3(kThreads), 0, st, a);
+            break;
+        default: return (int)hipErrorInvalidValue;
+    }
+    return (int)hipGetLastError();
+}
+
+int plan_batch_max_buckets() { return kRegion; }
+
+int launch_plan_batch(const PlanArgs& a, void* stream) {
+    hipStream_t st = (hipStream_t)stream;
+    const int B = a.n_inst;
+    switch (a.P) {
+        case 4:
+            hipLaunchKernelGGL((plan_batch_totals<4>), dim3(2 * B), dim3(kPlanThreads), 0, st, a);
+            hipLaunchKernelGGL((plan_batch_lists<4>), dim3(B), dim3(kPlanThreads), 0, st, a);
+            break;
+        case 9:
+            hipLaunchKernelGGL((plan_batch_totals<9>), dim3(2 * B), dim3(kPlanThreads), 0, st, a);
+            hipLaunchKernelGGL((plan_batch_lists<9>), dim3(B), dim3(kPlanThreads), 0, st, a);
+            break;
         default: return (int)hipErrorInvalidValue;
     }
     return (int)hipGetLastError();

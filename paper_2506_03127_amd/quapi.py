@@ -52,7 +52,7 @@ class quapi_info_t(ctypes.Structure):
     _fields_ = [("M", ctypes.c_int), ("P", ctypes.c_int), ("K", ctypes.c_int), ("L", ctypes.c_int),
                 ("bits_per_point", ctypes.c_int), ("record_bytes", ctypes.c_int),
                 ("capacity", ctypes.c_longlong), ("device_bytes", ctypes.c_size_t),
-                ("precision", ctypes.c_int), ("hash_merge", ctypes.c_int)]
+                ("precision", ctypes.c_int), ("hash_merge", ctypes.c_int), ("n_instances", ctypes.c_int)]
 
 
 class quapi_bath(ctypes.Structure):
@@ -85,6 +85,10 @@ def lib() -> ctypes.CDLL:
         L.quapi_rho_history.argtypes = [vp, ci, ci, vp]
         L.quapi_step_stats.argtypes = [vp, ci, ci, vp]
         L.quapi_groups.argtypes = [vp, cll, vp, vp, ctypes.POINTER(cll)]
+        L.quapi_create_batch.argtypes = [ctypes.POINTER(quapi_params), ci, vp, ctypes.POINTER(vp)]
+        L.quapi_batch_rho_history.argtypes = [vp, ci, ci, ci, vp]
+        L.quapi_batch_step_stats.argtypes = [vp, ci, ci, ci, vp]
+        L.quapi_batch_groups.argtypes = [vp, ci, cll, vp, vp, ctypes.POINTER(cll)]
         L.quapi_reset.argtypes = [vp]
         L.quapi_info.argtypes = [vp, ctypes.POINTER(quapi_info_t)]
         L.quapi_stream.restype = vp
@@ -123,12 +127,13 @@ def _c128(a, shape=None):
 
 
 # ------------------------------------------------------------------ C ABI, one to one
-def quapi_create(H, q, dt, dk_max, eta, rho0, mask=None, theta=0.0, mode=QUAPI_PRE, qbits=-1,
-                 max_groups=0, max_steps=0, stream=None, precision=QUAPI_FP64) -> int:
+def _params(H, q, dt, dk_max, eta, rho0, mask, theta, mode, qbits, max_groups, max_steps, stream,
+            precision):
+    """quapi_params and the arrays its pointers refer to (kept alive by the caller)."""
     H = _c128(H)
     M = H.shape[0]
     q = np.ascontiguousarray(np.asarray(q, dtype=np.float64))
-    eta = _c128(eta, (3, int(dk_max) + 1))
+    eta = None if eta is None else _c128(eta, (3, int(dk_max) + 1))
     rho0 = _c128(rho0, (M, M))
     m = None if mask is None else np.ascontiguousarray(np.asarray(mask, dtype=np.int32))
     p = quapi_params()
@@ -137,7 +142,7 @@ def quapi_create(H, q, dt, dk_max, eta, rho0, mask=None, theta=0.0, mode=QUAPI_P
     p.q = q.ctypes.data
     p.dt = float(dt)
     p.dk_max = int(dk_max)
-    p.eta = eta.ctypes.data
+    p.eta = None if eta is None else eta.ctypes.data
     p.mask = None if m is None else m.ctypes.data
     p.n_mask = 0 if m is None else len(m)
     p.theta = float(theta)
@@ -148,8 +153,28 @@ def quapi_create(H, q, dt, dk_max, eta, rho0, mask=None, theta=0.0, mode=QUAPI_P
     p.max_steps = int(max_steps)
     p.stream = None if stream is None else int(stream)
     p.precision = int(precision)
+    return p, (H, q, eta, rho0, m)
+
+
+def quapi_create(H, q, dt, dk_max, eta, rho0, mask=None, theta=0.0, mode=QUAPI_PRE, qbits=-1,
+                 max_groups=0, max_steps=0, stream=None, precision=QUAPI_FP64) -> int:
+    p, keep = _params(H, q, dt, dk_max, eta, rho0, mask, theta, mode, qbits, max_groups, max_steps,
+                      stream, precision)
     h = ctypes.c_void_p()
     _check(lib().quapi_create(ctypes.byref(p), ctypes.byref(h)), "quapi_create")
+    return h.value
+
+
+def quapi_create_batch(H, q, dt, dk_max, etas, rho0, mask=None, theta=0.0, mode=QUAPI_PRE, qbits=-1,
+                       max_groups=0, max_steps=0, stream=None) -> int:
+    """etas: (n_inst, 3, dk_max + 1) complex, one eta table per instance."""
+    etas = _c128(etas)
+    etas = etas.reshape(-1, 3, int(dk_max) + 1)
+    p, keep = _params(H, q, dt, dk_max, None, rho0, mask, theta, mode, qbits, max_groups, max_steps,
+                      stream, QUAPI_FP64)
+    h = ctypes.c_void_p()
+    _check(lib().quapi_create_batch(ctypes.byref(p), int(etas.shape[0]), etas.ctypes.data, ctypes.byref(h)),
+           "quapi_create_batch")
     return h.value
 
 
@@ -192,6 +217,29 @@ def quapi_groups(ctx, K: int):
     w = np.zeros(max(n.value, 1), dtype=np.complex128)
     _check(lib().quapi_groups(ctx, n.value, hist.ctypes.data, w.ctypes.data, ctypes.byref(n)),
            "quapi_groups")
+    return hist[:n.value], w[:n.value]
+
+
+def quapi_batch_rho_history(ctx, inst: int, t0: int, n: int, M: int) -> np.ndarray:
+    out = np.zeros((n, M, M), dtype=np.complex128)
+    _check(lib().quapi_batch_rho_history(ctx, int(inst), int(t0), int(n), out.ctypes.data),
+           "quapi_batch_rho_history")
+    return out
+
+
+def quapi_batch_step_stats(ctx, inst: int, t0: int, n: int) -> list:
+    arr = (quapi_stepstat_t * max(n, 1))()
+    _check(lib().quapi_batch_step_stats(ctx, int(inst), int(t0), int(n), arr), "quapi_batch_step_stats")
+    return [{k: getattr(arr[i], k) for k, _ in quapi_stepstat_t._fields_} for i in range(n)]
+
+
+def quapi_batch_groups(ctx, inst: int, K: int):
+    n = ctypes.c_longlong()
+    _check(lib().quapi_batch_groups(ctx, int(inst), 0, None, None, ctypes.byref(n)), "quapi_batch_groups")
+    hist = np.zeros((max(n.value, 1), K), dtype=np.uint8)
+    w = np.zeros(max(n.value, 1), dtype=np.complex128)
+    _check(lib().quapi_batch_groups(ctx, int(inst), n.value, hist.ctypes.data, w.ctypes.data, ctypes.byref(n)),
+           "quapi_batch_groups")
     return hist[:n.value], w[:n.value]
 
 
@@ -284,6 +332,54 @@ class Propagator:
 
     def groups(self):
         return quapi_groups(self.ctx, self.K)
+
+    def reset(self):
+        quapi_reset(self.ctx)
+
+    def info(self):
+        return quapi_info(self.ctx)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            quapi_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class BatchPropagator:
+    """Owns one batched context: n_inst instances with their own eta tables."""
+
+    def __init__(self, H, q, dt, dk_max, etas, rho0, **kw):
+        self.M = np.asarray(H).shape[0]
+        self.K = int(dk_max)
+        self.n_inst = int(np.asarray(etas).reshape(-1, 3, self.K + 1).shape[0])
+        self.ctx = quapi_create_batch(H, q, dt, dk_max, etas, rho0, **kw)
+
+    def step(self, n=1):
+        quapi_step(self.ctx, n)
+
+    def sync(self):
+        quapi_sync(self.ctx)
+
+    @property
+    def t(self) -> int:
+        return quapi_time(self.ctx)
+
+    def rho_history(self, inst, t0=0, n=None):
+        n = quapi_time(self.ctx) + 1 - t0 if n is None else n
+        return quapi_batch_rho_history(self.ctx, inst, t0, n, self.M)
+
+    def stats(self, inst, t0=1, n=None):
+        n = quapi_time(self.ctx) + 1 - t0 if n is None else n
+        return quapi_batch_step_stats(self.ctx, inst, t0, n)
+
+    def groups(self, inst):
+        return quapi_batch_groups(self.ctx, inst, self.K)
 
     def reset(self):
         quapi_reset(self.ctx)

@@ -98,6 +98,24 @@ def long_memory(n_steps: int = 1000) -> Workload:
                     n_steps=n_steps, mode="pre")
 
 
+def batched_scan(n_inst: int = 64, seed: int = 11, n_steps: int = 1000, K: int = 24, n_exact: int = 12,
+                 theta: float = 1e-8) -> Tuple[Workload, Tuple[BathSpec, ...]]:
+    """The structured bath at n_inst bath parameter points: peak frequency w0
+    uniform in [0.5, 2.0] and width gamma drawn from {0.02, 0.05, 0.1} (seeded);
+    everything else as `structured_bath`.  Returns the shared workload (its bath
+    is the first point's) and the points' baths."""
+    rng = np.random.default_rng(seed)
+    w0 = rng.uniform(0.5, 2.0, n_inst)
+    gam = rng.choice(np.array([0.02, 0.05, 0.1]), n_inst)
+    base = structured_bath(n_steps=n_steps, K=K, n_exact=n_exact, theta=theta)
+    baths = tuple(BathSpec(base.bath.ohmic_alpha, base.bath.ohmic_wc, ((float(a), float(g), 0.1),))
+                  for a, g in zip(w0, gam))
+    wl = Workload(name=f"batched_scan_{n_inst}x_structured_bath_K{K}_E{n_exact}", H=base.H, q=base.q,
+                  bath=baths[0], beta=base.beta, dt=base.dt, K=K, mask=base.mask, theta=theta,
+                  rho0=base.rho0, n_steps=n_steps, mode="pre")
+    return wl, baths
+
+
 def three_level(seed: int = 7, K: int = 16, n_exact: int = 6, theta: float = 1e-8,
                 n_steps: int = 200) -> Workload:
     """Three-level system with a seeded random Hermitian H_S (entries ~ N(0, 0.5))."""

@@ -1,0 +1,139 @@
+"""The batched form (quapi_create_batch): several instances -- bath parameter
+points -- propagated by one step-kernel launch per time step.
+
+Each instance's groups start at a chunk boundary and reduce in the order a
+lone instance has, so every instance must equal, bit for bit, a context made
+by quapi_create on its own eta with the same bucket depth (rho(t), counters
+and stored groups), and through it the oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2506_03127_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+RHO_TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def Q():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2506_03127_amd import quapi
+    quapi.lib()
+    return quapi
+
+
+def _etas(Q, wl, baths, K):
+    """One eta table per bath from the library's generator (pinned against the
+    oracle's quadrature in the CPU tests); both sides of every comparison here
+    take the same tables."""
+    return np.stack([Q.quapi_eta(b.ohmic_alpha, b.ohmic_wc, [x for pk in b.peaks for x in pk], wl.beta, wl.dt, K)
+                     for b in baths])
+
+
+def _singles_like(Q, monkeypatch, g, wl, etas, K, mode, **kw):
+    """Lone contexts with the batch's bucket depth (the batched form caps a
+    super-bucket count per instance at 4096 / P)."""
+    monkeypatch.setenv("QUAPI_MAX_SUPER", str(4096 // (wl.M * wl.M)))
+    return [Q.Propagator(wl.H, wl.q, wl.dt, K, e, wl.rho0, mask=wl.mask, theta=wl.theta, mode=mode, **kw)
+            for e in etas]
+
+
+def _assert_same(Q, g, singles, n, insts=None):
+    for j, s in enumerate(singles):
+        inst = j if insts is None else insts[j]
+        rb, rs = g.rho_history(inst, 0, n + 1), s.rho_history(0, n + 1)
+        assert np.array_equal(rb, rs), (inst, np.abs(rb - rs).max())
+        assert g.stats(inst, 1, n) == s.stats(1, n), inst
+        hb, wb = g.groups(inst)
+        hs, ws = s.groups()
+        assert np.array_equal(hb, hs) and np.array_equal(wb, ws), inst
+
+
+@pytest.mark.parametrize("mode", ["pre", "post"])
+def test_batch_equals_lone_instances(Q, monkeypatch, mode):
+    wl, baths = W.batched_scan(n_inst=5, seed=3, K=12, n_exact=6, theta=1e-7)
+    K, n = 12, 60
+    etas = _etas(Q, wl, baths, K)
+    mq = Q.QUAPI_PRE if mode == "pre" else Q.QUAPI_POST
+    print(f"[batch] 5 instances K={K} mode={mode} n={n}", flush=True)
+    g = Q.BatchPropagator(wl.H, wl.q, wl.dt, K, etas, wl.rho0, mask=wl.mask, theta=wl.theta, mode=mq)
+    assert g.info()["n_instances"] == 5
+    singles = _singles_like(Q, monkeypatch, g, wl, etas, K, mq)
+    g.step(n)
+    for s in singles:
+        s.step(n)
+    _assert_same(Q, g, singles, n)
+    # and the oracle, for two of them
+    for j in (0, 3):
+        o = oracle.Oracle(wl.H, wl.q, wl.dt, K, etas[j], wl.rho0, mask=wl.mask, theta=wl.theta,
+                          mode=oracle.PRE if mode == "pre" else oracle.POST)
+        o.step(n)
+        assert sum(o.stats(t)["n_amb_rep"] + o.stats(t)["n_amb_theta"] for t in range(1, n + 1)) == 0
+        assert np.abs(g.rho_history(j, 0, n + 1) - o.rho_history()).max() < RHO_TOL
+
+
+def test_batch_uneven_instances(Q, monkeypatch):
+    """Instances of very different size: a strongly coupled bath (few groups
+    survive theta) beside weakly coupled ones, and chunk-sized instances."""
+    wl, _ = W.batched_scan(n_inst=1, K=14, n_exact=9, theta=1e-5)
+    K, n = 14, 30
+    baths = [W.BathSpec(a, 5.0, ((w0, gam, lam),)) for a, w0, gam, lam in
+             [(0.05, 1.0, 0.05, 0.1), (2.0, 1.0, 0.05, 2.0), (0.01, 0.5, 0.1, 0.01), (0.5, 2.0, 0.02, 0.5)]]
+    etas = _etas(Q, wl, baths, K)
+    print(f"[batch] uneven instances K={K} n={n}", flush=True)
+    g = Q.BatchPropagator(wl.H, wl.q, wl.dt, K, etas, wl.rho0, mask=wl.mask, theta=wl.theta)
+    singles = _singles_like(Q, monkeypatch, g, wl, etas, K, Q.QUAPI_PRE)
+    g.step(n)
+    for s in singles:
+        s.step(n)
+    sizes = [g.stats(j, n, 1)[0]["n_groups"] for j in range(4)]
+    print(f"[batch] groups per instance at step {n}: {sizes}", flush=True)
+    assert max(sizes) > 4 * min(sizes)
+    _assert_same(Q, g, singles, n)
+
+
+def test_batch_full_size_sampled(Q, monkeypatch):
+    """64 instances of the structured bath (dk_max 24, lags 0..11, theta 1e-8)
+    as the benchmark runs them; three sampled instances against lone contexts."""
+    wl, baths = W.batched_scan(n_inst=64)
+    K, n = wl.K, 24
+    etas = _etas(Q, wl, baths, K)
+    print(f"[batch] 64 instances K={K} n={n}", flush=True)
+    g = Q.BatchPropagator(wl.H, wl.q, wl.dt, K, etas, wl.rho0, mask=wl.mask, theta=wl.theta)
+    pick = [0, 37, 63]
+    singles = _singles_like(Q, monkeypatch, g, wl, etas[pick], K, Q.QUAPI_PRE)
+    g.step(n)
+    for s in singles:
+        s.step(n)
+    _assert_same(Q, g, singles, n, insts=pick)
+    total = sum(g.stats(j, n, 1)[0]["n_groups"] for j in range(64))
+    print(f"[batch] groups at step {n}, all instances: {total}", flush=True)
+    for j in range(64):
+        assert abs(np.trace(g.rho_history(j, n, 1)[0]).real - 1.0) < 1e-3
+
+
+def test_batch_capacity_overflow_and_reset(Q):
+    # lags 0..7 exact: 4^7 keys per instance over 4^5 buckets of one group each
+    wl, baths = W.batched_scan(n_inst=3, K=12, n_exact=8, theta=0.0)
+    K = 12
+    etas = _etas(Q, wl, baths, K)
+    g = Q.BatchPropagator(wl.H, wl.q, wl.dt, K, etas, wl.rho0, mask=wl.mask, theta=0.0, max_groups=1024)
+    g.step(12)
+    with pytest.raises(Q.QuapiError) as e:
+        g.sync()
+    assert e.value.code == Q.QUAPI_ENOMEM
+    t = Q.quapi_time(g.ctx)
+    for j in range(3):
+        o = oracle.Oracle(wl.H, wl.q, wl.dt, K, etas[j], wl.rho0, mask=wl.mask, theta=0.0, mode=oracle.PRE)
+        o.step(t)
+        assert np.abs(g.rho_history(j, 0, t + 1) - o.rho_history()).max() < RHO_TOL
+    g.reset()
+    g.step(3)
+    o = oracle.Oracle(wl.H, wl.q, wl.dt, K, etas[1], wl.rho0, mask=wl.mask, theta=0.0, mode=oracle.PRE)
+    o.step(3)
+    assert np.abs(g.rho_history(1, 0, 4) - o.rho_history()).max() < RHO_TOL

@@ -100,6 +100,29 @@ def test_create_rejects_invalid_input_without_device(Q):
     assert _create_code(Q, H=H4, q=[1, 0.5, -0.5, -1], rho0=W.ground_projector(4)) == Q.QUAPI_EUNSUPPORTED
 
 
+def _create_batch_code(Q, n_inst=2, **over):
+    wl = W.structured_bath(K=8, n_exact=4)
+    args = dict(H=wl.H, q=wl.q, dt=wl.dt, dk_max=wl.K, etas=np.zeros((n_inst, 3, wl.K + 1)), rho0=wl.rho0,
+                mask=wl.mask, theta=0.0, mode=Q.QUAPI_PRE)
+    args.update(over)
+    try:
+        ctx = Q.quapi_create_batch(**args)
+    except Q.QuapiError as e:
+        return e.code
+    Q.quapi_destroy(ctx)
+    return 0
+
+
+def test_create_batch_rejects_invalid_input_without_device(Q):
+    assert _create_batch_code(Q, n_inst=0) == Q.QUAPI_EINVAL
+    assert _create_batch_code(Q, n_inst=1025) == Q.QUAPI_EINVAL
+    etas = np.zeros((3, 3, 9), dtype=complex)
+    etas[2, 1, 4] = np.inf                              # the last instance's table
+    assert _create_batch_code(Q, n_inst=3, etas=etas) == Q.QUAPI_EINVAL
+    assert _create_batch_code(Q, mask=[0, 1, 3]) == Q.QUAPI_EUNSUPPORTED   # hash-table merge
+    assert _create_batch_code(Q, mode=9) == Q.QUAPI_EINVAL
+
+
 def test_strerror_names_every_code(Q):
     names = {Q.strerror(c) for c in (0, -1, -2, -3, -4, -5)}
     assert len(names) == 6 and "unknown error" not in names
