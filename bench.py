@@ -18,6 +18,11 @@ and the CPU oracle timed on a bounded sample of the same workload.
 work: a kernel of known traffic against which the PMC byte counters of a
 profiled run are scaled.
 
+--workload batched-scan measures the batched form: the structured bath at 64
+bath parameter points (peak frequency w0 uniform in [0.5, 2], width gamma in
+{0.02, 0.05, 0.1}, seeded), all propagated together for 1000 steps, one
+step-kernel launch per time step; value counts the path-steps of all of them.
+
 --workload long-memory measures the long-memory configuration instead: the
 same structured bath with dk_max = 40, theta = 1e-9, the mask keeping lags
 0..11 exact and lags 16, 24 and 32 of the tail (80-bit histories, hash-table
@@ -52,6 +57,10 @@ WORKLOADS = {
         "kernel": "step_kernel", "kernel_label": "step_kernel<4,2>",
         "sources": [CSRC + "quapi_step.hip", CSRC + "quapi_device.h", CSRC + "quapi_host.h"],
         "traffic": "step_kernel_traffic.json", "cpu_steps": 22, "max_groups": 0},
+    "batched-scan": {
+        "kernel": "step_kernel", "kernel_label": "step_kernel<4,2,batched>",
+        "sources": [CSRC + "quapi_step.hip", CSRC + "quapi_device.h", CSRC + "quapi_host.h"],
+        "traffic": "step_kernel_batched_scan_traffic.json", "cpu_steps": 22, "max_groups": 0},
     "long-memory": {
         "kernel": "sparse_expand", "kernel_label": "sparse_expand<4,2,2>",
         "sources": [CSRC + "quapi_sparse.hip", CSRC + "quapi_sparse.h", CSRC + "quapi_device.h",
@@ -195,23 +204,41 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    wl = workloads.structured_bath() if args.workload == "structured-bath" else workloads.long_memory()
-    b = wl.bath
-    peaks = [x for pk in b.peaks for x in pk]
-    eta = quapi.quapi_eta(b.ohmic_alpha, b.ohmic_wc, peaks, wl.beta, wl.dt, wl.K)
+    def eta_of(b, K):
+        return quapi.quapi_eta(b.ohmic_alpha, b.ohmic_wc, [x for pk in b.peaks for x in pk], wl.beta, wl.dt, K)
+
     stream = torch.cuda.Stream()
     precision = quapi.QUAPI_FP32_LOG if args.precision == "fp32" else quapi.QUAPI_FP64
-    prop = quapi.Propagator(wl.H, wl.q, wl.dt, wl.K, eta, wl.rho0, mask=wl.mask, theta=wl.theta,
-                            mode=quapi.QUAPI_PRE, max_steps=wl.n_steps, stream=stream.cuda_stream,
-                            max_groups=spec["max_groups"], precision=precision)
+    baths = None
+    if args.workload == "batched-scan":
+        if args.precision != "fp64":
+            print("the batched form is FP64", file=sys.stderr)
+            sys.exit(2)
+        wl, baths = workloads.batched_scan()
+        etas = np.stack([eta_of(b, wl.K) for b in baths])
+        prop = quapi.BatchPropagator(wl.H, wl.q, wl.dt, wl.K, etas, wl.rho0, mask=wl.mask, theta=wl.theta,
+                                     mode=quapi.QUAPI_PRE, max_steps=wl.n_steps, stream=stream.cuda_stream)
+    else:
+        wl = workloads.structured_bath() if args.workload == "structured-bath" else workloads.long_memory()
+        prop = quapi.Propagator(wl.H, wl.q, wl.dt, wl.K, eta_of(wl.bath, wl.K), wl.rho0, mask=wl.mask,
+                                theta=wl.theta, mode=quapi.QUAPI_PRE, max_steps=wl.n_steps,
+                                stream=stream.cuda_stream, max_groups=spec["max_groups"], precision=precision)
+    b = wl.bath
     info = prop.info()
     record_bytes = info["record_bytes"]
+    n_inst = info["n_instances"]
     n_t = wl.n_steps
+
+    chunk_run = 1
+    if n_inst > 1:
+        # the library's own tuner picks the chunk run length (before any timing)
+        chunk_run = quapi.quapi_autotune(prop.ctx, 100)
 
     def run_once():
         prop.reset()
         quapi.quapi_step(prop.ctx, n_t)
-        return quapi.quapi_rho_history(prop.ctx, 0, n_t + 1, wl.M)
+        # rho(t) of every instance: [t][instance][M][M]
+        return quapi.quapi_batch_rho_all(prop.ctx, 0, n_t + 1, n_inst, wl.M)
 
     for _ in range(args.warmup):
         run_once()
@@ -224,10 +251,10 @@ def main():
         rho = run_once()
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t0)
-    st = prop.stats(1, n_t)
-    children = sum(s["n_children"] for s in st)
-    groups_in = np.array([s["n_groups"] for s in st], dtype=np.float64)
-    groups_out = np.array([s["n_stored"] for s in st], dtype=np.float64)
+    sts = [quapi.quapi_batch_step_stats(prop.ctx, j, 1, n_t) for j in range(n_inst)]
+    children = sum(s["n_children"] for st in sts for s in st)
+    groups_in = np.sum([[s["n_groups"] for s in st] for st in sts], axis=0, dtype=np.float64)
+    groups_out = np.sum([[s["n_stored"] for s in st] for st in sts], axis=0, dtype=np.float64)
     total = sum(times)
     ms_per_step = 1e3 * total / len(times)
     value = children * len(times) / total
@@ -253,14 +280,19 @@ def main():
                      "peaks_w0_gamma_lambda": [list(p) for p in b.peaks]},
             "beta": wl.beta, "dt": wl.dt, "eps": 0.5, "Delta": 1.0,
             "precision": args.precision, "merge": "hash table" if info["hash_merge"] else "bucketed store",
-            "record_bytes": record_bytes,
+            "record_bytes": record_bytes, "instances": n_inst, "chunk_run": chunk_run,
         },
         "time_per_rho_us": 1e3 * ms_per_step / n_t,
         "path_steps_per_propagation": children,
         "mean_groups_per_step": float(groups_in.mean()),
         "run_hbm_fraction": float(alg_bytes.sum() / (total / len(times)) / (HBM_PEAK_GBS * 1e9)),
-        "trace_final": float(np.trace(rho[-1]).real),
+        "trace_final": float(np.trace(rho[-1][0]).real),
     }
+
+    if baths is not None:
+        # the bath points of the scan (the config's "bath" is the first one)
+        out["config"]["scan"] = {"peak_w0_range": [min(x.peaks[0][0] for x in baths), max(x.peaks[0][0] for x in baths)],
+                                 "peak_gamma_set": sorted({x.peaks[0][1] for x in baths}), "seed": 11}
 
     if not args.no_roofline:
         # per-launch durations of the roofline kernel: HIP events recorded by the library on

@@ -180,6 +180,24 @@ int quapi_batch_step_stats(quapi_ctx* c, int inst, int t0, int n, quapi_stepstat
 int quapi_batch_groups(quapi_ctx* c, int inst, long long cap, unsigned char* hist, quapi_c64* w,
                        long long* n_out);
 
+/* rho(t0 .. t0+n-1) of every instance into caller-owned out[n][n_instances][M*M],
+ * in one copy (synchronises).  Errors: as quapi_rho_history. */
+int quapi_batch_rho_all(quapi_ctx* c, int t0, int n, quapi_c64* out);
+
+/* Run length of the step kernel's chunk assignment: a workgroup takes `run`
+ * consecutive chunks of the group order, then moves `run` times the grid on
+ * (1 = round-robin).  In the batched form a longer run changes instance less
+ * often (a chunk reloads its instance's coefficients) and finds its look-back
+ * predecessor in the same workgroup; a lone context ignores it.  Results do not
+ * depend on it.  Errors: EINVAL (run < 1 or > 64). */
+int quapi_set_chunk_run(quapi_ctx* c, int run);
+
+/* Time n_steps steps from t = 0 with each run length of 1, 2, 4, 8, 16 (HIP
+ * events on the context's stream), keep the fastest, write it to *run_out (may
+ * be NULL) and return the context to t = 0.  A lone context keeps 1 without
+ * timing.  Errors: EINVAL, ESTATE (a step had failed), and those of quapi_step. */
+int quapi_autotune(quapi_ctx* c, int n_steps, int* run_out);
+
 /* Return to t = 0 with the initial state (tables and buffers are kept). */
 int quapi_reset(quapi_ctx* c);
 

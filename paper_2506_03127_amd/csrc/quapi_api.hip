@@ -62,6 +62,7 @@ struct quapi_ctx {
     long long inst_buckets = 0;              // P^D, buckets of one instance
     unsigned long long* d_totals = nullptr;  // [n_inst]
     unsigned int* d_inst = nullptr;          // [2][n_inst][2] first chunk and groups, by step parity
+    int chunk_run = 1;                       // consecutive chunks a step-kernel workgroup takes in turn
 
     hipStream_t stream = nullptr;
     bool own_stream = false;
@@ -690,6 +691,7 @@ int quapi_step(quapi_ctx* c, int n_steps) {
     a.K = c->K;
     a.n_super = c->n_super;
     a.n_inst = c->n_inst;
+    a.chunk_run = c->chunk_run;
     a.theta2 = c->theta * c->theta;
     a.qmask = c->qbits >= 64 ? 0ull : ~((1ull << c->qbits) - 1ull);
     a.tables = c->d_tables;
@@ -756,6 +758,62 @@ int quapi_batch_rho_history(quapi_ctx* c, int inst, int t0, int n, quapi_c64* ou
 }
 
 int quapi_rho_history(quapi_ctx* c, int t0, int n, quapi_c64* out) { return quapi_batch_rho_history(c, 0, t0, n, out); }
+
+int quapi_batch_rho_all(quapi_ctx* c, int t0, int n, quapi_c64* out) {
+    if (!c || !out || t0 < 0 || n < 0) return QUAPI_EINVAL;
+    const int rc = sync_ctx(c);
+    if (rc == QUAPI_EDEVICE) return rc;
+    if (t0 + n - 1 > c->t) return QUAPI_EINVAL;
+    if (n == 0) return QUAPI_OK;
+    const size_t row = (size_t)c->n_inst * c->P;
+    return hip_to_code(hipMemcpy(out, c->d_rho + (size_t)t0 * row, (size_t)n * row * sizeof(double2),
+                                 hipMemcpyDeviceToHost));
+}
+
+int quapi_set_chunk_run(quapi_ctx* c, int run) {
+    if (!c || run < 1 || run > 64) return QUAPI_EINVAL;
+    (void)hipStreamSynchronize(c->stream);
+    c->chunk_run = run;
+    return QUAPI_OK;
+}
+
+int quapi_autotune(quapi_ctx* c, int n_steps, int* run_out) {
+    if (!c || n_steps < 1) return QUAPI_EINVAL;
+    if (c->err) return QUAPI_ESTATE;
+    // runs matter to the batched form only (they change how often a workgroup
+    // switches instance); a lone context keeps round-robin
+    static const int kRuns[] = {1, 2, 4, 8, 16};
+    int best = 1;
+    if (c->n_inst > 1) {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+            if (e0) (void)hipEventDestroy(e0);
+            return QUAPI_EDEVICE;
+        }
+        float best_ms = 0.0f;
+        int rc = QUAPI_OK;
+        for (int r : kRuns) {
+            c->chunk_run = r;
+            rc = quapi_reset(c);
+            if (rc) break;
+            (void)hipEventRecord(e0, c->stream);
+            rc = quapi_step(c, n_steps);
+            if (rc) break;
+            (void)hipEventRecord(e1, c->stream);
+            rc = sync_ctx(c);
+            if (rc) break;
+            float ms = 0.0f;
+            if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rc = QUAPI_EDEVICE; break; }
+            if (r == kRuns[0] || ms < best_ms) { best_ms = ms; best = r; }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (rc) return rc;
+    }
+    c->chunk_run = best;
+    if (run_out) *run_out = best;
+    return quapi_reset(c);
+}
 
 int quapi_rho(quapi_ctx* c, int t, quapi_c64* rho_out) { return quapi_rho_history(c, t, 1, rho_out); }
 

@@ -67,6 +67,7 @@ struct StepArgs {
     int P, L, K, t;
     int n_super;                    // P^(D-1), per instance
     int n_inst;                     // instances (1 unless batched)
+    int chunk_run;                  // consecutive chunks a workgroup takes in turn (1: round-robin)
     unsigned int epoch;             // step number of the context, tags the look-back words
     double theta2;
     unsigned long long qmask;       // keep-mask of the |w|^2 bit pattern

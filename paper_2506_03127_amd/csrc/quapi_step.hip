@@ -564,15 +564,28 @@ __global__ __launch_bounds__(kThreads, P == 4 ? 4 : 1) void step_kernel(const St
     const unsigned int n_chunks = a.plan->n_chunks;
     const unsigned int n_nz = a.plan->n_nonempty;
     const unsigned int G = gridDim.x;
-    unsigned int c = blockIdx.x;
+    // chunks in runs of R consecutive ones: workgroup w takes runs w, w+G, w+2G, ...
+    // (R = 1: plain round-robin).  Every workgroup takes its chunks in increasing
+    // order, so the look-back, which waits only on earlier chunks, always ends.
+    // (runs are used by the batched form, whose workgroups then change instance less often)
+    const unsigned int R = (BATCH && a.chunk_run > 0) ? (unsigned int)a.chunk_run : 1u;
+    auto succ = [&](unsigned int x, unsigned int k) -> unsigned int {   // the k-th chunk after x
+        if constexpr (!BATCH) {
+            return x + k * G;
+        } else {
+            for (unsigned int j = 0; j < k; ++j) x = (x % R == R - 1u) ? x + (G - 1u) * R + 1u : x + 1u;
+            return x;
+        }
+    };
+    unsigned int c = blockIdx.x * R;
     if (c >= n_chunks) return;
 
     // ---- the first chunk's window and the next one's, in flight during the set-up
     const unsigned int nrec = (unsigned int)((long long)a.n_super * P * a.cap * a.n_inst);
     WinRegs wr = load_window(a, a.desc[c], n_nz, N, i);
     WinRegs wn = {0u, 0u, 0u, 0u};
-    if (c + G < n_chunks) wn = load_window(a, a.desc[c + G], n_nz, N, i);
-    unsigned int d_after = (c + 2 * G < n_chunks) ? a.desc[c + 2 * G] : 0u;
+    if (succ(c, 1) < n_chunks) wn = load_window(a, a.desc[succ(c, 1)], n_nz, N, i);
+    unsigned int d_after = (succ(c, 2) < n_chunks) ? a.desc[succ(c, 2)] : 0u;
 
     // ---- tables and coefficients of this step
     const int K = a.K, L = a.L, t = a.t;
@@ -606,7 +619,8 @@ __global__ __launch_bounds__(kThreads, P == 4 ? 4 : 1) void step_kernel(const St
 
     for (;;) {
         // ---- fetch the next chunk's parents now; they arrive while this chunk computes
-        const bool has_next = c + G < n_chunks;
+        const unsigned int c1 = succ(c, 1);
+        const bool has_next = c1 < n_chunks;
         Parent nxt = cur;
         __syncthreads();                                   // the chunk before is done with the LDS
         // this chunk's instance: its coefficients and tables unless they are in the LDS
@@ -624,10 +638,11 @@ __global__ __launch_bounds__(kThreads, P == 4 ? 4 : 1) void step_kernel(const St
         if (has_next) {
             store_window(s, wn, i);
             __syncthreads();                               // (also publishes the tables)
-            nxt = fetch_parent<P, C, BATCH>(a, s, c + G, N, nrec, i, lane);
+            nxt = fetch_parent<P, C, BATCH>(a, s, c1, N, nrec, i, lane);
             if (BATCH && i == 0) s.chunk_inst = nxt.sig == 0xffffffffu ? 0u : nxt.sig / (unsigned int)a.n_super;
-            if (c + 2 * G < n_chunks) wn = load_window(a, d_after, n_nz, N, i);
-            d_after = (c + 3 * G < n_chunks) ? a.desc[c + 3 * G] : 0u;
+            const unsigned int c2 = succ(c1, 1), c3 = succ(c2, 1);
+            if (c2 < n_chunks) wn = load_window(a, d_after, n_nz, N, i);
+            d_after = (c3 < n_chunks) ? a.desc[c3] : 0u;
         }
 
         // ---- this chunk: groups [g0, g0 + nsz) loaded, segment heads [g0, g0 + H) owned;
@@ -985,7 +1000,7 @@ __global__ __launch_bounds__(kThreads, P == 4 ? 4 : 1) void step_kernel(const St
         }
         if (!has_next) break;
         cur = nxt;
-        c += G;
+        c = c1;
     }
 }
 

@@ -89,6 +89,9 @@ def lib() -> ctypes.CDLL:
         L.quapi_batch_rho_history.argtypes = [vp, ci, ci, ci, vp]
         L.quapi_batch_step_stats.argtypes = [vp, ci, ci, ci, vp]
         L.quapi_batch_groups.argtypes = [vp, ci, cll, vp, vp, ctypes.POINTER(cll)]
+        L.quapi_batch_rho_all.argtypes = [vp, ci, ci, vp]
+        L.quapi_set_chunk_run.argtypes = [vp, ci]
+        L.quapi_autotune.argtypes = [vp, ci, ctypes.POINTER(ci)]
         L.quapi_reset.argtypes = [vp]
         L.quapi_info.argtypes = [vp, ctypes.POINTER(quapi_info_t)]
         L.quapi_stream.restype = vp
@@ -225,6 +228,22 @@ def quapi_batch_rho_history(ctx, inst: int, t0: int, n: int, M: int) -> np.ndarr
     _check(lib().quapi_batch_rho_history(ctx, int(inst), int(t0), int(n), out.ctypes.data),
            "quapi_batch_rho_history")
     return out
+
+
+def quapi_batch_rho_all(ctx, t0: int, n: int, n_inst: int, M: int) -> np.ndarray:
+    out = np.zeros((n, n_inst, M, M), dtype=np.complex128)
+    _check(lib().quapi_batch_rho_all(ctx, int(t0), int(n), out.ctypes.data), "quapi_batch_rho_all")
+    return out
+
+
+def quapi_set_chunk_run(ctx, run: int):
+    _check(lib().quapi_set_chunk_run(ctx, int(run)), "quapi_set_chunk_run")
+
+
+def quapi_autotune(ctx, n_steps: int) -> int:
+    r = ctypes.c_int()
+    _check(lib().quapi_autotune(ctx, int(n_steps), ctypes.byref(r)), "quapi_autotune")
+    return r.value
 
 
 def quapi_batch_step_stats(ctx, inst: int, t0: int, n: int) -> list:
@@ -380,6 +399,18 @@ class BatchPropagator:
 
     def groups(self, inst):
         return quapi_batch_groups(self.ctx, inst, self.K)
+
+    def rho_all(self, t0=0, n=None):
+        """rho(t) of every instance: (n, n_inst, M, M)."""
+        n = quapi_time(self.ctx) + 1 - t0 if n is None else n
+        return quapi_batch_rho_all(self.ctx, t0, n, self.n_inst, self.M)
+
+    def set_chunk_run(self, run):
+        quapi_set_chunk_run(self.ctx, run)
+
+    def autotune(self, n_steps):
+        """Fastest chunk run length over n_steps from t = 0; leaves the context at t = 0."""
+        return quapi_autotune(self.ctx, n_steps)
 
     def reset(self):
         quapi_reset(self.ctx)

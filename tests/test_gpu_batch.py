@@ -137,3 +137,33 @@ def test_batch_capacity_overflow_and_reset(Q):
     o = oracle.Oracle(wl.H, wl.q, wl.dt, K, etas[1], wl.rho0, mask=wl.mask, theta=0.0, mode=oracle.PRE)
     o.step(3)
     assert np.abs(g.rho_history(1, 0, 4) - o.rho_history()).max() < RHO_TOL
+
+
+def test_chunk_runs_and_autotune_leave_results_unchanged(Q):
+    """Chunk run lengths change which workgroup takes which chunk, not what a
+    chunk computes: every run length gives the same bits."""
+    wl, baths = W.batched_scan(n_inst=6, seed=5, K=12, n_exact=7, theta=1e-7)
+    K, n = 12, 50
+    etas = _etas(Q, wl, baths, K)
+    g = Q.BatchPropagator(wl.H, wl.q, wl.dt, K, etas, wl.rho0, mask=wl.mask, theta=wl.theta)
+    ref = None
+    for run in (1, 3, 16):
+        g.reset()
+        g.set_chunk_run(run)
+        g.step(n)
+        r = g.rho_all(0, n + 1)
+        assert r.shape == (n + 1, 6, 2, 2)
+        for j in (0, 5):
+            assert np.array_equal(r[:, j], g.rho_history(j, 0, n + 1))
+        if ref is None:
+            ref = (r, [g.groups(j) for j in range(6)])
+        else:
+            assert np.array_equal(r, ref[0]), run
+            for j in range(6):
+                h, w = g.groups(j)
+                assert np.array_equal(h, ref[1][j][0]) and np.array_equal(w, ref[1][j][1])
+    best = g.autotune(20)
+    assert best in (1, 2, 4, 8, 16)
+    assert g.t == 0
+    g.step(n)
+    assert np.array_equal(g.rho_all(0, n + 1), ref[0])
