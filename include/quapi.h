@@ -132,17 +132,21 @@ int quapi_create(const quapi_params* p, quapi_ctx** out);
 
 /* Batched form: n_inst instances of the method (for instance bath parameter
  * points of eq. SD) that share every field of p but the influence
- * coefficients (p->eta is not read), propagated together: each step is one
- * launch of the step kernel over the groups of all instances.  Instance j's
- * coefficients are eta_batch[3*(K+1)*j .. 3*(K+1)*(j+1)-1], laid out as
- * quapi_params.eta; the caller keeps ownership.  Each instance's results
+ * coefficients (p->eta is not read) and, optionally, the system Hamiltonian,
+ * propagated together: each step is one launch of the step kernel over the
+ * groups of all instances.  Instance j's coefficients are
+ * eta_batch[3*(K+1)*j .. 3*(K+1)*(j+1)-1], laid out as quapi_params.eta; its
+ * Hamiltonian is H_batch[M*M*j ..] when H_batch is not NULL (each checked as
+ * p->H is), else p->H.  The caller keeps ownership of both.  Each instance's results
  * (rho(t), counters, groups) are those of a context created with quapi_create
  * on its own coefficients and the same bucket layout.  p->max_groups counts
  * one instance.  The functions without "batch" in their name address
  * instance 0.  Merge positions 0..L-1 (the bucketed store), FP64 only.
  * Errors: as quapi_create; EINVAL (n_inst < 1 or > 1024, eta_batch NULL or not
- * finite), EUNSUPPORTED (the hash-table merge or the FP32 form). */
-int quapi_create_batch(const quapi_params* p, int n_inst, const quapi_c64* eta_batch, quapi_ctx** out);
+ * finite, an H_batch matrix not Hermitian), EUNSUPPORTED (the hash-table merge
+ * or the FP32 form). */
+int quapi_create_batch(const quapi_params* p, int n_inst, const quapi_c64* eta_batch, const quapi_c64* H_batch,
+                       quapi_ctx** out);
 
 /* Enqueue n_steps time steps on the context's stream; returns without waiting.
  * Errors: EINVAL (n_steps < 0), ESTATE (a previous step failed), ENOMEM

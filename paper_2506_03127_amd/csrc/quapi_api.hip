@@ -70,6 +70,8 @@ struct quapi_ctx {
     unsigned int* counts[2] = {nullptr, nullptr};
     double* d_tables = nullptr;
     double* d_coef = nullptr;
+    std::vector<double> k4_batch;            // batched form with one H_S per instance: [n_inst][P*P] complex
+    double* d_k4_batch = nullptr;
     double* d_partials = nullptr;
     unsigned int* d_nz_bucket = nullptr;     // [n_buckets] nonempty buckets of the stored groups
     unsigned int* d_nz_prefix = nullptr;     // [n_buckets] their first global group index
@@ -382,8 +384,10 @@ int quapi_eta(const quapi_bath* bath, double beta, double dt, int dk_max, quapi_
 }
 
 // A context of n_inst instances that share p but for the eta tables (instance
-// j's at eta_all + 3*(K+1)*j); batch: the batched form (its planner and layout).
-static int create_ctx(const quapi_params* p, int n_inst, const quapi_c64* eta_all, bool batch, quapi_ctx** out) {
+// j's at eta_all + 3*(K+1)*j) and, when H_all is given, the Hamiltonians (j's at
+// H_all + M*M*j); batch: the batched form (its planner and layout).
+static int create_ctx(const quapi_params* p, int n_inst, const quapi_c64* eta_all, const quapi_c64* H_all,
+                      bool batch, quapi_ctx** out) {
     if (!out) return QUAPI_EINVAL;
     *out = nullptr;
     if (!p || !p->H || !p->q || !eta_all || !p->rho0 || n_inst < 1 || n_inst > kMaxInstances) return QUAPI_EINVAL;
@@ -394,6 +398,8 @@ static int create_ctx(const quapi_params* p, int n_inst, const quapi_c64* eta_al
     if (p->precision != QUAPI_FP64 && p->precision != QUAPI_FP32_LOG) return QUAPI_EINVAL;
     if (M > 3) return QUAPI_EUNSUPPORTED;
     if (!quapi_host::hermitian_ok(M, (const double*)p->H)) return QUAPI_EINVAL;
+    for (int j = 0; H_all && j < n_inst; ++j)
+        if (!quapi_host::hermitian_ok(M, (const double*)(H_all + (size_t)M * M * j))) return QUAPI_EINVAL;
     for (int i = 0; i < M; ++i)
         if (!is_finite_d(p->q[i])) return QUAPI_EINVAL;
     for (long long i = 0; i < 3ll * (K + 1) * n_inst; ++i)
@@ -493,17 +499,24 @@ static int create_ctx(const quapi_params* p, int n_inst, const quapi_c64* eta_al
     c->cap = cap;
 
     // tables: K4[pn][po] = U[an][ao] conj(U[bn][bo]); ds, ss; eta
-    std::vector<double> U(2 * M * M);
-    quapi_host::propagator(M, (const double*)p->H, p->dt, U.data());
+    auto k4_of = [&](const quapi_c64* H, double* dst) {
+        std::vector<double> U(2 * M * M);
+        quapi_host::propagator(M, (const double*)H, p->dt, U.data());
+        for (int pn = 0; pn < P; ++pn)
+            for (int po = 0; po < P; ++po) {
+                const std::complex<double> u1(U[2 * ((pn / M) * M + po / M)], U[2 * ((pn / M) * M + po / M) + 1]);
+                const std::complex<double> u2(U[2 * ((pn % M) * M + po % M)], U[2 * ((pn % M) * M + po % M) + 1]);
+                const std::complex<double> k4 = u1 * std::conj(u2);
+                dst[2 * (pn * P + po)] = k4.real();
+                dst[2 * (pn * P + po) + 1] = k4.imag();
+            }
+    };
     c->tables.assign(TableLayout::total(P, K), 0.0);
-    for (int pn = 0; pn < P; ++pn)
-        for (int po = 0; po < P; ++po) {
-            const std::complex<double> u1(U[2 * ((pn / M) * M + po / M)], U[2 * ((pn / M) * M + po / M) + 1]);
-            const std::complex<double> u2(U[2 * ((pn % M) * M + po % M)], U[2 * ((pn % M) * M + po % M) + 1]);
-            const std::complex<double> k4 = u1 * std::conj(u2);
-            c->tables[2 * (pn * P + po)] = k4.real();
-            c->tables[2 * (pn * P + po) + 1] = k4.imag();
-        }
+    k4_of(H_all ? H_all : p->H, c->tables.data());
+    if (H_all) {
+        c->k4_batch.assign((size_t)n_inst * 2 * P * P, 0.0);
+        for (int j = 0; j < n_inst; ++j) k4_of(H_all + (size_t)M * M * j, c->k4_batch.data() + (size_t)j * 2 * P * P);
+    }
     for (int pp = 0; pp < P; ++pp) {
         c->tables[TableLayout::ds(P) + pp] = p->q[pp / M] - p->q[pp % M];
         c->tables[TableLayout::ss(P) + pp] = p->q[pp / M] + p->q[pp % M];
@@ -579,6 +592,7 @@ static int create_ctx(const quapi_params* p, int n_inst, const quapi_c64* eta_al
     }
     if (!rc) rc = dev_alloc(c, &c->d_tables, c->tables.size());
     if (!rc) rc = dev_alloc(c, &c->d_coef, c->coef.size());
+    if (!rc && !c->k4_batch.empty()) rc = dev_alloc(c, &c->d_k4_batch, c->k4_batch.size());
     // (each instance of the batched form starts a chunk: one partial chunk more each)
     c->max_chunks = (int)std::min<long long>((long long)nrec / quapi_dev::chunk_heads(P) + n_inst + 2, 1ll << 30);
     if (!rc) rc = dev_alloc(c, &c->d_partials, (size_t)c->max_chunks * quapi_dev::partial_stride(P));
@@ -625,6 +639,9 @@ static int create_ctx(const quapi_params* p, int n_inst, const quapi_c64* eta_al
     if (e == hipSuccess)
         e = hipMemcpyAsync(c->d_coef, c->coef.data(), c->coef.size() * sizeof(double), hipMemcpyHostToDevice,
                            c->stream);
+    if (e == hipSuccess && c->d_k4_batch)
+        e = hipMemcpyAsync(c->d_k4_batch, c->k4_batch.data(), c->k4_batch.size() * sizeof(double),
+                           hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess)
         e = hipMemsetAsync(c->d_chain, 0, (size_t)P * c->max_chunks * sizeof(unsigned long long), c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(c->d_plan, 0, 2 * sizeof(quapi_dev::Plan), c->stream);
@@ -670,11 +687,12 @@ int quapi_create(const quapi_params* p, quapi_ctx** out) {
         if (out) *out = nullptr;
         return QUAPI_EINVAL;
     }
-    return create_ctx(p, 1, p->eta, false, out);
+    return create_ctx(p, 1, p->eta, nullptr, false, out);
 }
 
-int quapi_create_batch(const quapi_params* p, int n_inst, const quapi_c64* eta_batch, quapi_ctx** out) {
-    return create_ctx(p, n_inst, eta_batch, true, out);
+int quapi_create_batch(const quapi_params* p, int n_inst, const quapi_c64* eta_batch, const quapi_c64* H_batch,
+                       quapi_ctx** out) {
+    return create_ctx(p, n_inst, eta_batch, H_batch, true, out);
 }
 
 int quapi_step(quapi_ctx* c, int n_steps) {
@@ -692,6 +710,7 @@ int quapi_step(quapi_ctx* c, int n_steps) {
     a.n_super = c->n_super;
     a.n_inst = c->n_inst;
     a.chunk_run = c->chunk_run;
+    a.k4_batch = c->d_k4_batch;
     a.theta2 = c->theta * c->theta;
     a.qmask = c->qbits >= 64 ? 0ull : ~((1ull << c->qbits) - 1ull);
     a.tables = c->d_tables;

@@ -73,6 +73,8 @@ struct StepArgs {
     unsigned long long qmask;       // keep-mask of the |w|^2 bit pattern
     const double* tables;           // device tables, see TableLayout
     const double* coef;             // this step's coefficients: cre, cim, dre, dim [n_inst][4][K+1]
+    const double* k4_batch;         // [n_inst][P*P] complex K4 per instance (batched form with one H_S
+                                    // per instance), or null: the K4 of tables for all
     unsigned long long* chain;      // [P * max_chunks] look-back words, one per chunk and pair
     int max_chunks;
     double* partials;               // [partial_stride(P)][max_chunks], component-major

@@ -628,6 +628,11 @@ __global__ __launch_bounds__(kThreads, P == 4 ? 4 : 1) void step_kernel(const St
         if constexpr (BATCH) {
             const unsigned int inst = s.chunk_inst;
             if (inst != loaded) {
+                if (a.k4_batch)
+                    for (int k = i; k < P * P; k += kThreads) {
+                        s.k4re[k] = a.k4_batch[2 * ((size_t)inst * P * P + k)];
+                        s.k4im[k] = a.k4_batch[2 * ((size_t)inst * P * P + k) + 1];
+                    }
                 load_coefficients(s, a.coef + (size_t)inst * 4 * (K + 1), K, i);
                 __syncthreads();
                 build_tables<P, BP>(s, K, L, nk, nt, use_tabs, i);

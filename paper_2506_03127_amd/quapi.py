@@ -85,7 +85,7 @@ def lib() -> ctypes.CDLL:
         L.quapi_rho_history.argtypes = [vp, ci, ci, vp]
         L.quapi_step_stats.argtypes = [vp, ci, ci, vp]
         L.quapi_groups.argtypes = [vp, cll, vp, vp, ctypes.POINTER(cll)]
-        L.quapi_create_batch.argtypes = [ctypes.POINTER(quapi_params), ci, vp, ctypes.POINTER(vp)]
+        L.quapi_create_batch.argtypes = [ctypes.POINTER(quapi_params), ci, vp, vp, ctypes.POINTER(vp)]
         L.quapi_batch_rho_history.argtypes = [vp, ci, ci, ci, vp]
         L.quapi_batch_step_stats.argtypes = [vp, ci, ci, ci, vp]
         L.quapi_batch_groups.argtypes = [vp, ci, cll, vp, vp, ctypes.POINTER(cll)]
@@ -169,14 +169,17 @@ def quapi_create(H, q, dt, dk_max, eta, rho0, mask=None, theta=0.0, mode=QUAPI_P
 
 
 def quapi_create_batch(H, q, dt, dk_max, etas, rho0, mask=None, theta=0.0, mode=QUAPI_PRE, qbits=-1,
-                       max_groups=0, max_steps=0, stream=None) -> int:
-    """etas: (n_inst, 3, dk_max + 1) complex, one eta table per instance."""
+                       max_groups=0, max_steps=0, stream=None, H_batch=None) -> int:
+    """etas: (n_inst, 3, dk_max + 1) complex, one eta table per instance; H_batch:
+    (n_inst, M, M) complex, one Hamiltonian per instance, or None (H for all)."""
     etas = _c128(etas)
     etas = etas.reshape(-1, 3, int(dk_max) + 1)
     p, keep = _params(H, q, dt, dk_max, None, rho0, mask, theta, mode, qbits, max_groups, max_steps,
                       stream, QUAPI_FP64)
+    hb = None if H_batch is None else _c128(H_batch).reshape(etas.shape[0], p.M, p.M)
     h = ctypes.c_void_p()
-    _check(lib().quapi_create_batch(ctypes.byref(p), int(etas.shape[0]), etas.ctypes.data, ctypes.byref(h)),
+    _check(lib().quapi_create_batch(ctypes.byref(p), int(etas.shape[0]), etas.ctypes.data,
+                                    None if hb is None else hb.ctypes.data, ctypes.byref(h)),
            "quapi_create_batch")
     return h.value
 

@@ -167,3 +167,23 @@ def test_chunk_runs_and_autotune_leave_results_unchanged(Q):
     assert g.t == 0
     g.step(n)
     assert np.array_equal(g.rho_all(0, n + 1), ref[0])
+
+
+def test_batch_per_instance_hamiltonians(Q, monkeypatch):
+    """Instances that differ in the bias eps of H_S as well as in the bath."""
+    wl, baths = W.batched_scan(n_inst=4, seed=8, K=12, n_exact=6, theta=1e-7)
+    K, n = 12, 50
+    etas = _etas(Q, wl, baths, K)
+    Hs = np.stack([W.tls_hamiltonian(eps, 1.0) for eps in (0.0, 0.5, 1.0, -0.7)])
+    print(f"[batch] 4 instances with their own H_S K={K} n={n}", flush=True)
+    g = Q.BatchPropagator(wl.H, wl.q, wl.dt, K, etas, wl.rho0, mask=wl.mask, theta=wl.theta, H_batch=Hs)
+    monkeypatch.setenv("QUAPI_MAX_SUPER", "1024")
+    singles = [Q.Propagator(Hs[j], wl.q, wl.dt, K, etas[j], wl.rho0, mask=wl.mask, theta=wl.theta)
+               for j in range(4)]
+    g.step(n)
+    for s in singles:
+        s.step(n)
+    _assert_same(Q, g, singles, n)
+    o = oracle.Oracle(Hs[3], wl.q, wl.dt, K, etas[3], wl.rho0, mask=wl.mask, theta=wl.theta, mode=oracle.PRE)
+    o.step(n)
+    assert np.abs(g.rho_history(3, 0, n + 1) - o.rho_history()).max() < RHO_TOL

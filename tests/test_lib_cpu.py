@@ -121,6 +121,8 @@ def test_create_batch_rejects_invalid_input_without_device(Q):
     assert _create_batch_code(Q, n_inst=3, etas=etas) == Q.QUAPI_EINVAL
     assert _create_batch_code(Q, mask=[0, 1, 3]) == Q.QUAPI_EUNSUPPORTED   # hash-table merge
     assert _create_batch_code(Q, mode=9) == Q.QUAPI_EINVAL
+    Hb = np.stack([W.tls_hamiltonian(0.5, 1.0), np.array([[0, 1], [2, 0]], dtype=complex)])
+    assert _create_batch_code(Q, H_batch=Hb) == Q.QUAPI_EINVAL          # second H not Hermitian
 
 
 def test_strerror_names_every_code(Q):
