@@ -92,6 +92,17 @@ def lib() -> ctypes.CDLL:
         L.quapi_batch_rho_all.argtypes = [vp, ci, ci, vp]
         L.quapi_set_chunk_run.argtypes = [vp, ci]
         L.quapi_autotune.argtypes = [vp, ci, ctypes.POINTER(ci)]
+        L.quapi_mlp_create.argtypes = [ci, ci, ci, ci, ci, ctypes.c_ulonglong, vp, ctypes.POINTER(vp)]
+        L.quapi_mlp_n_params.argtypes = [vp, ctypes.POINTER(cll)]
+        L.quapi_mlp_set_params.argtypes = [vp, vp, cll]
+        L.quapi_mlp_get_params.argtypes = [vp, vp, cll]
+        L.quapi_mlp_get_grads.argtypes = [vp, vp, cll]
+        L.quapi_mlp_forward.argtypes = [vp, vp, ci, vp]
+        L.quapi_mlp_backward.argtypes = [vp, vp, vp, ci, vp]
+        L.quapi_mlp_adam.argtypes = [vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float]
+        L.quapi_mlp_sync.argtypes = [vp]
+        L.quapi_mlp_destroy.restype = None
+        L.quapi_mlp_destroy.argtypes = [vp]
         L.quapi_reset.argtypes = [vp]
         L.quapi_info.argtypes = [vp, ctypes.POINTER(quapi_info_t)]
         L.quapi_stream.restype = vp
@@ -425,6 +436,68 @@ class BatchPropagator:
         if getattr(self, "ctx", None):
             quapi_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------------ surrogate network
+class MLP:
+    """The library's multilayer perceptron (quapi_mlp_*).  Batches are torch
+    float32 tensors on the GPU (memory only; the arithmetic is the library's)."""
+
+    def __init__(self, n_in, width, depth, n_out, max_batch, seed=1, stream=None):
+        self.n_in, self.width, self.depth, self.n_out = int(n_in), int(width), int(depth), int(n_out)
+        self.max_batch = int(max_batch)
+        h = ctypes.c_void_p()
+        _check(lib().quapi_mlp_create(self.n_in, self.width, self.depth, self.n_out, self.max_batch,
+                                      ctypes.c_ulonglong(seed), None if stream is None else int(stream),
+                                      ctypes.byref(h)), "quapi_mlp_create")
+        self.h = h.value
+        n = ctypes.c_longlong()
+        _check(lib().quapi_mlp_n_params(self.h, ctypes.byref(n)), "quapi_mlp_n_params")
+        self.n_params = n.value
+
+    def layers(self):
+        """(fan_in, fan_out) of each layer, in the flat parameter order."""
+        dims = [self.n_in] + [self.width] * self.depth + [self.n_out]
+        return list(zip(dims[:-1], dims[1:]))
+
+    def params(self) -> np.ndarray:
+        out = np.zeros(self.n_params, dtype=np.float32)
+        _check(lib().quapi_mlp_get_params(self.h, out.ctypes.data, self.n_params), "quapi_mlp_get_params")
+        return out
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(np.asarray(p, dtype=np.float32))
+        _check(lib().quapi_mlp_set_params(self.h, p.ctypes.data, self.n_params), "quapi_mlp_set_params")
+
+    def grads(self) -> np.ndarray:
+        out = np.zeros(self.n_params, dtype=np.float32)
+        _check(lib().quapi_mlp_get_grads(self.h, out.ctypes.data, self.n_params), "quapi_mlp_get_grads")
+        return out
+
+    def forward(self, x, y):
+        """y[:B] = network(x[:B]) (device tensors, float32, contiguous)."""
+        _check(lib().quapi_mlp_forward(self.h, x.data_ptr(), int(x.shape[0]), y.data_ptr()), "quapi_mlp_forward")
+
+    def backward(self, x, target, loss=None):
+        _check(lib().quapi_mlp_backward(self.h, x.data_ptr(), target.data_ptr(), int(x.shape[0]),
+                                        None if loss is None else loss.data_ptr()), "quapi_mlp_backward")
+
+    def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        _check(lib().quapi_mlp_adam(self.h, lr, beta1, beta2, eps), "quapi_mlp_adam")
+
+    def sync(self):
+        _check(lib().quapi_mlp_sync(self.h), "quapi_mlp_sync")
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().quapi_mlp_destroy(self.h)
+            self.h = None
 
     def __del__(self):
         try:
