@@ -10,7 +10,8 @@
  * layer.  Loss: the mean over batch x n_out of (y - target)^2.  Optimiser:
  * Adam (Kingma & Ba 2015).  The matrix products run on the bf16 matrix cores
  * with FP32 accumulation (layer inputs, weights and back-propagated gradients
- * rounded to bf16 as they enter a product); everything else is FP32.
+ * rounded to bf16 as they enter a product); an input layer of at most 16
+ * inputs runs in FP32, and everything else is FP32.
  *
  * Parameters, flat FP32, for each layer l = 0 .. depth: W_l [fan_in][fan_out]
  * row-major, then b_l [fan_out].

@@ -6,7 +6,10 @@
 // gradient enters a product rounded to bf16; biases, pre-activations,
 // gradients, the loss and the Adam state are FP32, and the FP32 master
 // weights are what Adam updates (their bf16 copies are refreshed after each
-// step).  One strided GEMM kernel serves the forward product, the weight
+// step).  The input layer, with at most kFp32In inputs, is no matrix product
+// worth the matrix cores and runs in FP32 on the vector units: its inputs are
+// the network's coordinates (time and parameters), whose bf16 rounding would
+// cost 2^-9 of their range.  One strided GEMM kernel serves the forward product, the weight
 // gradient (reduction over the batch, split over workgroups and summed in a
 // fixed order) and the input gradient.
 //
@@ -36,6 +39,7 @@ constexpr int kTM = 64, kTN = 64, kTK = 32;   // workgroup tile; one MFMA's k pe
 constexpr int kLdsK = kTK + 8;                // row pitch of the LDS tiles (bf16), breaks bank strides
 constexpr int kVecThreads = 256;
 constexpr int kMaxSplit = 64;
+constexpr int kFp32In = 16;                   // input layers this narrow run in FP32
 
 enum Epilogue : int {
     kStoreF32 = 0,     // outf = acc (+ bias)
@@ -140,6 +144,30 @@ __global__ __launch_bounds__(kGemmThreads) void gemm_bf16(const GemmArgs g) {
             }
 }
 
+// FP32 input layer: z[m][n] = b[n] + sum_k x[m][k] W[k][n]; a = bf16(gelu(z))
+// (or z alone for a network without hidden layers)
+__global__ void dense_in(const float* x, const float* W, const float* b, int M, int K, int N, float* z, uint16_t* a) {
+    const long long idx = (long long)blockIdx.x * kVecThreads + threadIdx.x;
+    if (idx >= (long long)M * N) return;
+    const int m = (int)(idx / N), n = (int)(idx % N);
+    float s = b[n];
+    for (int k = 0; k < K; ++k) s = fmaf(x[(size_t)m * K + k], W[(size_t)k * N + n], s);
+    z[idx] = s;
+    if (a) a[idx] = to_bf16(gelu(s));
+}
+
+// its weight gradient, split over the batch: partial[z][k][n] = sum over the
+// rows m of split z of x[m][k] dz[m][n]
+__global__ void dense_in_grad(const float* x, const float* dz, int M, int K, int N, int rows, float* partial) {
+    const int idx = blockIdx.x * kVecThreads + threadIdx.x;
+    if (idx >= K * N) return;
+    const int k = idx / N, n = idx % N;
+    const int m0 = blockIdx.y * rows, m1 = min(M, m0 + rows);
+    float s = 0.0f;
+    for (int m = m0; m < m1; ++m) s = fmaf(x[(size_t)m * K + k], dz[(size_t)m * N + n], s);
+    partial[(size_t)blockIdx.y * K * N + idx] = s;
+}
+
 __global__ void to_bf16_kernel(const float* x, uint16_t* y, long long n) {
     for (long long k = (long long)blockIdx.x * kVecThreads + threadIdx.x; k < n; k += (long long)gridDim.x * kVecThreads)
         y[k] = to_bf16(x[k]);
@@ -230,6 +258,8 @@ struct quapi_mlp {
     uint16_t* dzb2 = nullptr;
     float* partial = nullptr;            // split-reduction partials
     float* loss_part = nullptr;
+    float* xf = nullptr;                 // FP32 network input [max_batch][n_in] (FP32 input layer)
+    bool fp32_in = false;
     int adam_t = 0;
     std::vector<void*> allocs;
 };
@@ -263,10 +293,17 @@ int refresh_bf16(quapi_mlp* c) {
     return hipGetLastError() == hipSuccess ? QUAPI_OK : QUAPI_EDEVICE;
 }
 
-// forward of a batch already in c->xb; the output pre-activations land in z[last]
+// forward of a batch already in c->xb (and c->xf); the output pre-activations land in z[last]
 int forward(quapi_mlp* c, int batch) {
     for (int l = 0; l < c->n_layers; ++l) {
         const bool last = l == c->n_layers - 1;
+        if (l == 0 && c->fp32_in) {
+            const long long n = (long long)batch * c->fout[0];
+            hipLaunchKernelGGL(dense_in, dim3((unsigned)((n + kVecThreads - 1) / kVecThreads)), dim3(kVecThreads), 0,
+                               c->stream, c->xf, c->w + c->w_off[0], c->w + c->b_off[0], batch, c->fin[0],
+                               c->fout[0], c->z[0], last ? nullptr : c->ab[0]);
+            continue;
+        }
         GemmArgs g{};
         g.A = l == 0 ? c->xb : c->ab[l - 1];
         g.sam = c->fin[l];
@@ -288,6 +325,18 @@ int forward(quapi_mlp* c, int batch) {
 }
 
 int check_batch(quapi_mlp* c, int batch) { return (batch < 1 || batch > c->max_batch) ? QUAPI_EINVAL : QUAPI_OK; }
+
+// the network input as the first layer reads it: FP32 copy, or bf16
+int stage_input(quapi_mlp* c, const float* x, int batch) {
+    const long long nx = (long long)batch * c->n_in;
+    if (c->fp32_in) {
+        if (hipMemcpyAsync(c->xf, x, (size_t)nx * sizeof(float), hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+            return QUAPI_EDEVICE;
+    } else {
+        hipLaunchKernelGGL(to_bf16_kernel, dim3(blocks_for(nx)), dim3(kVecThreads), 0, c->stream, x, c->xb, nx);
+    }
+    return hipGetLastError() == hipSuccess ? QUAPI_OK : QUAPI_EDEVICE;
+}
 
 }  // namespace
 
@@ -331,6 +380,8 @@ int quapi_mlp_create(int n_in, int width, int depth, int n_out, int max_batch, u
     if (!rc) rc = mlp_alloc(c, &c->m, c->n_params);
     if (!rc) rc = mlp_alloc(c, &c->v, c->n_params);
     if (!rc) rc = mlp_alloc(c, &c->xb, (size_t)max_batch * n_in);
+    c->fp32_in = n_in <= kFp32In;
+    if (!rc && c->fp32_in) rc = mlp_alloc(c, &c->xf, (size_t)max_batch * n_in);
     c->wb.assign(c->n_layers, nullptr);
     c->z.assign(c->n_layers, nullptr);
     c->ab.assign(depth, nullptr);
@@ -409,8 +460,7 @@ int quapi_mlp_get_grads(quapi_mlp* c, float* host, long long n) {
 int quapi_mlp_forward(quapi_mlp* c, const float* x, int batch, float* y) {
     if (!c || !x || !y) return QUAPI_EINVAL;
     if (check_batch(c, batch)) return QUAPI_EINVAL;
-    const long long nx = (long long)batch * c->n_in;
-    hipLaunchKernelGGL(to_bf16_kernel, dim3(blocks_for(nx)), dim3(kVecThreads), 0, c->stream, x, c->xb, nx);
+    if (stage_input(c, x, batch)) return QUAPI_EDEVICE;
     if (forward(c, batch)) return QUAPI_EDEVICE;
     const hipError_t e = hipMemcpyAsync(y, c->z[c->n_layers - 1], (size_t)batch * c->n_out * sizeof(float),
                                         hipMemcpyDeviceToDevice, c->stream);
@@ -420,8 +470,7 @@ int quapi_mlp_forward(quapi_mlp* c, const float* x, int batch, float* y) {
 int quapi_mlp_backward(quapi_mlp* c, const float* x, const float* target, int batch, float* loss) {
     if (!c || !x || !target) return QUAPI_EINVAL;
     if (check_batch(c, batch)) return QUAPI_EINVAL;
-    const long long nx = (long long)batch * c->n_in;
-    hipLaunchKernelGGL(to_bf16_kernel, dim3(blocks_for(nx)), dim3(kVecThreads), 0, c->stream, x, c->xb, nx);
+    if (stage_input(c, x, batch)) return QUAPI_EDEVICE;
     if (forward(c, batch)) return QUAPI_EDEVICE;
     const int L = c->n_layers;
     // dL/dy of the mean over batch x n_out of (y - t)^2
@@ -437,6 +486,20 @@ int quapi_mlp_backward(quapi_mlp* c, const float* x, const float* target, int ba
     uint16_t* dzb_next = c->dzb2;
     for (int l = L - 1; l >= 0; --l) {
         const int fin = c->fin[l], fout = c->fout[l];
+        if (l == 0 && c->fp32_in) {
+            // FP32 input layer: dW_0 = X^T dZ_0 in FP32, split over the batch
+            const int splits = std::min(kMaxSplit, std::max(1, (batch + 255) / 256));
+            const int rows = (batch + splits - 1) / splits;
+            const int used = (batch + rows - 1) / rows;
+            hipLaunchKernelGGL(dense_in_grad, dim3((fin * fout + kVecThreads - 1) / kVecThreads, used),
+                               dim3(kVecThreads), 0, c->stream, c->xf, dzf, batch, fin, fout, rows, c->partial);
+            const long long nw = (long long)fin * fout;
+            hipLaunchKernelGGL(sum_splits, dim3(blocks_for(nw)), dim3(kVecThreads), 0, c->stream, c->partial, used,
+                               nw, c->grad + c->w_off[0]);
+            hipLaunchKernelGGL(column_sums, dim3((fout + kVecThreads - 1) / kVecThreads), dim3(kVecThreads), 0,
+                               c->stream, dzf, batch, fout, c->grad + c->b_off[0]);
+            break;
+        }
         // dW_l = A_{l-1}^T dZ_l: reduction over the batch, split over workgroups
         const int splits = std::min(kMaxSplit, std::max(1, (batch + 255) / 256));
         GemmArgs g{};

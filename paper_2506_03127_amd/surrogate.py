@@ -1,0 +1,245 @@
+"""Learned surrogate of rho(t) over a box of bath and system parameters.
+
+A network maps (w0, gamma, lambda, alpha, eps, t) -- the Brownian-oscillator
+peak's frequency, width and reorganisation energy, the Ohmic coupling, the
+bias of H_S = (eps/2) sigma_z + (Delta/2) sigma_x, and the time -- to the four
+real components of rho(t) (rho_00, Re rho_01, Im rho_01, rho_11).  It is
+trained on trajectories of the batched propagation (one instance per
+parameter point) with the library's network kernels, validated on held-out
+points, and answers a query only inside the box and in a cell of the
+(w0, gamma) plane whose held-out error is within the tolerance; every other
+query is propagated by the method itself, which also judges the error.
+
+The paper contains no such network; it serves parameter scans.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Dict, Optional, Tuple
+
+import numpy as np
+
+from . import quapi, workloads
+
+PARAMS = ("w0", "gamma", "lam", "alpha", "eps")
+
+
+@dataclass
+class Box:
+    """Parameter ranges around the structured bath.  Toward w0 = 2 with
+    lambda = 0.15 the method itself leaves the physical range (|rho| up to 25
+    with lags 0..7 of 12 kept exact, 1.8 with 0..11 of 16), its memory far
+    shorter than the bath's; over this box it stays within |rho| <= 1."""
+    w0: Tuple[float, float] = (0.5, 1.5)
+    gamma: Tuple[float, float] = (0.02, 0.1)
+    lam: Tuple[float, float] = (0.05, 0.1)
+    alpha: Tuple[float, float] = (0.03, 0.07)
+    eps: Tuple[float, float] = (0.25, 0.75)
+
+    def lo_hi(self):
+        lo = np.array([getattr(self, p)[0] for p in PARAMS])
+        hi = np.array([getattr(self, p)[1] for p in PARAMS])
+        return lo, hi
+
+    def sample(self, n: int, seed: int) -> np.ndarray:
+        lo, hi = self.lo_hi()
+        return np.random.default_rng(seed).uniform(lo, hi, (n, len(PARAMS)))
+
+    def contains(self, pts: np.ndarray) -> np.ndarray:
+        lo, hi = self.lo_hi()
+        return np.all((pts >= lo) & (pts <= hi), axis=1)
+
+
+@dataclass
+class Solver:
+    """The method's settings for the trajectories: the structured bath's
+    (dk_max 24, lags 0..11 exact, theta 1e-8)."""
+    K: int = 24
+    n_exact: int = 12
+    theta: float = 1e-8
+    n_steps: int = 100
+    batch: int = 64
+    threads: int = 8                         # eta quadratures in parallel (host)
+
+    def solve(self, pts: np.ndarray) -> np.ndarray:
+        """rho(t), t = 0..n_steps, of every point: [n_points][n_steps + 1][2][2],
+        by the batched propagation, `batch` points per launch."""
+        from concurrent.futures import ThreadPoolExecutor
+        base = workloads.structured_bath(n_steps=self.n_steps, K=self.K, n_exact=self.n_exact, theta=self.theta)
+        out = np.zeros((len(pts), self.n_steps + 1, 2, 2), dtype=np.complex128)
+
+        def eta(pt):
+            w0, g, lam, a, _ = pt
+            return quapi.quapi_eta(a, base.bath.ohmic_wc, [w0, g, lam], base.beta, base.dt, self.K)
+
+        with ThreadPoolExecutor(self.threads) as ex:
+            etas_all = list(ex.map(eta, pts))
+        for s in range(0, len(pts), self.batch):
+            chunk = pts[s:s + self.batch]
+            etas = np.stack(etas_all[s:s + self.batch])
+            Hs = np.stack([workloads.tls_hamiltonian(e, 1.0) for e in chunk[:, 4]])
+            prop = quapi.BatchPropagator(base.H, base.q, base.dt, self.K, etas, base.rho0, mask=base.mask,
+                                         theta=self.theta, max_steps=self.n_steps, H_batch=Hs)
+            prop.step(self.n_steps)
+            out[s:s + len(chunk)] = np.transpose(prop.rho_all(0, self.n_steps + 1), (1, 0, 2, 3))
+            prop.close()
+        return out
+
+
+def free_evolution(pts: np.ndarray, n_t: int, dt: float, rho0: np.ndarray) -> np.ndarray:
+    """U(t) rho0 U(t)^+ of the system alone, U = exp(-i H_S t), H_S = (eps/2)
+    sigma_z + (1/2) sigma_x, t = 0, dt, ..., (n_t - 1) dt: [n][n_t][2][2]."""
+    eps = np.asarray(pts)[:, 4]
+    om = np.sqrt(eps ** 2 + 1.0)                     # level splitting
+    t = dt * np.arange(n_t)
+    ph = 0.5 * om[:, None] * t[None, :]
+    c, s = np.cos(ph), np.sin(ph)
+    nz, nx = (eps / om)[:, None], (1.0 / om)[:, None]
+    # U = cos(ph) 1 - i sin(ph) (nz sigma_z + nx sigma_x)
+    U = np.empty((len(eps), n_t, 2, 2), dtype=np.complex128)
+    U[..., 0, 0] = c - 1j * s * nz
+    U[..., 1, 1] = c + 1j * s * nz
+    U[..., 0, 1] = -1j * s * nx
+    U[..., 1, 0] = -1j * s * nx
+    return U @ rho0 @ np.conj(np.swapaxes(U, -1, -2))
+
+
+def rho_components(rho: np.ndarray) -> np.ndarray:
+    """[..., 2, 2] complex -> [..., 4] real: rho_00, Re rho_01, Im rho_01, rho_11."""
+    return np.stack([rho[..., 0, 0].real, rho[..., 0, 1].real, rho[..., 0, 1].imag, rho[..., 1, 1].real], axis=-1)
+
+
+@dataclass
+class Surrogate:
+    box: Box = field(default_factory=Box)
+    solver: Solver = field(default_factory=Solver)
+    width: int = 256
+    depth: int = 4
+    tol: float = 1e-3
+    cells: Tuple[int, int] = (4, 3)          # bins of w0 and gamma for the validation
+    seed: int = 1
+    net: Optional[quapi.MLP] = None
+    accepted: Optional[np.ndarray] = None    # [cells w0][cells gamma] bool
+    cell_error: Optional[np.ndarray] = None  # held-out error per cell (nan: no point)
+    history: Dict[str, list] = field(default_factory=dict)
+    stream: object = None                    # torch stream of the network and of its batches
+    residual: bool = True                    # learn rho(t) minus the system's own evolution
+
+    def _stream(self):
+        """One torch stream for the network and the tensor work around it (torch's
+        default stream has the null handle, which the library would replace by a
+        stream of its own, unordered with torch's)."""
+        import torch
+        if self.stream is None:
+            self.stream = torch.cuda.Stream()
+        return self.stream
+
+    # ---- features
+    def _features(self, pts: np.ndarray, n_t: int) -> np.ndarray:
+        """[n_points][n_t][6] in [-1, 1]: the parameters and the time."""
+        lo, hi = self.box.lo_hi()
+        p = 2.0 * (pts - lo) / (hi - lo) - 1.0
+        tt = 2.0 * np.arange(n_t) / max(self.solver.n_steps, 1) - 1.0
+        f = np.empty((len(pts), n_t, 6), dtype=np.float32)
+        f[:, :, :5] = p[:, None, :]
+        f[:, :, 5] = tt[None, :]
+        return f
+
+    def _baseline(self, pts: np.ndarray, n_t: int) -> np.ndarray:
+        base = workloads.structured_bath()
+        if not self.residual:
+            return np.zeros((len(pts), n_t, 2, 2), dtype=np.complex128)
+        return free_evolution(pts, n_t, base.dt, base.rho0)
+
+    def _cell(self, pts: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
+        lo, hi = self.box.lo_hi()
+        u = (pts[:, :2] - lo[:2]) / (hi[:2] - lo[:2])
+        cw = np.clip((u[:, 0] * self.cells[0]).astype(int), 0, self.cells[0] - 1)
+        cg = np.clip((u[:, 1] * self.cells[1]).astype(int), 0, self.cells[1] - 1)
+        return cw, cg
+
+    # ---- training and validation
+    def fit(self, train_pts: np.ndarray, train_rho: np.ndarray, steps: int = 4000, batch: int = 8192,
+            lr: float = 1e-3, lr_final: float = 1e-5, log_every: int = 500):
+        """Adam on random mini-batches of (point, t) samples, with the learning
+        rate decaying geometrically from lr to lr_final."""
+        import torch
+        st = self._stream()
+        n_t = train_rho.shape[1]
+        target = train_rho - self._baseline(train_pts, n_t)
+        with torch.cuda.stream(st):
+            x = torch.as_tensor(self._features(train_pts, n_t).reshape(-1, 6), device="cuda")
+            y = torch.as_tensor(rho_components(target).reshape(-1, 4).astype(np.float32), device="cuda")
+            n = x.shape[0]
+            batch = min(batch, n)
+            if self.net is None:
+                self.net = quapi.MLP(6, self.width, self.depth, 4, max_batch=max(batch, 65536), seed=self.seed,
+                                     stream=st.cuda_stream)
+            g = torch.Generator(device="cuda")
+            g.manual_seed(self.seed)
+            loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+            self.history["loss"] = []
+            for s in range(steps):
+                idx = torch.randint(0, n, (batch,), device="cuda", generator=g)
+                xb, yb = x[idx].contiguous(), y[idx].contiguous()
+                self.net.backward(xb, yb, loss)
+                self.net.adam(lr * (lr_final / lr) ** (s / max(steps - 1, 1)))
+                if log_every and (s % log_every == 0 or s == steps - 1):
+                    self.net.sync()
+                    self.history["loss"].append((s, loss.item()))
+        self.net.sync()
+
+    def predict(self, pts: np.ndarray, n_t: Optional[int] = None) -> np.ndarray:
+        """The network's rho(t), t = 0..n_t-1, of every point: [n][n_t][2][2]."""
+        import torch
+        n_t = self.solver.n_steps + 1 if n_t is None else n_t
+        f = self._features(pts, n_t).reshape(-1, 6)
+        out = np.empty((f.shape[0], 4), dtype=np.float32)
+        step = self.net.max_batch
+        with torch.cuda.stream(self._stream()):
+            for s in range(0, f.shape[0], step):
+                xb = torch.as_tensor(f[s:s + step], device="cuda")
+                yb = torch.empty((xb.shape[0], 4), dtype=torch.float32, device="cuda")
+                self.net.forward(xb, yb)
+                self.net.sync()
+                out[s:s + step] = yb.cpu().numpy()
+        c = out.reshape(len(pts), n_t, 4).astype(np.float64)
+        rho = np.empty((len(pts), n_t, 2, 2), dtype=np.complex128)
+        rho[..., 0, 0] = c[..., 0]
+        rho[..., 0, 1] = c[..., 1] + 1j * c[..., 2]
+        rho[..., 1, 0] = c[..., 1] - 1j * c[..., 2]
+        rho[..., 1, 1] = c[..., 3]
+        return rho + self._baseline(pts, n_t)
+
+    def validate(self, pts: np.ndarray, rho: np.ndarray) -> np.ndarray:
+        """Held-out error of every point (max over t and elements of |rho_net -
+        rho_method|); a cell is accepted when its held-out points are all within
+        the tolerance."""
+        err = np.abs(self.predict(pts, rho.shape[1]) - rho).max(axis=(1, 2, 3))
+        cw, cg = self._cell(pts)
+        self.cell_error = np.full(self.cells, np.nan)
+        for a in range(self.cells[0]):
+            for b in range(self.cells[1]):
+                sel = (cw == a) & (cg == b)
+                if sel.any():
+                    self.cell_error[a, b] = err[sel].max()
+        self.accepted = np.nan_to_num(self.cell_error, nan=np.inf) <= self.tol
+        return err
+
+    # ---- queries
+    def query(self, pts: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
+        """rho(t), t = 0..n_steps, of every point, and which were answered by the
+        network (the rest by the method)."""
+        pts = np.asarray(pts, dtype=np.float64).reshape(-1, len(PARAMS))
+        use = self.box.contains(pts)
+        if self.accepted is None:
+            use[:] = False
+        else:
+            cw, cg = self._cell(pts)
+            use &= self.accepted[cw, cg]
+        out = np.empty((len(pts), self.solver.n_steps + 1, 2, 2), dtype=np.complex128)
+        if use.any():
+            out[use] = self.predict(pts[use])
+        if (~use).any():
+            out[~use] = self.solver.solve(pts[~use])
+        return out, use

@@ -1,9 +1,10 @@
 """The surrogate network's kernels (quapi_mlp_*) against a plain torch CPU
 reference in float64.
 
-Forward: the reference rounds to bf16 where the kernels do (network input,
-weights, hidden activations); the rest of the difference is FP32 accumulation
-and the FP32 erf, so outputs agree to a few bf16 units of the largest output.
+Forward: the reference rounds to bf16 where the kernels do (the operands of
+every product but an input layer of at most 16 inputs, which runs in FP32, and
+the hidden activations); the rest of the difference is FP32 accumulation and
+the FP32 erf, so outputs agree to a few bf16 units of the largest output.
 Gradients: against torch autograd of the unrounded network in float64; bf16
 rounding of the product operands leaves a relative error of the order of
 2^-8 per element, so the bar is on whole layers (relative norm error < 3e-2,
@@ -43,11 +44,14 @@ def _bf16(a):
 
 
 def _ref_forward(net, p, x, rounded):
+    """rounded: bf16 where the kernels round -- every product's operands but
+    those of an input layer of at most 16 inputs, which runs in FP32."""
     import torch
-    a = _bf16(x) if rounded else torch.as_tensor(x, dtype=torch.float64)
+    fp32_in = net.n_in <= 16
+    a = _bf16(x) if rounded and not fp32_in else torch.as_tensor(x, dtype=torch.float64)
     layers = _split(net, p)
     for l, (W, b) in enumerate(layers):
-        Wt = _bf16(W) if rounded else torch.as_tensor(W, dtype=torch.float64)
+        Wt = _bf16(W) if rounded and not (l == 0 and fp32_in) else torch.as_tensor(W, dtype=torch.float64)
         z = a @ Wt + torch.as_tensor(b, dtype=torch.float64)
         if l == len(layers) - 1:
             return z
@@ -55,7 +59,8 @@ def _ref_forward(net, p, x, rounded):
         a = _bf16(g) if rounded else g
 
 
-SHAPES = [(6, 256, 4, 4, 1000), (5, 96, 2, 3, 77), (6, 64, 3, 4, 4096)]
+# the last shape has a bf16 input layer (more than 16 inputs)
+SHAPES = [(6, 256, 4, 4, 1000), (5, 96, 2, 3, 77), (6, 64, 3, 4, 4096), (40, 128, 2, 4, 500)]
 
 
 @pytest.mark.parametrize("n_in,width,depth,n_out,batch", SHAPES)
