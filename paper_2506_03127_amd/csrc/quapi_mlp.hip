@@ -79,6 +79,50 @@ struct GemmArgs {
     uint16_t* outb;               // [M][N] or null
 };
 
+// One operand's 64 x 32 tile into the LDS as T[row][k] (row = m of A, n of
+// B): element (row, k) of the operand is X[row * s_row + k * s_k].
+__device__ inline void stage_tile(const uint16_t* X, long long s_row, long long s_k, int rows, int r0, int k0,
+                                  int k_hi, int i, uint16_t (*T)[kLdsK]) {
+    if (s_k == 1) {
+        // 8 consecutive k of one row
+        const int r = i >> 2, kq = (i & 3) * 8;
+        const int row = r0 + r, k = k0 + kq;
+        const long long o = (long long)row * s_row + k;
+        if (row < rows && k + 8 <= k_hi && (o & 7) == 0) {
+            *reinterpret_cast<uint4*>(&T[r][kq]) = *reinterpret_cast<const uint4*>(X + o);
+            return;
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            T[r][kq + j] = (row < rows && k + j < k_hi) ? X[o + j] : (uint16_t)0;
+        return;
+    }
+    if (s_row == 1) {
+        // 8 consecutive rows at one k
+        const int kk = i >> 3, rq = (i & 7) * 8;
+        const int row = r0 + rq, k = k0 + kk;
+        const long long o = (long long)k * s_k + row;
+        if (k < k_hi && row + 8 <= rows && (o & 7) == 0) {
+            const uint4 v = *reinterpret_cast<const uint4*>(X + o);
+            const uint16_t* e = reinterpret_cast<const uint16_t*>(&v);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) T[rq + j][kk] = e[j];
+            return;
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            T[rq + j][kk] = (k < k_hi && row + j < rows) ? X[o + j] : (uint16_t)0;
+        return;
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int idx = e * kGemmThreads + i;
+        const int r = idx / kTK, kk = idx % kTK;
+        const int row = r0 + r, k = k0 + kk;
+        T[r][kk] = (row < rows && k < k_hi) ? X[(long long)row * s_row + (long long)k * s_k] : (uint16_t)0;
+    }
+}
+
 // C = A B over one 64 x 64 tile; waves (wr, wc) take 32 x 32 quarters as 2 x 2
 // MFMA tiles of 16 x 16.  MFMA operands: lane l holds row l % 16 of A and
 // column l % 16 of B at k = (l / 16) * 8 .. + 8; the result holds rows
@@ -101,16 +145,11 @@ __global__ __launch_bounds__(kGemmThreads) void gemm_bf16(const GemmArgs g) {
 
     for (int k0 = k_lo; k0 < k_hi; k0 += kTK) {
         __syncthreads();
-        // stage 64 x 32 of A and 32 x 64 of B (8 elements each per thread), zero outside
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int idx = e * kGemmThreads + i;
-            const int r = idx / kTK, kk = idx % kTK;
-            const int m = m0 + r, k = k0 + kk;
-            As[r][kk] = (m < g.M && k < k_hi) ? g.A[(long long)m * g.sam + (long long)k * g.sak] : (uint16_t)0;
-            const int n = n0 + r;
-            Bt[r][kk] = (n < g.N && k < k_hi) ? g.B[(long long)k * g.sbk + (long long)n * g.sbn] : (uint16_t)0;
-        }
+        // stage 64 x 32 of A and 32 x 64 of B, 8 elements per thread each: one
+        // 16-byte load along the operand's contiguous dimension where the 8 lie
+        // inside it and aligned, else element by element (zero outside)
+        stage_tile(g.A, g.sam, g.sak, g.M, m0, k0, k_hi, i, As);
+        stage_tile(g.B, g.sbn, g.sbk, g.N, n0, k0, k_hi, i, Bt);
         __syncthreads();
         bf16x8 af[2], bfr[2];
 #pragma unroll
@@ -157,15 +196,33 @@ __global__ void dense_in(const float* x, const float* W, const float* b, int M, 
 }
 
 // its weight gradient, split over the batch: partial[z][k][n] = sum over the
-// rows m of split z of x[m][k] dz[m][n]
-__global__ void dense_in_grad(const float* x, const float* dz, int M, int K, int N, int rows, float* partial) {
-    const int idx = blockIdx.x * kVecThreads + threadIdx.x;
-    if (idx >= K * N) return;
-    const int k = idx / N, n = idx % N;
+// rows m of split z of x[m][k] dz[m][n].  Lanes take 64 columns n; the four
+// waves take every fourth row of the split and add up in the LDS in wave order.
+__global__ __launch_bounds__(kVecThreads) void dense_in_grad(const float* x, const float* dz, int M, int K, int N,
+                                                              int rows, float* partial) {
+    __shared__ float red[kVecThreads / 64][kFp32In][64];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int n = blockIdx.x * 64 + lane;
     const int m0 = blockIdx.y * rows, m1 = min(M, m0 + rows);
-    float s = 0.0f;
-    for (int m = m0; m < m1; ++m) s = fmaf(x[(size_t)m * K + k], dz[(size_t)m * N + n], s);
-    partial[(size_t)blockIdx.y * K * N + idx] = s;
+    float acc[kFp32In];
+#pragma unroll
+    for (int k = 0; k < kFp32In; ++k) acc[k] = 0.0f;
+    if (n < N)
+        for (int m = m0 + wave; m < m1; m += kVecThreads / 64) {
+            const float d = dz[(size_t)m * N + n];
+#pragma unroll
+            for (int k = 0; k < kFp32In; ++k)
+                if (k < K) acc[k] = fmaf(x[(size_t)m * K + k], d, acc[k]);
+        }
+#pragma unroll
+    for (int k = 0; k < kFp32In; ++k) red[wave][k][lane] = acc[k];
+    __syncthreads();
+    if (wave == 0 && n < N)
+        for (int k = 0; k < K; ++k) {
+            float t = 0.0f;
+            for (int w = 0; w < kVecThreads / 64; ++w) t += red[w][k][lane];
+            partial[(size_t)blockIdx.y * K * N + (size_t)k * N + n] = t;
+        }
 }
 
 __global__ void to_bf16_kernel(const float* x, uint16_t* y, long long n) {
@@ -212,13 +269,25 @@ __global__ void sum_splits(const float* partial, int splits, long long n, float*
     }
 }
 
-// bias gradient: column sums of dZ [rows][cols], one thread per column, rows in order
-__global__ void column_sums(const float* dz, int rows, int cols, float* out) {
-    const int c = blockIdx.x * kVecThreads + threadIdx.x;
-    if (c >= cols) return;
+// bias gradient, split over the batch: partial[z][c] = sum over the rows of
+// split z of dZ[r][c] (summed over the splits in order by sum_splits).  Lanes
+// take 64 columns; the four waves take every fourth row and add up in wave order.
+__global__ __launch_bounds__(kVecThreads) void column_sums(const float* dz, int rows, int cols, int per,
+                                                            float* partial) {
+    __shared__ float red[kVecThreads / 64][64];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int c = blockIdx.x * 64 + lane;
+    const int r0 = blockIdx.y * per, r1 = min(rows, r0 + per);
     float s = 0.0f;
-    for (int r = 0; r < rows; ++r) s += dz[(size_t)r * cols + c];
-    out[c] = s;
+    if (c < cols)
+        for (int r = r0 + wave; r < r1; r += kVecThreads / 64) s += dz[(size_t)r * cols + c];
+    red[wave][lane] = s;
+    __syncthreads();
+    if (wave == 0 && c < cols) {
+        float t = 0.0f;
+        for (int w = 0; w < kVecThreads / 64; ++w) t += red[w][lane];
+        partial[(size_t)blockIdx.y * cols + c] = t;
+    }
 }
 
 // Adam (Kingma & Ba 2015) on the flat FP32 parameters; bias-corrected step sizes
@@ -236,6 +305,8 @@ __global__ void adam_kernel(float* w, float* m, float* v, const float* grad, lon
 }
 
 int blocks_for(long long n) { return (int)std::min<long long>((n + kVecThreads - 1) / kVecThreads, 2048); }
+
+constexpr int kBiasRows = 256;  // rows per split of the bias gradient
 
 }  // namespace
 
@@ -259,6 +330,7 @@ struct quapi_mlp {
     float* partial = nullptr;            // split-reduction partials
     float* loss_part = nullptr;
     float* xf = nullptr;                 // FP32 network input [max_batch][n_in] (FP32 input layer)
+    float* bias_part = nullptr;          // bias-gradient partials [<= 4096 splits][max width]
     bool fp32_in = false;
     int adam_t = 0;
     std::vector<void*> allocs;
@@ -325,6 +397,19 @@ int forward(quapi_mlp* c, int batch) {
 }
 
 int check_batch(quapi_mlp* c, int batch) { return (batch < 1 || batch > c->max_batch) ? QUAPI_EINVAL : QUAPI_OK; }
+
+// bias gradient: column sums of dz [batch][cols] over splits of at least
+// kBiasRows rows (at most 4096 splits), then summed over the splits in order
+int bias_grad(quapi_mlp* c, const float* dz, int batch, int cols, float* out) {
+    const int per = std::max(kBiasRows, (batch + 4095) / 4096);
+    const int splits = (batch + per - 1) / per;
+    float* part = c->bias_part;
+    hipLaunchKernelGGL(column_sums, dim3((cols + 63) / 64, splits), dim3(kVecThreads), 0, c->stream, dz, batch, cols,
+                       per, part);
+    hipLaunchKernelGGL(sum_splits, dim3(blocks_for(cols)), dim3(kVecThreads), 0, c->stream, part, splits,
+                       (long long)cols, out);
+    return hipGetLastError() == hipSuccess ? QUAPI_OK : QUAPI_EDEVICE;
+}
 
 // the network input as the first layer reads it: FP32 copy, or bf16
 int stage_input(quapi_mlp* c, const float* x, int batch) {
@@ -397,6 +482,7 @@ int quapi_mlp_create(int n_in, int width, int depth, int n_out, int max_batch, u
     const long long wmax_params = (long long)std::max(n_in, width) * wmax;
     if (!rc) rc = mlp_alloc(c, &c->partial, (size_t)kMaxSplit * wmax_params);
     if (!rc) rc = mlp_alloc(c, &c->loss_part, 2048);
+    if (!rc) rc = mlp_alloc(c, &c->bias_part, (size_t)std::min(max_batch / kBiasRows + 1, 4096) * wmax);
     if (rc) {
         quapi_mlp_destroy(c);
         return rc;
@@ -491,13 +577,12 @@ int quapi_mlp_backward(quapi_mlp* c, const float* x, const float* target, int ba
             const int splits = std::min(kMaxSplit, std::max(1, (batch + 255) / 256));
             const int rows = (batch + splits - 1) / splits;
             const int used = (batch + rows - 1) / rows;
-            hipLaunchKernelGGL(dense_in_grad, dim3((fin * fout + kVecThreads - 1) / kVecThreads, used),
-                               dim3(kVecThreads), 0, c->stream, c->xf, dzf, batch, fin, fout, rows, c->partial);
+            hipLaunchKernelGGL(dense_in_grad, dim3((fout + 63) / 64, used), dim3(kVecThreads), 0, c->stream, c->xf,
+                               dzf, batch, fin, fout, rows, c->partial);
             const long long nw = (long long)fin * fout;
             hipLaunchKernelGGL(sum_splits, dim3(blocks_for(nw)), dim3(kVecThreads), 0, c->stream, c->partial, used,
                                nw, c->grad + c->w_off[0]);
-            hipLaunchKernelGGL(column_sums, dim3((fout + kVecThreads - 1) / kVecThreads), dim3(kVecThreads), 0,
-                               c->stream, dzf, batch, fout, c->grad + c->b_off[0]);
+            if (bias_grad(c, dzf, batch, fout, c->grad + c->b_off[0])) return QUAPI_EDEVICE;
             break;
         }
         // dW_l = A_{l-1}^T dZ_l: reduction over the batch, split over workgroups
@@ -520,8 +605,7 @@ int quapi_mlp_backward(quapi_mlp* c, const float* x, const float* target, int ba
         const long long nw = (long long)fin * fout;
         hipLaunchKernelGGL(sum_splits, dim3(blocks_for(nw)), dim3(kVecThreads), 0, c->stream, c->partial, used, nw,
                            c->grad + c->w_off[l]);
-        hipLaunchKernelGGL(column_sums, dim3((fout + kVecThreads - 1) / kVecThreads), dim3(kVecThreads), 0, c->stream,
-                           dzf, batch, fout, c->grad + c->b_off[l]);
+        if (bias_grad(c, dzf, batch, fout, c->grad + c->b_off[l])) return QUAPI_EDEVICE;
         if (l == 0) break;
         // dZ_{l-1} = (dZ_l W_l^T) * gelu'(Z_{l-1})
         GemmArgs h{};
