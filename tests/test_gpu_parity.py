@@ -359,3 +359,27 @@ def test_launch_timing_record(Q, eta_cache):
         Q.quapi_profile_end(g.ctx, 16)
     assert e.value.code == Q.QUAPI_ESTATE
     assert g.t == 8
+
+
+# ------------------------------------------------------------------ pre- against post-merging study
+def test_merging_study_matches_oracle(Q, eta_cache):
+    """The study's population difference and path-steps of the two merging
+    orders are the oracle's."""
+    from paper_2506_03127_amd import merging_study
+    wl = W.structured_bath(K=10, n_exact=5)
+    n, th = 40, 1e-7
+    rows = merging_study.compare(wl, [th], n)
+    r = rows[0]
+    b = wl.bath
+    eta = Q.quapi_eta(b.ohmic_alpha, b.ohmic_wc, [x for pk in b.peaks for x in pk], wl.beta, wl.dt, wl.K)
+    res = {}
+    for mode in (oracle.PRE, oracle.POST):
+        o = oracle.Oracle(wl.H, wl.q, wl.dt, wl.K, eta, wl.rho0, mask=wl.mask, theta=th, mode=mode)
+        o.step(n)
+        assert ambiguous(o, n) == 0
+        res[mode] = (o.rho_history(), sum(o.stats(t)["n_children"] for t in range(1, n + 1)))
+    pop = np.abs(np.real(np.einsum("tii->ti", res[oracle.PRE][0]) - np.einsum("tii->ti", res[oracle.POST][0]))).max()
+    assert abs(r["max_population_difference"] - pop) < 1e-12
+    assert r["pre_path_steps"] == res[oracle.PRE][1]
+    assert r["post_path_steps"] == res[oracle.POST][1]
+    assert r["post_stored_max"] >= r["pre_stored_max"]
