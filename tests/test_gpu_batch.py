@@ -187,3 +187,17 @@ def test_batch_per_instance_hamiltonians(Q, monkeypatch):
     o = oracle.Oracle(Hs[3], wl.q, wl.dt, K, etas[3], wl.rho0, mask=wl.mask, theta=wl.theta, mode=oracle.PRE)
     o.step(n)
     assert np.abs(g.rho_history(3, 0, n + 1) - o.rho_history()).max() < RHO_TOL
+
+
+def test_batch_of_one_equals_lone_context(Q, monkeypatch):
+    """The batched planner and layout with a single instance (one closing list
+    entry, the lone step kernel)."""
+    wl, baths = W.batched_scan(n_inst=1, seed=4, K=12, n_exact=6, theta=1e-7)
+    K, n = 12, 40
+    etas = _etas(Q, wl, baths, K)
+    g = Q.BatchPropagator(wl.H, wl.q, wl.dt, K, etas, wl.rho0, mask=wl.mask, theta=wl.theta)
+    assert g.info()["n_instances"] == 1
+    singles = _singles_like(Q, monkeypatch, g, wl, etas, K, Q.QUAPI_PRE)
+    g.step(n)
+    singles[0].step(n)
+    _assert_same(Q, g, singles, n)

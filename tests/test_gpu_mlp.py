@@ -154,3 +154,17 @@ def test_training_reduces_loss(Q):
     net.sync()
     print(f"[mlp] loss {first:.3e} -> {loss.item():.3e}", flush=True)
     assert loss.item() < first / 20
+
+
+def test_batch_bounds(Q):
+    import torch
+    net = Q.MLP(6, 32, 1, 4, max_batch=100, seed=1)
+    x = torch.zeros((101, 6), device="cuda")
+    y = torch.zeros((101, 4), device="cuda")
+    with pytest.raises(Q.QuapiError) as e:
+        net.forward(x, y)
+    assert e.value.code == Q.QUAPI_EINVAL
+    with pytest.raises(Q.QuapiError):
+        net.forward(x[:0], y[:0])
+    with pytest.raises(Q.QuapiError):
+        net.adam(-1.0)

@@ -125,6 +125,16 @@ def test_create_batch_rejects_invalid_input_without_device(Q):
     assert _create_batch_code(Q, H_batch=Hb) == Q.QUAPI_EINVAL          # second H not Hermitian
 
 
+def test_mlp_create_rejects_invalid_sizes_without_device(Q):
+    import ctypes
+    h = ctypes.c_void_p()
+    for args in [(0, 256, 4, 4, 64), (6, 0, 4, 4, 64), (6, 256, 0, 4, 64), (6, 256, 4, 0, 64), (6, 256, 4, 4, 0),
+                 (6, 5000, 4, 4, 64), (6, 256, 65, 4, 64), (6, 256, 4, 4, (1 << 22) + 1)]:
+        rc = Q.lib().quapi_mlp_create(*args, ctypes.c_ulonglong(1), None, ctypes.byref(h))
+        assert rc == Q.QUAPI_EINVAL, args
+        assert not h.value
+
+
 def test_strerror_names_every_code(Q):
     names = {Q.strerror(c) for c in (0, -1, -2, -3, -4, -5)}
     assert len(names) == 6 and "unknown error" not in names
