@@ -179,6 +179,8 @@ def main():
                          "default: 22 for the structured bath, 15 for the long-memory workload)")
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="structured-bath")
+    ap.add_argument("--chunk-run", type=int, default=0,
+                    help="batched form: chunk run length (0: the library's tuner picks it)")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64",
                     help="fp32: the FP32 log-domain form (hash-table merge)")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -231,8 +233,12 @@ def main():
 
     chunk_run = 1
     if n_inst > 1:
-        # the library's own tuner picks the chunk run length (before any timing)
-        chunk_run = quapi.quapi_autotune(prop.ctx, 100)
+        if args.chunk_run > 0:
+            chunk_run = args.chunk_run
+            quapi.quapi_set_chunk_run(prop.ctx, chunk_run)
+        else:
+            # the library's own tuner picks the chunk run length (before any timing)
+            chunk_run = quapi.quapi_autotune(prop.ctx, 100)
 
     def run_once():
         prop.reset()

@@ -72,6 +72,7 @@ struct quapi_ctx {
     double* d_coef = nullptr;
     std::vector<double> k4_batch;            // batched form with one H_S per instance: [n_inst][P*P] complex
     double* d_k4_batch = nullptr;
+    double* d_inst_tabs = nullptr;           // batched form: each instance's subset tables of the current set
     double* d_partials = nullptr;
     unsigned int* d_nz_bucket = nullptr;     // [n_buckets] nonempty buckets of the stored groups
     unsigned int* d_nz_prefix = nullptr;     // [n_buckets] their first global group index
@@ -593,6 +594,8 @@ static int create_ctx(const quapi_params* p, int n_inst, const quapi_c64* eta_al
     if (!rc) rc = dev_alloc(c, &c->d_tables, c->tables.size());
     if (!rc) rc = dev_alloc(c, &c->d_coef, c->coef.size());
     if (!rc && !c->k4_batch.empty()) rc = dev_alloc(c, &c->d_k4_batch, c->k4_batch.size());
+    if (!rc && batch && P == 4)
+        rc = dev_alloc(c, &c->d_inst_tabs, (size_t)n_inst * quapi_dev::instance_table_doubles());
     // (each instance of the batched form starts a chunk: one partial chunk more each)
     c->max_chunks = (int)std::min<long long>((long long)nrec / quapi_dev::chunk_heads(P) + n_inst + 2, 1ll << 30);
     if (!rc) rc = dev_alloc(c, &c->d_partials, (size_t)c->max_chunks * quapi_dev::partial_stride(P));
@@ -711,6 +714,7 @@ int quapi_step(quapi_ctx* c, int n_steps) {
     a.n_inst = c->n_inst;
     a.chunk_run = c->chunk_run;
     a.k4_batch = c->d_k4_batch;
+    a.inst_tabs = c->n_inst > 1 ? c->d_inst_tabs : nullptr;
     a.theta2 = c->theta * c->theta;
     a.qmask = c->qbits >= 64 ? 0ull : ~((1ull << c->qbits) - 1ull);
     a.tables = c->d_tables;
@@ -731,6 +735,13 @@ int quapi_step(quapi_ctx* c, int n_steps) {
         a.t = t;
         a.epoch = ++c->epoch;
         a.coef = c->d_coef + (size_t)(std::min(t, c->K + 1) - 1) * c->n_inst * 4 * n;
+        // the batched form's instance tables follow the coefficient set, which is
+        // the same from step K+1 on
+        if (a.inst_tabs && t <= c->K + 1 &&
+            quapi_dev::launch_instance_tables(a, c->d_inst_tabs, c->stream) != (int)hipSuccess) {
+            c->err = QUAPI_EDEVICE;
+            return c->err;
+        }
         hipEvent_t* ev = (c->prof_on && c->prof_n < c->prof_cap) ? &c->prof_ev[3 * (size_t)c->prof_n++] : nullptr;
         if (ev && hipEventRecord(ev[0], c->stream) != hipSuccess) ev = nullptr;
         if (quapi_dev::launch_step(a, c->grid, c->stream) != (int)hipSuccess) {

@@ -75,6 +75,8 @@ struct StepArgs {
     const double* coef;             // this step's coefficients: cre, cim, dre, dim [n_inst][4][K+1]
     const double* k4_batch;         // [n_inst][P*P] complex K4 per instance (batched form with one H_S
                                     // per instance), or null: the K4 of tables for all
+    const double* inst_tabs;        // batched form: [n_inst][instance_table_doubles()] subset tables and
+                                    // end-point factors of this step's coefficients, or null: rebuilt
     unsigned long long* chain;      // [P * max_chunks] look-back words, one per chunk and pair
     int max_chunks;
     double* partials;               // [partial_stride(P)][max_chunks], component-major
@@ -120,6 +122,8 @@ int launch_step(const StepArgs& a, int grid, void* stream);   // returns hipErro
 int launch_plan(const PlanArgs& a, void* stream);
 int launch_plan_batch(const PlanArgs& a, void* stream);   // two kernels: totals and reduce, then lists
 int plan_batch_max_buckets();                            // P^D of one instance at most
+size_t instance_table_doubles();                         // per instance, of instance_tables
+int launch_instance_tables(const StepArgs& a, double* out, void* stream);   // one workgroup per instance
 int chunk_heads(int P);
 int plan_max_buckets();              // bucket count the planner is built for
 int step_grid(int P, int n_cu, int per_cu, bool batch);   // persistent workgroups that are co-resident

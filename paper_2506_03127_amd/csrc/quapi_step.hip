@@ -56,6 +56,7 @@ constexpr int kWin = kThreads + 6;
 constexpr int kTabPts = 2;            // points per subset-sum table (two-level systems)
 constexpr int kTabEntries = 16;       // 4^2
 constexpr int kMaxTabs = 16;
+constexpr int kInstTabs = kMaxTabs * kTabEntries * 4 + 2;   // doubles per instance of instance_tables
 constexpr unsigned int kSpinLimit = 1u << 22;
 constexpr unsigned long long kAgg = 1ull << 32;   // look-back word: own totals only
 constexpr unsigned long long kInc = 2ull << 32;   // look-back word: inclusive totals
@@ -547,6 +548,36 @@ __device__ inline void build_tables(Lds<P>& s, int K, int L, int nk, int nt, boo
     }
 }
 
+// Each instance's subset tables and end-point factors of one coefficient set,
+// built by the code the step kernel builds them with (so bit for bit the same),
+// for the batched form's chunks to copy instead of rebuilding:
+// out[inst][kInstTabs]: tab[q][v][4] for q < kMaxTabs, then e0, f0.
+template <int P, int BP>
+__global__ __launch_bounds__(kThreads) void instance_tables(const StepArgs a, double* out) {
+    __shared__ Lds<P> s;
+    const int i = threadIdx.x;
+    const unsigned int inst = blockIdx.x;
+    const int K = a.K, L = a.L;
+    if (i < P) {
+        s.ds[i] = a.tables[TableLayout::ds(P) + i];
+        s.ss[i] = a.tables[TableLayout::ss(P) + i];
+    }
+    load_coefficients(s, a.coef + (size_t)inst * 4 * (K + 1), K, i);
+    __syncthreads();
+    const int nk = (L + kTabPts - 1) / kTabPts, nt = (K - L + kTabPts - 1) / kTabPts;
+    build_tables<P, BP>(s, K, L, nk, nt, (P == 4) && (nk + nt <= kMaxTabs), i);
+    __syncthreads();
+    double* o = out + (size_t)inst * kInstTabs;
+    if constexpr (P == 4) {
+        const double* t = &s.tab[0][0][0];
+        for (int idx = i; idx < (nk + nt) * kTabEntries * 4; idx += kThreads) o[idx] = t[idx];
+        if (i == 0) {
+            o[kMaxTabs * kTabEntries * 4] = s.e0;
+            o[kMaxTabs * kTabEntries * 4 + 1] = s.f0;
+        }
+    }
+}
+
 // BATCH: the batched form (several instances; chunks reload the coefficients of
 // their instance, and positions past an instance's end hold no group)
 template <int P, int BP, bool BATCH>
@@ -634,8 +665,19 @@ __global__ __launch_bounds__(kThreads, P == 4 ? 4 : 1) void step_kernel(const St
                         s.k4im[k] = a.k4_batch[2 * ((size_t)inst * P * P + k) + 1];
                     }
                 load_coefficients(s, a.coef + (size_t)inst * 4 * (K + 1), K, i);
-                __syncthreads();
-                build_tables<P, BP>(s, K, L, nk, nt, use_tabs, i);
+                if (P == 4 && use_tabs && a.inst_tabs) {
+                    // the instance's tables as instance_tables built them
+                    const double* src = a.inst_tabs + (size_t)inst * kInstTabs;
+                    double* t = &s.tab[0][0][0];
+                    for (int idx = i; idx < (nk + nt) * kTabEntries * 4; idx += kThreads) t[idx] = src[idx];
+                    if (i == 0) {
+                        s.e0 = src[kMaxTabs * kTabEntries * 4];
+                        s.f0 = src[kMaxTabs * kTabEntries * 4 + 1];
+                    }
+                } else {
+                    __syncthreads();
+                    build_tables<P, BP>(s, K, L, nk, nt, use_tabs, i);
+                }
                 loaded = inst;
             }
             ob_base = inst * (unsigned int)(P - 1) * (unsigned int)a.n_super;
@@ -1046,6 +1088,14 @@ int launch_step(const StepArgs& a, int grid, void* stream) {
 }
 
 int plan_batch_max_buckets() { return kRegion; }
+
+size_t instance_table_doubles() { return kInstTabs; }
+
+int launch_instance_tables(const StepArgs& a, double* out, void* stream) {
+    if (a.P != 4) return (int)hipSuccess;    // the tables serve two-level systems
+    hipLaunchKernelGGL((instance_tables<4, 2>), dim3(a.n_inst), dim3(kThreads), 0, (hipStream_t)stream, a, out);
+    return (int)hipGetLastError();
+}
 
 int launch_plan_batch(const PlanArgs& a, void* stream) {
     hipStream_t st = (hipStream_t)stream;
