@@ -33,6 +33,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "quapi_device.h"
 #include "quapi_host.h"
 #include "quapi_sparse.h"
@@ -99,30 +101,57 @@ __device__ inline Hist<W> load_hist(const uint64_t* p, unsigned long long g) {
     return h;
 }
 
+// History chunks of kChunkBits bits (two points of a two-level system, one of
+// a three-level one) index two tables built per step and workgroup: the
+// chunk's share of the influence sums A, B, Ac, Bc, and its points placed
+// where the child holds them (key or other word).  A parent then costs one
+// table read per chunk instead of a loop over its points.
+constexpr int kChunkBits = 4;
+constexpr int kChunkVals = 1 << kChunkBits;
+constexpr int kMaxChunks = 128 / kChunkBits;              // a two-word history
+
+template <int W>
+__device__ inline unsigned int chunk_at(const Hist<W>& h, int c) {
+    const int bit = kChunkBits * c;
+    const unsigned long long word = (W == 1 || bit < 64) ? h.w[0] : h.w[W - 1];
+    return (unsigned int)((word >> (bit & 63)) & (unsigned long long)(kChunkVals - 1));
+}
+
 // F32: the precision form.  A group's amplitude is read as (ln|w|, arg w) in
 // FP32; each child adds ln K4 and its influence exponent in FP32, leaves the
 // log domain with FP32 exp and sin/cos, and enters the filter, the merge sums
 // and rho(t) in FP64.
+//
+// A thread takes one parent at a time.  Its children are inserted in groups of
+// PB: the first probes of a group are issued together, so that their round
+// trips to the memory-side atomics overlap.
 template <int P, int BP, int W, bool F32>
 __global__ __launch_bounds__(kSparseThreads) void sparse_expand(const SparseArgs a) {
+    using Real = typename std::conditional<F32, float, double>::type;
+    using Real2 = typename std::conditional<F32, float2, double2>::type;
     constexpr int S = partial_stride(P);
+    constexpr int PPC = kChunkBits / BP;                     // points per chunk
+    constexpr int PB = P == 4 ? 4 : 3;                       // children per insertion group
     constexpr unsigned long long DM = (1ull << BP) - 1;
     __shared__ double k4re[P * P], k4im[P * P], ds[P], ss[P];
     __shared__ double cre[kMaxK + 1], cim[kMaxK + 1], dre[kMaxK + 1], dim[kMaxK + 1];
+    __shared__ double e0f0[2];                               // two-level FP64: exp(-D^2 Re c_0), exp(-D^2 Re delta_0)
     // FP32 precision form: ln|K4|, arg K4 and the exponent tables in FP32
     __shared__ float lk4[F32 ? P * P : 1], ak4[F32 ? P * P : 1], dsf[F32 ? P : 1], ssf[F32 ? P : 1];
     __shared__ float cref[F32 ? kMaxK + 1 : 1], cimf[F32 ? kMaxK + 1 : 1];
     __shared__ float dref[F32 ? kMaxK + 1 : 1], dimf[F32 ? kMaxK + 1 : 1];
     __shared__ double wpart[kSpWaves][S];
-    // for each merge (other) position, the bit of the parent's point that the
-    // child holds there; -1 for position 0, the new point
-    __shared__ int qsh[kMaxK], nsh[kMaxK];
+    // child position -> its shift in the key, or 256 + its shift in the other word
+    __shared__ int pmap[kMaxK];
+    __shared__ Real2 itab[kMaxChunks][kChunkVals][2];        // (A, B), (Ac, Bc) of a chunk value
+    __shared__ ulonglong2 gtab[kMaxChunks][kChunkVals];      // (key bits, other bits) of a chunk value
     const int i = threadIdx.x;
     const int wave = i >> 6;
     const unsigned int lane = lane_id();
     const int K = a.K, t = a.t, nq = a.nq, nn = a.nn;
-    if (i < nq) qsh[i] = a.qpos[i] == 0 ? -1 : BP * (a.qpos[i] - 1);
-    if (i < nn) nsh[i] = a.npos[i] == 0 ? -1 : BP * (a.npos[i] - 1);
+    const int dmax = t < K ? t : K;
+    if (i < nq) pmap[a.qpos[i]] = BP * (nq - 1 - i);
+    if (i < nn) pmap[a.npos[i]] = 256 + BP * (nn - 1 - i);
     // where the new point goes: its shift in the key, else in the other word
     int kshift = -1, nshift = -1;
     for (int k = 0; k < nq; ++k)
@@ -159,6 +188,49 @@ __global__ __launch_bounds__(kSparseThreads) void sparse_expand(const SparseArgs
         }
     }
     __syncthreads();
+    if (P == 4 && !F32 && i == 0) {
+        const double D = ds[1];
+        e0f0[0] = exp(-D * (cre[0] * D));
+        e0f0[1] = exp(-D * (dre[0] * D));
+    }
+    // the chunk tables: parent point j = c*PPC + u lies at lag j+1 and goes to
+    // the child's position j+1 (dropped at K)
+    const int n_chunks = (K + PPC - 1) / PPC;
+    for (int e = i; e < n_chunks * kChunkVals; e += kSparseThreads) {
+        const int c = e / kChunkVals, v = e % kChunkVals;
+        Real A = 0, B = 0, Ac = 0, Bc = 0;
+        unsigned long long kp = 0ull, np = 0ull;
+#pragma unroll
+        for (int u = 0; u < PPC; ++u) {
+            const unsigned int x = (unsigned int)((v >> (BP * u)) & DM);
+            const int j = c * PPC + u;
+            if ((int)x >= P) continue;                       // not a point (three levels)
+            if (j < dmax) {
+                if (F32) {
+                    A = __builtin_fmaf(cref[j + 1], dsf[x], A);
+                    B = __builtin_fmaf(cimf[j + 1], ssf[x], B);
+                    Ac = __builtin_fmaf(dref[j + 1], dsf[x], Ac);
+                    Bc = __builtin_fmaf(dimf[j + 1], ssf[x], Bc);
+                } else {
+                    A = __builtin_fma(cre[j + 1], ds[x], A);
+                    B = __builtin_fma(cim[j + 1], ss[x], B);
+                    Ac = __builtin_fma(dre[j + 1], ds[x], Ac);
+                    Bc = __builtin_fma(dim[j + 1], ss[x], Bc);
+                }
+            }
+            if (j + 1 < K) {
+                const int m = pmap[j + 1];
+                if (m >= 256) np |= (unsigned long long)x << (m - 256);
+                else kp |= (unsigned long long)x << m;
+            }
+        }
+        Real2 ab, abc;
+        ab.x = A; ab.y = B; abc.x = Ac; abc.y = Bc;
+        itab[c][v][0] = ab;
+        itab[c][v][1] = abc;
+        gtab[c][v] = make_ulonglong2(kp, np);
+    }
+    __syncthreads();
 
     double acc[S];
 #pragma unroll
@@ -167,7 +239,6 @@ __global__ __launch_bounds__(kSparseThreads) void sparse_expand(const SparseArgs
     const unsigned long long n_in = groups_in(a);
     const unsigned long long N = failed ? 0ull : n_in;
     const unsigned long long tm = table_mask(a, n_in);
-    const int dmax = t < K ? t : K;
     const bool packed = a.packed != 0;
     const unsigned long long omask = packed ? other_mask(a) : 0ull;
     const unsigned long long qmask = ~((1ull << a.qbits) - 1ull);
@@ -179,117 +250,150 @@ __global__ __launch_bounds__(kSparseThreads) void sparse_expand(const SparseArgs
         float2 Wl = make_float2(0.0f, 0.0f);
         if (F32) Wl = a.wf_in[g];
         else Wt = a.w_in[g];
-        double A = 0.0, B = 0.0, Ac = 0.0, Bc = 0.0;
-        float Af = 0.0f, Bf = 0.0f, Acf = 0.0f, Bcf = 0.0f;
-        for (int d = 1; d <= dmax; ++d) {
-            const unsigned int x = (unsigned int)point_at<BP, W>(h, BP * (d - 1));
-            if (F32) {
-                Af = __builtin_fmaf(cref[d], dsf[x], Af);
-                Bf = __builtin_fmaf(cimf[d], ssf[x], Bf);
-                Acf = __builtin_fmaf(dref[d], dsf[x], Acf);
-                Bcf = __builtin_fmaf(dimf[d], ssf[x], Bcf);
-            } else {
-                A = __builtin_fma(cre[d], ds[x], A);
-                B = __builtin_fma(cim[d], ss[x], B);
-                Ac = __builtin_fma(dre[d], ds[x], Ac);
-                Bc = __builtin_fma(dim[d], ss[x], Bc);
-            }
-        }
-        // the children's key and other points, but for the new point
+        // influence sums over lags 1..dmax, and the children's key and other
+        // points but for the new point
+        Real A = 0, B = 0, Ac = 0, Bc = 0;
         unsigned long long kb = 0ull, nb = 0ull;
-        for (int k = 0; k < nq; ++k) {
-            const int sh = qsh[k];
-            kb = (kb << BP) | (sh < 0 ? 0ull : point_at<BP, W>(h, sh));
-        }
-        for (int k = 0; k < nn; ++k) {
-            const int sh = nsh[k];
-            nb = (nb << BP) | (sh < 0 ? 0ull : point_at<BP, W>(h, sh));
+        for (int c = 0; c < n_chunks; ++c) {
+            const unsigned int v = chunk_at<W>(h, c);
+            const Real2 ab = itab[c][v][0], abc = itab[c][v][1];
+            const ulonglong2 kn = gtab[c][v];
+            A += ab.x;
+            B += ab.y;
+            Ac += abc.x;
+            Bc += abc.y;
+            kb |= kn.x;
+            nb |= kn.y;
         }
         const int h0 = (int)(h.w[0] & DM);
+        // two levels, FP64: pairs (0,1) and (1,0) have ds = +D, -D and equal ss,
+        // so their exponents are mirror images and share one exp and one sincos
+        double er1 = 1.0, ei1 = 0.0, er2 = 1.0, ei2 = 0.0, fr1 = 1.0, fi1 = 0.0, fr2 = 1.0, fi2 = 0.0;
+        if constexpr (P == 4 && !F32) {
+            const double D = ds[1], Sg = ss[1];
+            const double x = D * A, y = D * __builtin_fma(cim[0], Sg, B);
+            const double xc = D * Ac, yc = D * __builtin_fma(dim[0], Sg, Bc);
+            const double ex = exp(x), exc = exp(xc);
+            const double iex = recip(ex), iexc = recip(exc);
+            double sy, cy, syc, cyc;
+            sincos(y, &sy, &cy);
+            sincos(yc, &syc, &cyc);
+            const double e0 = e0f0[0], f0 = e0f0[1];
+            er1 = e0 * iex * cy;  ei1 = -(e0 * iex * sy);
+            er2 = e0 * ex * cy;   ei2 = e0 * ex * sy;
+            fr1 = f0 * iexc * cyc; fi1 = -(f0 * iexc * syc);
+            fr2 = f0 * exc * cyc;  fi2 = f0 * exc * syc;
+        }
 #pragma unroll
-        for (int p = 0; p < P; ++p) {
-            double wr, wi, rr, ri;   // the child's amplitude; its rho(t) term
-            if (F32) {
-                float lr = Wl.x + lk4[p * P + h0], ph = Wl.y + ak4[p * P + h0];
-                float lc = lr, pc = ph;
-                const float dsp = dsf[p], ssp = ssf[p];
-                if (dsp != 0.0f) {
-                    lr += -dsp * (cref[0] * dsp + Af);
-                    ph += -dsp * (cimf[0] * ssp + Bf);
-                    lc = lr - dsp * (dref[0] * dsp + Acf);
-                    pc = ph - dsp * (dimf[0] * ssp + Bcf);
+        for (int p0 = 0; p0 < P; p0 += PB) {
+            double cwr[PB], cwi[PB];
+            unsigned long long ckk[PB], cs[PB], prev[PB];
+            bool live[PB];
+            // the group's children: amplitude, filter, rho(t) term, first slot
+#pragma unroll
+            for (int u = 0; u < PB; ++u) {
+                const int p = p0 + u;
+                live[u] = false;
+                cwr[u] = cwi[u] = 0.0;
+                ckk[u] = cs[u] = prev[u] = 0ull;
+                if (p >= P) continue;
+                double wr, wi, rr, ri;   // the child's amplitude; its rho(t) term
+                if constexpr (F32) {
+                    float lr = Wl.x + lk4[p * P + h0], ph = Wl.y + ak4[p * P + h0];
+                    float lc = lr, pc = ph;
+                    const float dsp = dsf[p], ssp = ssf[p];
+                    if (dsp != 0.0f) {
+                        lr += -dsp * (cref[0] * dsp + A);
+                        ph += -dsp * (cimf[0] * ssp + B);
+                        lc = lr - dsp * (dref[0] * dsp + Ac);
+                        pc = ph - dsp * (dimf[0] * ssp + Bc);
+                    }
+                    const float m = expf(lr), mc = expf(lc);
+                    float sn, cs2, snc, csc;
+                    sincosf(ph, &sn, &cs2);
+                    sincosf(pc, &snc, &csc);
+                    wr = (double)(m * cs2);
+                    wi = (double)(m * sn);
+                    rr = (double)(mc * csc);
+                    ri = (double)(mc * snc);
+                } else {
+                    double er = 1.0, ei = 0.0, fr = 1.0, fi = 0.0;
+                    if constexpr (P == 4) {
+                        if (p == 1) { er = er1; ei = ei1; fr = fr1; fi = fi1; }
+                        if (p == 2) { er = er2; ei = ei2; fr = fr2; fi = fi2; }
+                    } else {
+                        const double dsp = ds[p], ssp = ss[p];
+                        if (dsp != 0.0) {
+                            const double e = exp(-dsp * (cre[0] * dsp + A));
+                            double sn, cs2;
+                            sincos(-dsp * (cim[0] * ssp + B), &sn, &cs2);
+                            er = e * cs2;
+                            ei = e * sn;
+                            const double f = exp(-dsp * (dre[0] * dsp + Ac));
+                            double fs, fc;
+                            sincos(-dsp * (dim[0] * ssp + Bc), &fs, &fc);
+                            fr = f * fc;
+                            fi = f * fs;
+                        }
+                    }
+                    const double k4r = k4re[p * P + h0], k4i = k4im[p * P + h0];
+                    const double br = Wt.x * k4r - Wt.y * k4i;
+                    const double bi = Wt.x * k4i + Wt.y * k4r;
+                    wr = br * er - bi * ei;
+                    wi = br * ei + bi * er;
+                    rr = wr * fr - wi * fi;
+                    ri = wr * fi + wi * fr;
                 }
-                const float m = expf(lr), mc = expf(lc);
-                float sn, cs, snc, csc;
-                sincosf(ph, &sn, &cs);
-                sincosf(pc, &snc, &csc);
-                wr = (double)(m * cs);
-                wi = (double)(m * sn);
-                rr = (double)(mc * csc);
-                ri = (double)(mc * snc);
-            } else {
-                double er = 1.0, ei = 0.0, fr = 1.0, fi = 0.0;
-                const double dsp = ds[p], ssp = ss[p];
-                if (dsp != 0.0) {
-                    const double e = exp(-dsp * (cre[0] * dsp + A));
-                    double sn, cs;
-                    sincos(-dsp * (cim[0] * ssp + B), &sn, &cs);
-                    er = e * cs;
-                    ei = e * sn;
-                    const double f = exp(-dsp * (dre[0] * dsp + Ac));
-                    double fs, fc;
-                    sincos(-dsp * (dim[0] * ssp + Bc), &fs, &fc);
-                    fr = f * fc;
-                    fi = f * fs;
+                const double n2 = norm2_nocontract(wr, wi);
+                if (!((a.theta2 == 0.0) || !(n2 < a.theta2))) {
+                    acc[2 * P] += sqrt(n2);
+                    if (!packed) a.cslot[g * P + p] = ~0u;
+                    continue;
                 }
-                const double k4r = k4re[p * P + h0], k4i = k4im[p * P + h0];
-                const double br = Wt.x * k4r - Wt.y * k4i;
-                const double bi = Wt.x * k4i + Wt.y * k4r;
-                wr = br * er - bi * ei;
-                wi = br * ei + bi * er;
-                rr = wr * fr - wi * fi;
-                ri = wr * fi + wi * fr;
+                acc[2 * p] += rr;
+                acc[2 * p + 1] += ri;
+                acc[2 * P + 1] += 1.0;
+                const unsigned long long key = kb | (kshift < 0 ? 0ull : (unsigned long long)p << kshift);
+                ckk[u] = key + 1ull;                         // stored form: zero is a free slot
+                cs[u] = mix64(key) & tm;
+                cwr[u] = wr;
+                cwi[u] = wi;
+                live[u] = true;
             }
-            const double n2 = norm2_nocontract(wr, wi);
-            const unsigned long long ci = g * P + p;
-            if (!((a.theta2 == 0.0) || !(n2 < a.theta2))) {
-                acc[2 * P] += sqrt(n2);
-                if (!packed) a.cslot[ci] = ~0u;
-                continue;
-            }
-            acc[2 * p] += rr;
-            acc[2 * p + 1] += ri;
-            acc[2 * P + 1] += 1.0;
-            const unsigned long long key = kb | (kshift < 0 ? 0ull : (unsigned long long)p << kshift);
-            const unsigned long long kk = key + 1ull;     // stored form: zero is a free slot
-            unsigned long long s = mix64(key) & tm;
-            bool placed = false;
-            for (int probe = 0; probe < kMaxProbe; ++probe) {
-                const unsigned long long prev = atomicCAS(&a.slot[s].key, 0ull, kk);
-                if (prev == 0ull || prev == kk) {
-                    placed = true;
-                    break;
+            // first probes, all in flight together
+#pragma unroll
+            for (int u = 0; u < PB; ++u)
+                if (live[u]) prev[u] = atomicCAS(&a.slot[cs[u]].key, 0ull, ckk[u]);
+            // further probes where taken by another key, then the slot's updates
+#pragma unroll
+            for (int u = 0; u < PB; ++u) {
+                if (!live[u]) continue;
+                const int p = p0 + u;
+                const unsigned long long ci = g * P + p;
+                for (int probe = 1; prev[u] != 0ull && prev[u] != ckk[u] && probe < kMaxProbe; ++probe) {
+                    cs[u] = (cs[u] + 1ull) & tm;
+                    prev[u] = atomicCAS(&a.slot[cs[u]].key, 0ull, ckk[u]);
                 }
-                s = (s + 1ull) & tm;
+                if (prev[u] != 0ull && prev[u] != ckk[u]) {
+                    raise_error(a.error, t, kErrOverflow);
+                    if (!packed) a.cslot[ci] = ~0u;
+                    continue;
+                }
+                SpSlot* const e = a.slot + cs[u];
+                const unsigned long long n2b = (unsigned long long)__double_as_longlong(norm2_nocontract(cwr[u], cwi[u]));
+                const unsigned long long nk = nb | (nshift < 0 ? 0ull : (unsigned long long)p << nshift);
+                if (packed) {
+                    atomicMax(&e->best, ((n2b >> a.qbits) << (a.qbits + 1)) | (omask ^ nk));
+                } else {
+                    const unsigned long long q = n2b & qmask;
+                    atomicMax(&e->best, q);
+                    a.cslot[ci] = (unsigned int)cs[u];
+                    a.cN[ci] = nk;
+                    a.cq[ci] = q;
+                }
+                unsafeAtomicAdd(&e->wr, cwr[u]);
+                unsafeAtomicAdd(&e->wi, cwi[u]);
             }
-            if (!placed) {
-                raise_error(a.error, t, kErrOverflow);
-                if (!packed) a.cslot[ci] = ~0u;
-                continue;
-            }
-            const unsigned long long n2b = (unsigned long long)__double_as_longlong(n2);
-            const unsigned long long nk = nb | (nshift < 0 ? 0ull : (unsigned long long)p << nshift);
-            if (packed) {
-                atomicMax(&a.slot[s].best, ((n2b >> a.qbits) << (a.qbits + 1)) | (omask ^ nk));
-            } else {
-                const unsigned long long q = n2b & qmask;
-                atomicMax(&a.slot[s].best, q);
-                a.cslot[ci] = (unsigned int)s;
-                a.cN[ci] = nk;
-                a.cq[ci] = q;
-            }
-            unsafeAtomicAdd(&a.slot[s].wr, wr);
-            unsafeAtomicAdd(&a.slot[s].wi, wi);
         }
     }
 
@@ -330,15 +434,19 @@ __global__ __launch_bounds__(kSparseThreads) void sparse_resolve(const SparseArg
 
 // Tiles of kRows x kSparseThreads slots: each tile takes its place in the
 // output with one counter update and writes its used slots in slot order.
+// The used slots of a tile are first listed in the LDS, so that consecutive
+// threads rebuild consecutive groups (most slots are free: the table is sized
+// for twice the children, and children merge).
 template <int BP, int W, bool F32>
 __global__ __launch_bounds__(kSparseThreads) void sparse_compact(const SparseArgs a) {
     constexpr unsigned long long DM = (1ull << BP) - 1;
     __shared__ unsigned int wcnt[kRows][kSpWaves];
-    __shared__ unsigned int tile_base;
+    __shared__ unsigned int tile_base, tile_used;
+    __shared__ unsigned short lpos[kTile];                  // used slots of the tile, in slot order
+    __shared__ unsigned long long lkey[kTile];              // and their stored keys
     const int i = threadIdx.x;
     const int wave = i >> 6;
     const bool failed = error_word(a.error) != 0u;
-    const unsigned int lane = lane_id();
     unsigned int* const out_count = a.count + (a.t & 1);
     const unsigned long long tm = table_mask(a, groups_in(a));
     const unsigned long long n_tiles = (tm + kTile) / kTile;
@@ -346,14 +454,14 @@ __global__ __launch_bounds__(kSparseThreads) void sparse_compact(const SparseArg
     const unsigned long long omask = packed ? other_mask(a) : 0ull;
     const int nq = a.nq, nn = a.nn;
     for (unsigned long long tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-        const unsigned long long s0 = tile * kTile + (unsigned long long)i;
+        const unsigned long long s0 = tile * kTile;
         unsigned long long kk[kRows], bal[kRows];
 #pragma unroll
         for (int r = 0; r < kRows; ++r) {
-            const unsigned long long sl = s0 + (unsigned long long)r * kSparseThreads;
+            const unsigned long long sl = s0 + (unsigned long long)(r * kSparseThreads + i);
             kk[r] = sl <= tm ? a.slot[sl].key : 0ull;
             bal[r] = __ballot(kk[r] != 0ull);
-            if (lane == 0u) wcnt[r][wave] = (unsigned int)__popcll(bal[r]);
+            if (lane_id() == 0u) wcnt[r][wave] = (unsigned int)__popcll(bal[r]);
         }
         __syncthreads();
         if (i == 0) {
@@ -364,15 +472,22 @@ __global__ __launch_bounds__(kSparseThreads) void sparse_compact(const SparseArg
                     wcnt[r][w] = tot;
                     tot += c;
                 }
+            tile_used = tot;
             tile_base = tot ? atomicAdd(out_count, tot) : 0u;
         }
         __syncthreads();
-        const unsigned int base = tile_base;
 #pragma unroll
         for (int r = 0; r < kRows; ++r) {
             if (kk[r] == 0ull) continue;
-            const unsigned long long sl = s0 + (unsigned long long)r * kSparseThreads;
-            const unsigned long long idx = (unsigned long long)base + wcnt[r][wave] + rank_below(bal[r]);
+            const unsigned int j = wcnt[r][wave] + rank_below(bal[r]);
+            lpos[j] = (unsigned short)(r * kSparseThreads + i);
+            lkey[j] = kk[r];
+        }
+        __syncthreads();
+        const unsigned int base = tile_base, used = tile_used;
+        for (unsigned int j = (unsigned int)i; j < used; j += kSparseThreads) {
+            const unsigned long long sl = s0 + lpos[j];
+            const unsigned long long idx = (unsigned long long)base + j;
             SpSlot* const e = a.slot + sl;
             unsigned long long nk = 0ull;
             if (packed) {
@@ -383,7 +498,7 @@ __global__ __launch_bounds__(kSparseThreads) void sparse_compact(const SparseArg
             }
             if (!failed && idx < (unsigned long long)a.cap) {
                 // the key's points at the merge positions, the representative's elsewhere
-                const unsigned long long key = kk[r] - 1ull;
+                const unsigned long long key = lkey[j] - 1ull;
                 Hist<W> hist;
 #pragma unroll
                 for (int w = 0; w < W; ++w) hist.w[w] = 0ull;
@@ -414,7 +529,7 @@ __global__ __launch_bounds__(kSparseThreads) void sparse_compact(const SparseArg
             e->wr = 0.0;
             e->wi = 0.0;
         }
-        __syncthreads();   // wcnt and tile_base are rewritten by the next tile
+        __syncthreads();   // the LDS list and counts are rewritten by the next tile
     }
 }
 
