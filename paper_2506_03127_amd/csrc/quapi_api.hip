@@ -313,6 +313,11 @@ int step_sparse(quapi_ctx* c, int n_steps) {
         a.qpos[k] = k < a.nq ? c->qpos[k] : 0;
         a.npos[k] = k < a.nn ? c->npos[k] : 0;
     }
+    // the clustered positions: merge positions q with q+1 also a merge position
+    a.cmask = 0ull;
+    for (int k = 0; k < a.nq; ++k)
+        if (std::find(c->qpos.begin(), c->qpos.end(), c->qpos[k] + 1) != c->qpos.end())
+            a.cmask |= ((1ull << c->bits) - 1ull) << (c->bits * (a.nq - 1 - k));
     a.partials = c->sp_partials;
     a.grid = c->sp_grid;
     a.rho_hist = c->d_rho;

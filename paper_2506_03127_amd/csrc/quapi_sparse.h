@@ -51,6 +51,7 @@ struct SparseArgs {
     int nn;                         // the other positions, oldest (most significant) first
     int qpos[kMaxK];
     int npos[kMaxK];
+    unsigned long long cmask;       // key bits of the merge positions q with q+1 also one (table windows)
     double* partials;               // [partial_stride(P)][grid] per expand workgroup
     int grid;
     double2* rho_hist;

@@ -11,11 +11,11 @@
 //             element (eq. SysP) times the influence factor of the new point
 //             (eq. inf_fun); drop children below theta (Sec. 2.1); add the
 //             survivors to this workgroup's rho(t) sums with the end-point
-//             correction of the final point (Sec. 3.2.1); insert each
-//             survivor's merge key into the table, raise the slot's
-//             representative word to the child's and add the weight to the
-//             key's sum (the group amplitude is the sum of all its members,
-//             Sec. 3.1.2);
+//             correction of the final point (Sec. 3.2.1); merge the
+//             survivors of a pass in an LDS table, then insert each merged
+//             key into the table, raise the slot's representative word to
+//             the best child's and add the weights to the key's sum (the
+//             group amplitude is the sum of all its members, Sec. 3.1.2);
 //   resolve - unpacked form only: among the children of a key with its
 //             largest quantised |w|^2, keep the smallest history;
 //   compact - write one group per used slot, its history rebuilt from the key
@@ -33,6 +33,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "quapi_device.h"
@@ -54,6 +55,21 @@ __device__ inline unsigned long long mix64(unsigned long long z) {
     z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
     z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
     return z ^ (z >> 31);
+}
+
+// The table is cut into windows of 2^kWinBits slots.  A key's window is the
+// hash of its points at the clustered positions (merge positions q with q+1
+// also a merge position), its place inside the window the hash of the whole
+// key.  A group's clustered points are the points of its next-step merge
+// signature that its key holds, so groups whose children merge at the next
+// step share a window, and compact, which scans in slot order, stores them
+// side by side: the next expand then meets them in one workgroup pass.
+constexpr int kWinBits = 9;
+
+__device__ inline unsigned long long home_slot(unsigned long long key, unsigned long long cmask,
+                                               unsigned long long tm) {
+    if (cmask == 0ull) return mix64(key) & tm;
+    return ((mix64(key & cmask) << kWinBits) | (mix64(key) & ((1ull << kWinBits) - 1ull))) & tm;
 }
 
 // groups stored at t-1 (the step's input), bounded by the capacity
@@ -108,7 +124,14 @@ __device__ inline Hist<W> load_hist(const uint64_t* p, unsigned long long g) {
 // table read per chunk instead of a loop over its points.
 constexpr int kChunkBits = 4;
 constexpr int kChunkVals = 1 << kChunkBits;
-constexpr int kMaxChunks = 128 / kChunkBits;              // a two-word history
+constexpr int kLdsRows = 4;                               // LDS merge slots per thread
+constexpr int kLds = kLdsRows * kSparseThreads;           // a pass's children at P = 4
+constexpr int kLdsProbe = 32;
+// dynamic LDS of the expand kernel at least this, which with its static LDS
+// leaves room for two workgroups per CU: with more in flight the memory-side
+// atomics contend (long memory, K = 40: 5.4 ms per expand at two per CU,
+// 6.1 ms at three, 7.1 ms at one)
+constexpr size_t kExpandLdsFloor = 24 * 1024;
 
 template <int W>
 __device__ inline unsigned int chunk_at(const Hist<W>& h, int c) {
@@ -117,21 +140,33 @@ __device__ inline unsigned int chunk_at(const Hist<W>& h, int c) {
     return (unsigned int)((word >> (bit & 63)) & (unsigned long long)(kChunkVals - 1));
 }
 
+// bytes of the influence table of n chunks; the key table follows it
+template <bool F32>
+__host__ __device__ constexpr size_t sparse_itab_bytes(int n_chunks) {
+    return (size_t)n_chunks * kChunkVals * 2 * (F32 ? sizeof(float2) : sizeof(double2));
+}
+template <bool F32>
+__host__ __device__ constexpr size_t sparse_chunk_lds(int n_chunks) {
+    return sparse_itab_bytes<F32>(n_chunks) + (size_t)n_chunks * kChunkVals * sizeof(ulonglong2);
+}
+
 // F32: the precision form.  A group's amplitude is read as (ln|w|, arg w) in
 // FP32; each child adds ln K4 and its influence exponent in FP32, leaves the
 // log domain with FP32 exp and sin/cos, and enters the filter, the merge sums
 // and rho(t) in FP64.
 //
-// A thread takes one parent at a time.  Its children are inserted in groups of
-// PB: the first probes of a group are issued together, so that their round
-// trips to the memory-side atomics overlap.
+// A workgroup takes kSparseThreads parents per pass.  Their children merge
+// first in a table in the LDS (key, best word, weight sums; unpacked form:
+// also the smallest other word at the best q); each used LDS slot then makes
+// one insertion into the table in HBM, whose atomics are performed at the
+// memory side and bound the kernel.  Children that find the LDS table full go
+// to the HBM table directly.
 template <int P, int BP, int W, bool F32>
 __global__ __launch_bounds__(kSparseThreads) void sparse_expand(const SparseArgs a) {
     using Real = typename std::conditional<F32, float, double>::type;
     using Real2 = typename std::conditional<F32, float2, double2>::type;
     constexpr int S = partial_stride(P);
     constexpr int PPC = kChunkBits / BP;                     // points per chunk
-    constexpr int PB = P == 4 ? 4 : 3;                       // children per insertion group
     constexpr unsigned long long DM = (1ull << BP) - 1;
     __shared__ double k4re[P * P], k4im[P * P], ds[P], ss[P];
     __shared__ double cre[kMaxK + 1], cim[kMaxK + 1], dre[kMaxK + 1], dim[kMaxK + 1];
@@ -143,8 +178,16 @@ __global__ __launch_bounds__(kSparseThreads) void sparse_expand(const SparseArgs
     __shared__ double wpart[kSpWaves][S];
     // child position -> its shift in the key, or 256 + its shift in the other word
     __shared__ int pmap[kMaxK];
-    __shared__ Real2 itab[kMaxChunks][kChunkVals][2];        // (A, B), (Ac, Bc) of a chunk value
-    __shared__ ulonglong2 gtab[kMaxChunks][kChunkVals];      // (key bits, other bits) of a chunk value
+    // the chunk tables, in dynamic LDS sized for the step's chunks:
+    // (A, B), (Ac, Bc) and (key bits, other bits) of each chunk value
+    extern __shared__ __align__(16) unsigned char chunk_lds[];
+    Real2 (*const itab)[kChunkVals][2] = reinterpret_cast<Real2 (*)[kChunkVals][2]>(chunk_lds);
+    // the LDS merge of one pass's children: key + 1 (0: free), best word
+    // (unpacked form: then the smallest other word at the best q), weight sums
+    __shared__ unsigned long long lkey[kLds], lbest[kLds];
+    __shared__ double lwr[kLds], lwi[kLds];
+    __shared__ unsigned int loff[kLdsRows][kSpWaves];
+    __shared__ unsigned int lovf[2], lused;
     const int i = threadIdx.x;
     const int wave = i >> 6;
     const unsigned int lane = lane_id();
@@ -159,6 +202,13 @@ __global__ __launch_bounds__(kSparseThreads) void sparse_expand(const SparseArgs
     for (int k = 0; k < nn; ++k)
         if (a.npos[k] == 0) nshift = BP * (nn - 1 - k);
 
+    for (int k = i; k < kLds; k += kSparseThreads) {
+        lkey[k] = 0ull;
+        lbest[k] = 0ull;
+        lwr[k] = 0.0;
+        lwi[k] = 0.0;
+    }
+    if (i < 2) lovf[i] = 0u;
     for (int k = i; k < P * P; k += kSparseThreads) {
         k4re[k] = a.tables[2 * k];
         k4im[k] = a.tables[2 * k + 1];
@@ -196,6 +246,8 @@ __global__ __launch_bounds__(kSparseThreads) void sparse_expand(const SparseArgs
     // the chunk tables: parent point j = c*PPC + u lies at lag j+1 and goes to
     // the child's position j+1 (dropped at K)
     const int n_chunks = (K + PPC - 1) / PPC;
+    ulonglong2 (*const gtab)[kChunkVals] =
+        reinterpret_cast<ulonglong2 (*)[kChunkVals]>(chunk_lds + sparse_itab_bytes<F32>(n_chunks));
     for (int e = i; e < n_chunks * kChunkVals; e += kSparseThreads) {
         const int c = e / kChunkVals, v = e % kChunkVals;
         Real A = 0, B = 0, Ac = 0, Bc = 0;
@@ -242,61 +294,87 @@ __global__ __launch_bounds__(kSparseThreads) void sparse_expand(const SparseArgs
     const bool packed = a.packed != 0;
     const unsigned long long omask = packed ? other_mask(a) : 0ull;
     const unsigned long long qmask = ~((1ull << a.qbits) - 1ull);
+    const unsigned long long cmask = a.cmask;
     const unsigned long long stride = (unsigned long long)gridDim.x * kSparseThreads;
 
-    for (unsigned long long g = (unsigned long long)blockIdx.x * kSparseThreads + i; g < N; g += stride) {
-        const Hist<W> h = load_hist<W>(a.h_in, g);
-        double2 Wt = make_double2(0.0, 0.0);
-        float2 Wl = make_float2(0.0f, 0.0f);
-        if (F32) Wl = a.wf_in[g];
-        else Wt = a.w_in[g];
-        // influence sums over lags 1..dmax, and the children's key and other
-        // points but for the new point
-        Real A = 0, B = 0, Ac = 0, Bc = 0;
-        unsigned long long kb = 0ull, nb = 0ull;
-        for (int c = 0; c < n_chunks; ++c) {
-            const unsigned int v = chunk_at<W>(h, c);
-            const Real2 ab = itab[c][v][0], abc = itab[c][v][1];
-            const ulonglong2 kn = gtab[c][v];
-            A += ab.x;
-            B += ab.y;
-            Ac += abc.x;
-            Bc += abc.y;
-            kb |= kn.x;
-            nb |= kn.y;
+    // A slot of the table takes its updates from a child or from a merged LDS
+    // slot (all its children's sum and best word).  Unpacked form: the entry
+    // (slot, other word, q) that the resolve pass reads.
+    auto update = [&](unsigned long long sl, unsigned long long word, unsigned long long nk, double wr, double wi,
+                      unsigned long long entry) {
+        SpSlot* const e = a.slot + sl;
+        atomicMax(&e->best, word);
+        if (!packed) {
+            a.cslot[entry] = (unsigned int)sl;
+            a.cN[entry] = nk;
+            a.cq[entry] = word;
         }
-        const int h0 = (int)(h.w[0] & DM);
-        // two levels, FP64: pairs (0,1) and (1,0) have ds = +D, -D and equal ss,
-        // so their exponents are mirror images and share one exp and one sincos
-        double er1 = 1.0, ei1 = 0.0, er2 = 1.0, ei2 = 0.0, fr1 = 1.0, fi1 = 0.0, fr2 = 1.0, fi2 = 0.0;
-        if constexpr (P == 4 && !F32) {
-            const double D = ds[1], Sg = ss[1];
-            const double x = D * A, y = D * __builtin_fma(cim[0], Sg, B);
-            const double xc = D * Ac, yc = D * __builtin_fma(dim[0], Sg, Bc);
-            const double ex = exp(x), exc = exp(xc);
-            const double iex = recip(ex), iexc = recip(exc);
-            double sy, cy, syc, cyc;
-            sincos(y, &sy, &cy);
-            sincos(yc, &syc, &cyc);
-            const double e0 = e0f0[0], f0 = e0f0[1];
-            er1 = e0 * iex * cy;  ei1 = -(e0 * iex * sy);
-            er2 = e0 * ex * cy;   ei2 = e0 * ex * sy;
-            fr1 = f0 * iexc * cyc; fi1 = -(f0 * iexc * syc);
-            fr2 = f0 * exc * cyc;  fi2 = f0 * exc * syc;
-        }
+        unsafeAtomicAdd(&e->wr, wr);
+        unsafeAtomicAdd(&e->wi, wi);
+    };
+    auto overflow = [&](unsigned long long entry) {
+        raise_error(a.error, t, kErrOverflow);
+        if (!packed) a.cslot[entry] = ~0u;
+    };
+
+    unsigned int pass = 0u;
+    for (unsigned long long base = (unsigned long long)blockIdx.x * kSparseThreads; base < N; base += stride, ++pass) {
+        // this pass: parents [base, base + n_par); unpacked-form entries
+        // [base*P, base*P + n_ent): merged LDS slots from the bottom, children
+        // that found the LDS full from the top, the rest marked unused
+        const unsigned int n_par = (unsigned int)((N - base) < kSparseThreads ? (N - base) : kSparseThreads);
+        const unsigned int n_ent = n_par * P;
+        const unsigned long long ebase = base * P;
+        unsigned int* const ovf = &lovf[pass & 1u];
+        if (i == 0) lovf[(pass + 1u) & 1u] = 0u;          // the next pass's counter (last read a pass ago)
+        unsigned int mls[P];                              // unpacked: LDS slot, q and other word of each child
+        unsigned long long mq[P], mnk[P];
 #pragma unroll
-        for (int p0 = 0; p0 < P; p0 += PB) {
-            double cwr[PB], cwi[PB];
-            unsigned long long ckk[PB], cs[PB], prev[PB];
-            bool live[PB];
-            // the group's children: amplitude, filter, rho(t) term, first slot
+        for (int p = 0; p < P; ++p) { mls[p] = ~0u; mq[p] = 0ull; mnk[p] = 0ull; }
+
+        const unsigned long long g = base + i;
+        if (g < N) {
+            const Hist<W> h = load_hist<W>(a.h_in, g);
+            double2 Wt = make_double2(0.0, 0.0);
+            float2 Wl = make_float2(0.0f, 0.0f);
+            if (F32) Wl = a.wf_in[g];
+            else Wt = a.w_in[g];
+            // influence sums over lags 1..dmax, and the children's key and other
+            // points but for the new point
+            Real A = 0, B = 0, Ac = 0, Bc = 0;
+            unsigned long long kb = 0ull, nb = 0ull;
+            for (int c = 0; c < n_chunks; ++c) {
+                const unsigned int v = chunk_at<W>(h, c);
+                const Real2 ab = itab[c][v][0], abc = itab[c][v][1];
+                const ulonglong2 kn = gtab[c][v];
+                A += ab.x;
+                B += ab.y;
+                Ac += abc.x;
+                Bc += abc.y;
+                kb |= kn.x;
+                nb |= kn.y;
+            }
+            const int h0 = (int)(h.w[0] & DM);
+            // two levels, FP64: pairs (0,1) and (1,0) have ds = +D, -D and equal ss,
+            // so their exponents are mirror images and share one exp and one sincos
+            double er1 = 1.0, ei1 = 0.0, er2 = 1.0, ei2 = 0.0, fr1 = 1.0, fi1 = 0.0, fr2 = 1.0, fi2 = 0.0;
+            if constexpr (P == 4 && !F32) {
+                const double D = ds[1], Sg = ss[1];
+                const double x = D * A, y = D * __builtin_fma(cim[0], Sg, B);
+                const double xc = D * Ac, yc = D * __builtin_fma(dim[0], Sg, Bc);
+                const double ex = exp(x), exc = exp(xc);
+                const double iex = recip(ex), iexc = recip(exc);
+                double sy, cy, syc, cyc;
+                sincos(y, &sy, &cy);
+                sincos(yc, &syc, &cyc);
+                const double e0 = e0f0[0], f0 = e0f0[1];
+                er1 = e0 * iex * cy;  ei1 = -(e0 * iex * sy);
+                er2 = e0 * ex * cy;   ei2 = e0 * ex * sy;
+                fr1 = f0 * iexc * cyc; fi1 = -(f0 * iexc * syc);
+                fr2 = f0 * exc * cyc;  fi2 = f0 * exc * syc;
+            }
 #pragma unroll
-            for (int u = 0; u < PB; ++u) {
-                const int p = p0 + u;
-                live[u] = false;
-                cwr[u] = cwi[u] = 0.0;
-                ckk[u] = cs[u] = prev[u] = 0ull;
-                if (p >= P) continue;
+            for (int p = 0; p < P; ++p) {
                 double wr, wi, rr, ri;   // the child's amplitude; its rho(t) term
                 if constexpr (F32) {
                     float lr = Wl.x + lk4[p * P + h0], ph = Wl.y + ak4[p * P + h0];
@@ -347,54 +425,127 @@ __global__ __launch_bounds__(kSparseThreads) void sparse_expand(const SparseArgs
                 const double n2 = norm2_nocontract(wr, wi);
                 if (!((a.theta2 == 0.0) || !(n2 < a.theta2))) {
                     acc[2 * P] += sqrt(n2);
-                    if (!packed) a.cslot[g * P + p] = ~0u;
                     continue;
                 }
                 acc[2 * p] += rr;
                 acc[2 * p + 1] += ri;
                 acc[2 * P + 1] += 1.0;
                 const unsigned long long key = kb | (kshift < 0 ? 0ull : (unsigned long long)p << kshift);
-                ckk[u] = key + 1ull;                         // stored form: zero is a free slot
-                cs[u] = mix64(key) & tm;
-                cwr[u] = wr;
-                cwi[u] = wi;
-                live[u] = true;
-            }
-            // first probes, all in flight together
-#pragma unroll
-            for (int u = 0; u < PB; ++u)
-                if (live[u]) prev[u] = atomicCAS(&a.slot[cs[u]].key, 0ull, ckk[u]);
-            // further probes where taken by another key, then the slot's updates
-#pragma unroll
-            for (int u = 0; u < PB; ++u) {
-                if (!live[u]) continue;
-                const int p = p0 + u;
-                const unsigned long long ci = g * P + p;
-                for (int probe = 1; prev[u] != 0ull && prev[u] != ckk[u] && probe < kMaxProbe; ++probe) {
-                    cs[u] = (cs[u] + 1ull) & tm;
-                    prev[u] = atomicCAS(&a.slot[cs[u]].key, 0ull, ckk[u]);
-                }
-                if (prev[u] != 0ull && prev[u] != ckk[u]) {
-                    raise_error(a.error, t, kErrOverflow);
-                    if (!packed) a.cslot[ci] = ~0u;
-                    continue;
-                }
-                SpSlot* const e = a.slot + cs[u];
-                const unsigned long long n2b = (unsigned long long)__double_as_longlong(norm2_nocontract(cwr[u], cwi[u]));
+                const unsigned long long kk = key + 1ull;         // stored form: zero is a free slot
                 const unsigned long long nk = nb | (nshift < 0 ? 0ull : (unsigned long long)p << nshift);
-                if (packed) {
-                    atomicMax(&e->best, ((n2b >> a.qbits) << (a.qbits + 1)) | (omask ^ nk));
-                } else {
-                    const unsigned long long q = n2b & qmask;
-                    atomicMax(&e->best, q);
-                    a.cslot[ci] = (unsigned int)cs[u];
-                    a.cN[ci] = nk;
-                    a.cq[ci] = q;
+                const unsigned long long n2b = (unsigned long long)__double_as_longlong(n2);
+                const unsigned long long word =
+                    packed ? (((n2b >> a.qbits) << (a.qbits + 1)) | (omask ^ nk)) : (n2b & qmask);
+                // merge in the LDS first
+                unsigned int ls = (unsigned int)(mix64(key) >> 40) & (unsigned int)(kLds - 1);
+                bool in_lds = false;
+                for (int probe = 0; probe < kLdsProbe; ++probe) {
+                    const unsigned long long prev = atomicCAS(&lkey[ls], 0ull, kk);
+                    if (prev == 0ull || prev == kk) {
+                        in_lds = true;
+                        break;
+                    }
+                    ls = (ls + 1u) & (unsigned int)(kLds - 1);
                 }
-                unsafeAtomicAdd(&e->wr, cwr[u]);
-                unsafeAtomicAdd(&e->wi, cwi[u]);
+                if (in_lds) {
+                    atomicMax(&lbest[ls], word);
+                    unsafeAtomicAdd(&lwr[ls], wr);
+                    unsafeAtomicAdd(&lwi[ls], wi);
+                    if (!packed) { mls[p] = ls; mq[p] = word; mnk[p] = nk; }
+                } else {
+                    // no room in the LDS: straight to the table
+                    const unsigned long long entry = packed ? 0ull : ebase + n_ent - 1u - atomicAdd(ovf, 1u);
+                    unsigned long long sl = home_slot(key, cmask, tm), prev = 0ull;
+                    int probe = 0;
+                    for (; probe < kMaxProbe; ++probe) {
+                        prev = atomicCAS(&a.slot[sl].key, 0ull, kk);
+                        if (prev == 0ull || prev == kk) break;
+                        sl = (sl + 1ull) & tm;
+                    }
+                    if (probe < kMaxProbe) update(sl, word, nk, wr, wi, entry);
+                    else overflow(entry);
+                }
             }
         }
+        __syncthreads();
+
+        // unpacked form: among the LDS children at a slot's largest q, the
+        // smallest other word, kept in the best-word array once its q is
+        // saved; and the entries of the used LDS slots
+        unsigned long long lbal[kLdsRows], savedq[kLdsRows];
+        if (!packed) {
+            bool win[P];
+#pragma unroll
+            for (int p = 0; p < P; ++p) win[p] = mls[p] != ~0u && mq[p] == lbest[mls[p]];
+#pragma unroll
+            for (int r = 0; r < kLdsRows; ++r) {
+                const int ls = r * kSparseThreads + i;
+                savedq[r] = lbest[ls];
+                lbal[r] = __ballot(lkey[ls] != 0ull);
+                if (lane == 0u) loff[r][wave] = (unsigned int)__popcll(lbal[r]);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < kLdsRows; ++r) lbest[r * kSparseThreads + i] = ~0ull;
+            if (i == 0) {
+                unsigned int tot = 0u;
+                for (int r = 0; r < kLdsRows; ++r)
+                    for (int w = 0; w < kSpWaves; ++w) {
+                        const unsigned int c = loff[r][w];
+                        loff[r][w] = tot;
+                        tot += c;
+                    }
+                lused = tot;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int p = 0; p < P; ++p)
+                if (win[p]) atomicMin(&lbest[mls[p]], mnk[p]);
+            __syncthreads();
+        }
+
+        // each used LDS slot is one insertion into the table; the first probes
+        // of a thread's slots are in flight together
+        {
+            unsigned long long fkk[kLdsRows], fsl[kLdsRows], fprev[kLdsRows];
+#pragma unroll
+            for (int r = 0; r < kLdsRows; ++r) {
+                fkk[r] = lkey[r * kSparseThreads + i];
+                fsl[r] = fkk[r] ? home_slot(fkk[r] - 1ull, cmask, tm) : 0ull;
+                fprev[r] = 0ull;
+            }
+#pragma unroll
+            for (int r = 0; r < kLdsRows; ++r)
+                if (fkk[r]) fprev[r] = atomicCAS(&a.slot[fsl[r]].key, 0ull, fkk[r]);
+#pragma unroll
+            for (int r = 0; r < kLdsRows; ++r) {
+                const int ls = r * kSparseThreads + i;
+                if (fkk[r]) {
+                    const unsigned long long entry =
+                        packed ? 0ull : ebase + loff[r][wave] + rank_below(lbal[r]);
+                    for (int probe = 1; fprev[r] != 0ull && fprev[r] != fkk[r] && probe < kMaxProbe; ++probe) {
+                        fsl[r] = (fsl[r] + 1ull) & tm;
+                        fprev[r] = atomicCAS(&a.slot[fsl[r]].key, 0ull, fkk[r]);
+                    }
+                    if (fprev[r] == 0ull || fprev[r] == fkk[r]) {
+                        if (packed) update(fsl[r], lbest[ls], 0ull, lwr[ls], lwi[ls], entry);
+                        else update(fsl[r], savedq[r], lbest[ls], lwr[ls], lwi[ls], entry);
+                    } else {
+                        overflow(entry);
+                    }
+                }
+                lkey[ls] = 0ull;
+                lbest[ls] = 0ull;
+                lwr[ls] = 0.0;
+                lwi[ls] = 0.0;
+            }
+        }
+        if (!packed) {
+            // entries of this pass that no child took
+            const unsigned int lo = lused, hi = n_ent - *ovf;
+            for (unsigned int j = lo + (unsigned int)i; j < hi; j += kSparseThreads) a.cslot[ebase + j] = ~0u;
+        }
+        __syncthreads();   // the LDS table is clear for the next pass
     }
 
     // this workgroup's sums, in a fixed order
@@ -585,7 +736,9 @@ __global__ __launch_bounds__(kSparseThreads) void sparse_reduce(const SparseArgs
 template <int P, int BP, int W, bool F32>
 void launch_sparse(const SparseArgs& a, hipStream_t st, hipEvent_t after_expand) {
     const int g = a.grid;
-    hipLaunchKernelGGL((sparse_expand<P, BP, W, F32>), dim3(g), dim3(kSparseThreads), 0, st, a);
+    constexpr int ppc = kChunkBits / BP;
+    const size_t chunk_bytes = std::max(sparse_chunk_lds<F32>((a.K + ppc - 1) / ppc), kExpandLdsFloor);
+    hipLaunchKernelGGL((sparse_expand<P, BP, W, F32>), dim3(g), dim3(kSparseThreads), chunk_bytes, st, a);
     if (after_expand) (void)hipEventRecord(after_expand, st);
     if (!a.packed) hipLaunchKernelGGL((sparse_resolve<P>), dim3(g), dim3(kSparseThreads), 0, st, a);
     hipLaunchKernelGGL((sparse_compact<BP, W, F32>), dim3(g), dim3(kSparseThreads), 0, st, a);
