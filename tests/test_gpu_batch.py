@@ -201,3 +201,27 @@ def test_batch_of_one_equals_lone_context(Q, monkeypatch):
     g.step(n)
     singles[0].step(n)
     _assert_same(Q, g, singles, n)
+
+
+def test_batch_three_level(Q, monkeypatch):
+    """Three levels (9 pairs, 4-bit points): the seeded random H_S with
+    q = (+1, 0, -1), dk_max 16, lags 0..5 exact, at five bath points (peak
+    frequency and width varied), against lone contexts and the oracle."""
+    wl = W.three_level(K=16, n_exact=6, theta=1e-8)
+    K, n = 16, 30
+    baths = [W.BathSpec(wl.bath.ohmic_alpha, wl.bath.ohmic_wc, ((w0, gam, 0.1),))
+             for w0, gam in [(1.0, 0.05), (0.5, 0.02), (2.0, 0.1), (1.4, 0.05), (0.8, 0.1)]]
+    etas = _etas(Q, wl, baths, K)
+    print(f"[batch] three-level, 5 instances K={K} n={n}", flush=True)
+    g = Q.BatchPropagator(wl.H, wl.q, wl.dt, K, etas, wl.rho0, mask=wl.mask, theta=wl.theta)
+    assert g.info()["n_instances"] == 5
+    singles = _singles_like(Q, monkeypatch, g, wl, etas, K, Q.QUAPI_PRE)
+    g.step(n)
+    for s in singles:
+        s.step(n)
+    _assert_same(Q, g, singles, n)
+    for j in (1, 4):
+        o = oracle.Oracle(wl.H, wl.q, wl.dt, K, etas[j], wl.rho0, mask=wl.mask, theta=wl.theta, mode=oracle.PRE)
+        o.step(n)
+        assert sum(o.stats(t)["n_amb_rep"] + o.stats(t)["n_amb_theta"] for t in range(1, n + 1)) == 0
+        assert np.abs(g.rho_history(j, 0, n + 1) - o.rho_history()).max() < RHO_TOL
