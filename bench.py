@@ -181,6 +181,8 @@ def main():
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="structured-bath")
     ap.add_argument("--chunk-run", type=int, default=0,
                     help="batched form: chunk run length (0: the library's tuner picks it)")
+    ap.add_argument("--graph", action="store_true",
+                    help="each propagation as one HIP graph (quapi_step_graph), recorded in the warm-up")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64",
                     help="fp32: the FP32 log-domain form (hash-table merge)")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -189,6 +191,8 @@ def main():
                     help="write the step kernel's HBM traffic per launch from the counter files of "
                          "two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of bench.py --copy-mib; no GPU")
     args = ap.parse_args()
+    if args.graph and args.warmup < 1:
+        args.warmup = 1                      # the graph is recorded outside the timed region
     spec = workload_spec(args.workload, args.precision)
     if args.cpu_steps < 0:
         args.cpu_steps = spec["cpu_steps"]
@@ -242,7 +246,10 @@ def main():
 
     def run_once():
         prop.reset()
-        quapi.quapi_step(prop.ctx, n_t)
+        if args.graph:
+            quapi.quapi_step_graph(prop.ctx, n_t)
+        else:
+            quapi.quapi_step(prop.ctx, n_t)
         # rho(t) of every instance: [t][instance][M][M]
         return quapi.quapi_batch_rho_all(prop.ctx, 0, n_t + 1, n_inst, wl.M)
 
@@ -287,6 +294,7 @@ def main():
             "beta": wl.beta, "dt": wl.dt, "eps": 0.5, "Delta": 1.0,
             "precision": args.precision, "merge": "hash table" if info["hash_merge"] else "bucketed store",
             "record_bytes": record_bytes, "instances": n_inst, "chunk_run": chunk_run,
+            "hip_graph": bool(args.graph),
         },
         "time_per_rho_us": 1e3 * ms_per_step / n_t,
         "path_steps_per_propagation": children,

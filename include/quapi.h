@@ -154,6 +154,18 @@ int quapi_create_batch(const quapi_params* p, int n_inst, const quapi_c64* eta_b
  * the next synchronising call; the context then stays at the last complete step. */
 int quapi_step(quapi_ctx* c, int n_steps);
 
+/* Enqueue n_steps >= 1 time steps, in the step order of Sec. 3.2.1 (merge,
+ * extend, filter, rho(t)), as one HIP graph: the launches quapi_step makes,
+ * recorded once after a kernel that clears the look-back words, then replayed
+ * by later calls that start at the same step with the same buffers (after
+ * quapi_reset, for instance).  A call that does not match the recorded run
+ * records anew.  Results equal quapi_step's bit for bit.  Launch timing
+ * (quapi_profile_*) skips graph steps.  Bucketed store only (lone or batched).
+ * Errors: EINVAL (n_steps < 1), ESTATE (a previous step failed), ENOMEM
+ * (history growth), EUNSUPPORTED (the hash-table merge), EDEVICE (capture,
+ * instantiation or launch failed). */
+int quapi_step_graph(quapi_ctx* c, int n_steps);
+
 /* Wait for the enqueued steps; returns the first error a step reported. */
 int quapi_sync(quapi_ctx* c);
 

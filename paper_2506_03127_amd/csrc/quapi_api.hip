@@ -91,6 +91,14 @@ struct quapi_ctx {
     int err = QUAPI_OK;          // sticky error of a failed step
     size_t device_bytes = 0;
     std::vector<void*> allocations;
+    // quapi_step_graph: the last recorded run of steps, replayed while it starts
+    // at the context's step and parity with the buffers it recorded
+    hipGraphExec_t graph = nullptr;
+    int graph_t0 = -1, graph_n = 0, graph_cur0 = 0, graph_run = 0;
+    double2* graph_rho = nullptr;
+    StepStatsDev* graph_stats = nullptr;
+    unsigned int graph_epoch_end = 0;
+    bool capturing = false;
     // launch timing: three events per recorded step
     bool prof_on = false;
     int prof_cap = 0, prof_n = 0;
@@ -334,7 +342,8 @@ int step_sparse(quapi_ctx* c, int n_steps) {
         a.wf_out = c->sp_wf[1 - c->cur];
         a.t = t;
         a.coef = c->d_coef + (size_t)(std::min(t, c->K + 1) - 1) * 4 * n;
-        hipEvent_t* ev = (c->prof_on && c->prof_n < c->prof_cap) ? &c->prof_ev[3 * (size_t)c->prof_n++] : nullptr;
+        hipEvent_t* ev = (c->prof_on && !c->capturing && c->prof_n < c->prof_cap)
+                             ? &c->prof_ev[3 * (size_t)c->prof_n++] : nullptr;
         if (ev && hipEventRecord(ev[0], c->stream) != hipSuccess) ev = nullptr;
         // profiled: ev[0]..ev[1] brackets expand, ev[1]..ev[2] the rest of the step
         if (quapi_dev::launch_sparse_step(a, c->stream, ev ? (void*)ev[1] : nullptr) != (int)hipSuccess) {
@@ -747,7 +756,8 @@ int quapi_step(quapi_ctx* c, int n_steps) {
             c->err = QUAPI_EDEVICE;
             return c->err;
         }
-        hipEvent_t* ev = (c->prof_on && c->prof_n < c->prof_cap) ? &c->prof_ev[3 * (size_t)c->prof_n++] : nullptr;
+        hipEvent_t* ev = (c->prof_on && !c->capturing && c->prof_n < c->prof_cap)
+                             ? &c->prof_ev[3 * (size_t)c->prof_n++] : nullptr;
         if (ev && hipEventRecord(ev[0], c->stream) != hipSuccess) ev = nullptr;
         if (quapi_dev::launch_step(a, c->grid, c->stream) != (int)hipSuccess) {
             c->err = QUAPI_EDEVICE;
@@ -763,6 +773,65 @@ int quapi_step(quapi_ctx* c, int n_steps) {
         }
         if (ev) (void)hipEventRecord(ev[2], c->stream);
     }
+    return QUAPI_OK;
+}
+
+int quapi_step_graph(quapi_ctx* c, int n_steps) {
+    if (!c || n_steps < 1) return QUAPI_EINVAL;
+    if (c->err) return QUAPI_ESTATE;
+    if (c->sparse) return QUAPI_EUNSUPPORTED;
+    int rc = grow_history(c, c->t + n_steps);      // allocations stay outside the capture
+    if (rc) return rc;
+    const bool hit = c->graph && c->graph_t0 == c->t && c->graph_n == n_steps && c->graph_cur0 == c->cur &&
+                     c->graph_run == c->chunk_run && c->graph_rho == c->d_rho && c->graph_stats == c->d_stats;
+    if (!hit) {
+        if (c->graph) {
+            (void)hipGraphExecDestroy(c->graph);
+            c->graph = nullptr;
+        }
+        const int t0 = c->t, cur0 = c->cur;
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_to_code(e);
+        // look-back words of an earlier replay carry the same epochs: clear them first
+        int lr = quapi_dev::launch_clear_words(c->d_chain, (size_t)c->P * c->max_chunks, c->stream);
+        c->capturing = true;
+        rc = lr == (int)hipSuccess ? quapi_step(c, n_steps) : QUAPI_EDEVICE;
+        c->capturing = false;
+        e = hipStreamEndCapture(c->stream, &g);
+        // nothing recorded has run: back to the state before the capture
+        c->t = t0;
+        c->cur = cur0;
+        if (rc == QUAPI_EDEVICE) c->err = QUAPI_OK;
+        if (rc != QUAPI_OK || e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            (void)hipGetLastError();
+            return rc != QUAPI_OK ? rc : hip_to_code(e);
+        }
+        e = hipGraphInstantiateWithFlags(&c->graph, g, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            c->graph = nullptr;
+            (void)hipGetLastError();
+            return hip_to_code(e);
+        }
+        c->graph_t0 = t0;
+        c->graph_n = n_steps;
+        c->graph_cur0 = cur0;
+        c->graph_run = c->chunk_run;
+        c->graph_rho = c->d_rho;
+        c->graph_stats = c->d_stats;
+        c->graph_epoch_end = c->epoch;
+    }
+    const hipError_t e = hipGraphLaunch(c->graph, c->stream);
+    if (e != hipSuccess) {
+        c->err = QUAPI_EDEVICE;
+        return c->err;
+    }
+    c->t += n_steps;
+    if (n_steps & 1) c->cur = 1 - c->cur;
+    // later eager steps take epochs above every recorded one
+    if (c->epoch < c->graph_epoch_end) c->epoch = c->graph_epoch_end;
     return QUAPI_OK;
 }
 
@@ -1022,6 +1091,7 @@ int quapi_profile_end(quapi_ctx* c, int cap, double* step_ms, double* plan_ms, i
 void quapi_destroy(quapi_ctx* c) {
     if (!c) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
+    if (c->graph) (void)hipGraphExecDestroy(c->graph);
     for (hipEvent_t e : c->prof_ev) (void)hipEventDestroy(e);
     c->prof_ev.clear();
     for (void* p : c->allocations) (void)hipFree(p);

@@ -79,6 +79,7 @@ def lib() -> ctypes.CDLL:
         vp, ci, cd, cll = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_longlong
         L.quapi_create.argtypes = [ctypes.POINTER(quapi_params), ctypes.POINTER(vp)]
         L.quapi_step.argtypes = [vp, ci]
+        L.quapi_step_graph.argtypes = [vp, ci]
         L.quapi_sync.argtypes = [vp]
         L.quapi_time.argtypes = [vp, ctypes.POINTER(ci)]
         L.quapi_rho.argtypes = [vp, ci, vp]
@@ -197,6 +198,10 @@ def quapi_create_batch(H, q, dt, dk_max, etas, rho0, mask=None, theta=0.0, mode=
 
 def quapi_step(ctx, n_steps: int):
     _check(lib().quapi_step(ctx, int(n_steps)), "quapi_step")
+
+
+def quapi_step_graph(ctx, n_steps: int):
+    _check(lib().quapi_step_graph(ctx, int(n_steps)), "quapi_step_graph")
 
 
 def quapi_sync(ctx):
@@ -343,6 +348,11 @@ class Propagator:
     def step(self, n=1):
         quapi_step(self.ctx, n)
 
+    def step_graph(self, n):
+        """n steps as one HIP graph, replayed when a later call starts at the
+        same step (see quapi_step_graph)."""
+        quapi_step_graph(self.ctx, n)
+
     def sync(self):
         quapi_sync(self.ctx)
 
@@ -395,6 +405,11 @@ class BatchPropagator:
 
     def step(self, n=1):
         quapi_step(self.ctx, n)
+
+    def step_graph(self, n):
+        """n steps as one HIP graph, replayed when a later call starts at the
+        same step (see quapi_step_graph)."""
+        quapi_step_graph(self.ctx, n)
 
     def sync(self):
         quapi_sync(self.ctx)
