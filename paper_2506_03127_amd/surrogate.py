@@ -61,7 +61,7 @@ class Solver:
     batch: int = 64
     threads: int = 8                         # eta quadratures in parallel (host)
 
-    def solve(self, pts: np.ndarray) -> np.ndarray:
+    def solve(self, pts: np.ndarray, progress: bool = False) -> np.ndarray:
         """rho(t), t = 0..n_steps, of every point: [n_points][n_steps + 1][2][2],
         by the batched propagation, `batch` points per launch."""
         from concurrent.futures import ThreadPoolExecutor
@@ -83,6 +83,8 @@ class Solver:
             prop.step(self.n_steps)
             out[s:s + len(chunk)] = np.transpose(prop.rho_all(0, self.n_steps + 1), (1, 0, 2, 3))
             prop.close()
+            if progress:
+                print(f"[solver] points {s + len(chunk)} of {len(pts)}", flush=True)
         return out
 
 
@@ -124,6 +126,7 @@ class Surrogate:
     history: Dict[str, list] = field(default_factory=dict)
     stream: object = None                    # torch stream of the network and of its batches
     residual: bool = True                    # learn rho(t) minus the system's own evolution
+    time_features: bool = True               # add cos/sin of Omega t and w0 t to the inputs
 
     def _stream(self):
         """One torch stream for the network and the tensor work around it (torch's
@@ -135,14 +138,31 @@ class Surrogate:
         return self.stream
 
     # ---- features
+    @property
+    def n_features(self) -> int:
+        return 10 if self.time_features else 6
+
     def _features(self, pts: np.ndarray, n_t: int) -> np.ndarray:
-        """[n_points][n_t][6] in [-1, 1]: the parameters and the time."""
+        """[n_points][n_t][n_features] in [-1, 1]: the parameters and the time,
+        then (time_features) cos and sin of Omega t and of w0 t, Omega =
+        sqrt(eps^2 + Delta^2) the splitting of H_S and w0 the bath peak: over
+        hundreds of steps rho(t) oscillates many times, which a network with
+        the time as one input learns poorly.  They are fixed functions of the
+        same six inputs."""
         lo, hi = self.box.lo_hi()
         p = 2.0 * (pts - lo) / (hi - lo) - 1.0
         tt = 2.0 * np.arange(n_t) / max(self.solver.n_steps, 1) - 1.0
-        f = np.empty((len(pts), n_t, 6), dtype=np.float32)
+        f = np.empty((len(pts), n_t, self.n_features), dtype=np.float32)
         f[:, :, :5] = p[:, None, :]
         f[:, :, 5] = tt[None, :]
+        if self.time_features:
+            t = workloads.structured_bath().dt * np.arange(n_t)
+            om = np.sqrt(np.asarray(pts)[:, 4] ** 2 + 1.0)
+            w0 = np.asarray(pts)[:, 0]
+            f[:, :, 6] = np.cos(om[:, None] * t[None, :])
+            f[:, :, 7] = np.sin(om[:, None] * t[None, :])
+            f[:, :, 8] = np.cos(w0[:, None] * t[None, :])
+            f[:, :, 9] = np.sin(w0[:, None] * t[None, :])
         return f
 
     def _baseline(self, pts: np.ndarray, n_t: int) -> np.ndarray:
@@ -168,12 +188,13 @@ class Surrogate:
         n_t = train_rho.shape[1]
         target = train_rho - self._baseline(train_pts, n_t)
         with torch.cuda.stream(st):
-            x = torch.as_tensor(self._features(train_pts, n_t).reshape(-1, 6), device="cuda")
+            x = torch.as_tensor(self._features(train_pts, n_t).reshape(-1, self.n_features), device="cuda")
             y = torch.as_tensor(rho_components(target).reshape(-1, 4).astype(np.float32), device="cuda")
             n = x.shape[0]
             batch = min(batch, n)
             if self.net is None:
-                self.net = quapi.MLP(6, self.width, self.depth, 4, max_batch=max(batch, 65536), seed=self.seed,
+                self.net = quapi.MLP(self.n_features, self.width, self.depth, 4, max_batch=max(batch, 65536),
+                                     seed=self.seed,
                                      stream=st.cuda_stream)
             g = torch.Generator(device="cuda")
             g.manual_seed(self.seed)
@@ -193,7 +214,7 @@ class Surrogate:
         """The network's rho(t), t = 0..n_t-1, of every point: [n][n_t][2][2]."""
         import torch
         n_t = self.solver.n_steps + 1 if n_t is None else n_t
-        f = self._features(pts, n_t).reshape(-1, 6)
+        f = self._features(pts, n_t).reshape(-1, self.n_features)
         out = np.empty((f.shape[0], 4), dtype=np.float32)
         step = self.net.max_batch
         with torch.cuda.stream(self._stream()):
@@ -243,3 +264,63 @@ class Surrogate:
         if (~use).any():
             out[~use] = self.solver.solve(pts[~use])
         return out, use
+
+
+def main(argv=None):
+    """Train and validate at a given scale; one JSON line of results.
+
+        python -m paper_2506_03127_amd.surrogate --points 4096 --steps 500   (needs the GPU)
+    """
+    import argparse
+    import json
+    import time
+
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--points", type=int, default=4096, help="training points")
+    ap.add_argument("--held-out", type=int, default=512, help="validation points")
+    ap.add_argument("--steps", type=int, default=500, help="time steps per trajectory")
+    ap.add_argument("--train-steps", type=int, default=6000)
+    ap.add_argument("--batch", type=int, default=8192)
+    ap.add_argument("--tol", type=float, default=1e-3)
+    ap.add_argument("--seed", type=int, default=1)
+    args = ap.parse_args(argv)
+
+    import torch
+    # torch's device first, before the library's first HIP call (the network
+    # and its batches run on a torch stream)
+    if not torch.cuda.is_available():
+        raise SystemExit("the surrogate needs a GPU")
+    sur = Surrogate(solver=Solver(n_steps=args.steps), tol=args.tol)
+    sur._stream()
+    pts = sur.box.sample(args.points + args.held_out, seed=args.seed)
+    t0 = time.perf_counter()
+    rho = sur.solver.solve(pts, progress=True)
+    t_solve = time.perf_counter() - t0
+    train, held = slice(0, args.points), slice(args.points, None)
+    t0 = time.perf_counter()
+    sur.fit(pts[train], rho[train], steps=args.train_steps, batch=args.batch,
+            log_every=max(args.train_steps // 10, 1))
+    t_fit = time.perf_counter() - t0
+    print(f"[surrogate] loss {sur.history['loss'][0][1]:.3e} -> {sur.history['loss'][-1][1]:.3e}", flush=True)
+    err = sur.validate(pts[held], rho[held])
+    q = pts[held][:64]
+    t0 = time.perf_counter()
+    sur.predict(q)
+    t_net = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    sur.solver.solve(q)
+    t_method = time.perf_counter() - t0
+    out = {
+        "points": args.points, "held_out": args.held_out, "time_steps": args.steps,
+        "train_steps": args.train_steps, "batch": args.batch,
+        "solve_s": t_solve, "fit_s": t_fit, "loss_final": sur.history["loss"][-1][1],
+        "held_out_error_median": float(np.median(err)), "held_out_error_p90": float(np.percentile(err, 90)),
+        "held_out_error_max": float(err.max()), "tol": args.tol,
+        "cells_accepted": int(sur.accepted.sum()), "cells": int(sur.accepted.size),
+        "query_64_points_network_ms": 1e3 * t_net, "query_64_points_method_ms": 1e3 * t_method,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
