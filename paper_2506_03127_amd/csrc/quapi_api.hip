@@ -365,6 +365,23 @@ long long ipow(long long b, int e) {
 
 }  // namespace
 
+namespace {
+
+// zero n 64-bit words: a kernel, so that a HIP graph records it as a kernel node
+__global__ __launch_bounds__(256) void clear_words(unsigned long long* p, size_t n) {
+    for (size_t k = (size_t)blockIdx.x * 256u + threadIdx.x; k < n; k += (size_t)gridDim.x * 256u) p[k] = 0ull;
+}
+
+hipError_t launch_clear_words(unsigned long long* p, size_t n, hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    const size_t blocks = (n + 255u) / 256u;
+    const unsigned int g = (unsigned int)(blocks < 1024u ? blocks : 1024u);
+    hipLaunchKernelGGL(clear_words, dim3(g), dim3(256), 0, stream, p, n);
+    return hipGetLastError();
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* quapi_strerror(int code) {
@@ -794,9 +811,9 @@ int quapi_step_graph(quapi_ctx* c, int n_steps) {
         hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hip_to_code(e);
         // look-back words of an earlier replay carry the same epochs: clear them first
-        int lr = quapi_dev::launch_clear_words(c->d_chain, (size_t)c->P * c->max_chunks, c->stream);
+        const hipError_t lr = launch_clear_words(c->d_chain, (size_t)c->P * c->max_chunks, c->stream);
         c->capturing = true;
-        rc = lr == (int)hipSuccess ? quapi_step(c, n_steps) : QUAPI_EDEVICE;
+        rc = lr == hipSuccess ? quapi_step(c, n_steps) : QUAPI_EDEVICE;
         c->capturing = false;
         e = hipStreamEndCapture(c->stream, &g);
         // nothing recorded has run: back to the state before the capture

@@ -126,8 +126,6 @@ size_t instance_table_doubles();                         // per instance, of ins
 int launch_instance_tables(const StepArgs& a, double* out, void* stream);   // one workgroup per instance
 int chunk_heads(int P);
 int plan_max_buckets();              // bucket count the planner is built for
-// zero n 64-bit words on the stream with a kernel (recordable into a HIP graph)
-int launch_clear_words(unsigned long long* p, size_t n, void* stream);
 int step_grid(int P, int n_cu, int per_cu, bool batch);   // persistent workgroups that are co-resident
 
 }  // namespace quapi_dev

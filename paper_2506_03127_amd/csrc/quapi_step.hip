@@ -1069,19 +1069,6 @@ int step_grid(int P, int n_cu, int per_cu, bool batch) {
     return (per_cu > 0 ? (per_cu < nb ? per_cu : nb) : nb) * n_cu;
 }
 
-// zero n 64-bit words (a kernel, so that it may be recorded into a graph)
-__global__ __launch_bounds__(256) void clear_words(unsigned long long* p, size_t n) {
-    for (size_t k = (size_t)blockIdx.x * 256u + threadIdx.x; k < n; k += (size_t)gridDim.x * 256u) p[k] = 0ull;
-}
-
-int launch_clear_words(unsigned long long* p, size_t n, void* stream) {
-    if (n == 0) return (int)hipSuccess;
-    const size_t blocks = (n + 255u) / 256u;
-    const unsigned int g = (unsigned int)(blocks < 1024u ? blocks : 1024u);
-    hipLaunchKernelGGL(clear_words, dim3(g), dim3(256), 0, (hipStream_t)stream, p, n);
-    return (int)hipGetLastError();
-}
-
 int launch_step(const StepArgs& a, int grid, void* stream) {
 
     hipStream_t st = (hipStream_t)stream;
