@@ -64,7 +64,11 @@ __device__ inline unsigned long long mix64(unsigned long long z) {
 // signature that its key holds, so groups whose children merge at the next
 // step share a window, and compact, which scans in slot order, stores them
 // side by side: the next expand then meets them in one workgroup pass.
-constexpr int kWinBits = 9;
+// Smaller windows crowd the keys of a pass into long probe chains, larger ones
+// split partners over passes (long memory, K = 40, expand per step: 27.6 ms
+// at 128 slots, 5.4 at 512, 3.4 at 1024, 3.5 at 2048, 4.2 at 4096, 4.8 at
+// 8192, 5.5 with keys hashed whole).
+constexpr int kWinBits = 10;
 
 __device__ inline unsigned long long home_slot(unsigned long long key, unsigned long long cmask,
                                                unsigned long long tm) {
