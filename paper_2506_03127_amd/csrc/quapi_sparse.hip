@@ -129,12 +129,13 @@ __device__ inline Hist<W> load_hist(const uint64_t* p, unsigned long long g) {
 constexpr int kChunkBits = 4;
 constexpr int kChunkVals = 1 << kChunkBits;
 constexpr int kLdsRows = 4;                               // LDS merge slots per thread
-constexpr int kLds = kLdsRows * kSparseThreads;           // a pass's children at P = 4
+constexpr int kLds = kLdsRows * kSparseThreads;           // a pass's children at P = 4 (a share at P = 9)
 constexpr int kLdsProbe = 32;
 // dynamic LDS of the expand kernel at least this, which with its static LDS
 // leaves room for two workgroups per CU: with more in flight the memory-side
-// atomics contend (long memory, K = 40: 5.4 ms per expand at two per CU,
-// 6.1 ms at three, 7.1 ms at one)
+// atomics contend (long memory, K = 40, expand per step: 3.5 ms at two per
+// CU against 3.8 ms at three with 2048-slot windows; 5.4, 6.1 and 7.1 ms at
+// two, three and one with 512-slot windows)
 constexpr size_t kExpandLdsFloor = 24 * 1024;
 
 template <int W>
