@@ -344,6 +344,38 @@ def test_structured_bath_full_run(Q, eta_cache):
     assert tr.real.max() < 1.0 + 1e-12 and tr.real[-1] > 0.9
 
 
+def test_long_memory_full_run(Q, eta_cache):
+    """The long-memory workload (dk_max 40, lags 0..11, 16, 24 and 32 exact,
+    theta 1e-9: 80-bit histories on the hash-table merge, ~1.6e7 groups) for
+    1000 steps at the full size, launched as the benchmark launches it: the
+    first 12 steps against the oracle element by element, the counters of
+    every step against the bookkeeping of the method."""
+    wl = W.long_memory()
+    eta = eta_cache(wl)
+    g = Q.Propagator(wl.H, wl.q, wl.dt, wl.K, eta, wl.rho0, mask=wl.mask, theta=wl.theta,
+                     max_steps=wl.n_steps, max_groups=48 << 20)
+    assert Q.quapi_info(g.ctx)["hash_merge"] == 1
+    print(f"[parity] long memory, {wl.n_steps} steps", flush=True)
+    g.step(wl.n_steps)
+    g.sync()
+    assert g.t == wl.n_steps
+    r = g.rho_history()
+    st = g.stats(1, wl.n_steps)
+    n0 = 12
+    o = oracle.Oracle(wl.H, wl.q, wl.dt, wl.K, eta, wl.rho0, mask=wl.mask, theta=wl.theta, mode=oracle.PRE)
+    o.step(n0)
+    assert ambiguous(o, n0) == 0
+    assert np.abs(r[:n0 + 1] - o.rho_history()).max() < RHO_TOL
+    for k, s in enumerate(st):
+        assert s["n_children"] == 4 * s["n_groups"]
+        assert s["n_stored"] <= s["n_survivors"] <= s["n_children"]
+        if k + 1 < len(st):
+            assert st[k + 1]["n_groups"] == s["n_stored"]
+    assert max(s["n_groups"] for s in st) > 10_000_000
+    tr = np.trace(r, axis1=1, axis2=2)
+    assert np.isfinite(r).all() and abs(tr[-1] - 1.0) < 1e-2
+
+
 def test_launch_timing_record(Q, eta_cache):
     """The launch-timing entry points record one positive duration per step kernel and
     planner launch, and recording ends at the requested count."""
