@@ -94,7 +94,10 @@ typedef struct {
                               /* (at least one each; an uneven fill reports ENOMEM first); 0: room   */
                               /* for every key of the merge positions (hash-table merge: up to 2^21) */
     int max_steps;            /* initial capacity of the rho(t) history; grows on demand; <= 0: 1024    */
-    void* stream;             /* hipStream_t to run on (e.g. a torch stream); NULL: a library stream   */
+    void* stream;             /* hipStream_t to run on (e.g. a torch stream); NULL: the library's      */
+                              /* stream of the device, shared by every context that passes NULL.  A     */
+                              /* step kernel needs the whole GPU resident: contexts on streams of their */
+                              /* own must not step side by side (the look-back then reports EDEVICE)    */
     int precision;            /* QUAPI_FP64 (0) or QUAPI_FP32_LOG                                       */
 } quapi_params;
 

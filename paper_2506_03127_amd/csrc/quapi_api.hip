@@ -8,6 +8,8 @@
 #include <complex>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -65,7 +67,8 @@ struct quapi_ctx {
     int chunk_run = 1;                       // consecutive chunks a step-kernel workgroup takes in turn
 
     hipStream_t stream = nullptr;
-    bool own_stream = false;
+    bool own_stream = false;                 // the device's shared library stream, released at destroy
+    int stream_dev = 0;
     GroupBuf buf[2] = {};
     unsigned int* counts[2] = {nullptr, nullptr};
     double* d_tables = nullptr;
@@ -367,6 +370,42 @@ long long ipow(long long b, int e) {
 
 namespace {
 
+// Contexts that pass no stream share one per device.  The step kernel's grid is
+// co-resident: its chunks wait on earlier chunks of the same launch, so two step
+// kernels side by side, neither with the whole GPU, can wait on each other until
+// the look-back's spin limit reports a fault.  One stream orders them.
+std::mutex g_stream_mu;
+struct SharedStream {
+    hipStream_t s = nullptr;
+    int refs = 0;
+};
+std::map<int, SharedStream> g_streams;
+
+hipError_t acquire_shared_stream(int dev, hipStream_t* out) {
+    std::lock_guard<std::mutex> lk(g_stream_mu);
+    SharedStream& e = g_streams[dev];
+    if (!e.s) {
+        const hipError_t r = hipStreamCreateWithFlags(&e.s, hipStreamNonBlocking);
+        if (r != hipSuccess) {
+            e.s = nullptr;
+            return r;
+        }
+    }
+    ++e.refs;
+    *out = e.s;
+    return hipSuccess;
+}
+
+void release_shared_stream(int dev) {
+    std::lock_guard<std::mutex> lk(g_stream_mu);
+    auto it = g_streams.find(dev);
+    if (it == g_streams.end()) return;
+    if (--it->second.refs == 0) {
+        (void)hipStreamDestroy(it->second.s);
+        g_streams.erase(it);
+    }
+}
+
 // zero n 64-bit words: a kernel, so that a HIP graph records it as a kernel node
 __global__ __launch_bounds__(256) void clear_words(unsigned long long* p, size_t n) {
     for (size_t k = (size_t)blockIdx.x * 256u + threadIdx.x; k < n; k += (size_t)gridDim.x * 256u) p[k] = 0ull;
@@ -608,11 +647,13 @@ static int create_ctx(const quapi_params* p, int n_inst, const quapi_c64* eta_al
     if (p->stream) {
         c->stream = (hipStream_t)p->stream;
     } else {
-        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess || acquire_shared_stream(dev, &c->stream) != hipSuccess) {
             delete c;
             return QUAPI_EDEVICE;
         }
         c->own_stream = true;
+        c->stream_dev = dev;
     }
 
     const size_t nrec = c->sparse ? 1 : (size_t)c->n_buckets * (size_t)cap;
@@ -1113,7 +1154,7 @@ void quapi_destroy(quapi_ctx* c) {
     c->prof_ev.clear();
     for (void* p : c->allocations) (void)hipFree(p);
     c->allocations.clear();
-    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    if (c->own_stream && c->stream) release_shared_stream(c->stream_dev);
     delete c;
 }
 
