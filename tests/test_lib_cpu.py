@@ -138,3 +138,14 @@ def test_mlp_create_rejects_invalid_sizes_without_device(Q):
 def test_strerror_names_every_code(Q):
     names = {Q.strerror(c) for c in (0, -1, -2, -3, -4, -5)}
     assert len(names) == 6 and "unknown error" not in names
+
+
+def test_calls_on_no_context_are_rejected_without_device(Q):
+    """Every stepping and reading call checks its context before any device
+    work: a null context is EINVAL."""
+    L = Q.lib()
+    assert L.quapi_step(None, 1) == Q.QUAPI_EINVAL
+    assert L.quapi_step_graph(None, 1) == Q.QUAPI_EINVAL
+    assert L.quapi_sync(None) == Q.QUAPI_EINVAL
+    assert L.quapi_reset(None) == Q.QUAPI_EINVAL
+    assert L.quapi_set_chunk_run(None, 1) == Q.QUAPI_EINVAL
