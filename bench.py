@@ -61,6 +61,10 @@ WORKLOADS = {
         "kernel": "step_kernel", "kernel_label": "step_kernel<4,2,batched>",
         "sources": [CSRC + "quapi_step.hip", CSRC + "quapi_device.h", CSRC + "quapi_host.h"],
         "traffic": "step_kernel_batched_scan_traffic.json", "cpu_steps": 22, "max_groups": 0},
+    "three-level": {
+        "kernel": "step_kernel", "kernel_label": "step_kernel<9,4>",
+        "sources": [CSRC + "quapi_step.hip", CSRC + "quapi_device.h", CSRC + "quapi_host.h"],
+        "traffic": "step_kernel_three_level_traffic.json", "cpu_steps": 100, "max_groups": 0},
     "long-memory": {
         "kernel": "sparse_expand", "kernel_label": "sparse_expand<4,2,2>",
         "sources": [CSRC + "quapi_sparse.hip", CSRC + "quapi_sparse.h", CSRC + "quapi_device.h",
@@ -225,7 +229,12 @@ def main():
         prop = quapi.BatchPropagator(wl.H, wl.q, wl.dt, wl.K, etas, wl.rho0, mask=wl.mask, theta=wl.theta,
                                      mode=quapi.QUAPI_PRE, max_steps=wl.n_steps, stream=stream.cuda_stream)
     else:
-        wl = workloads.structured_bath() if args.workload == "structured-bath" else workloads.long_memory()
+        if args.workload == "structured-bath":
+            wl = workloads.structured_bath()
+        elif args.workload == "three-level":
+            wl = workloads.three_level(K=16, n_exact=6, theta=1e-8, n_steps=200)
+        else:
+            wl = workloads.long_memory()
         prop = quapi.Propagator(wl.H, wl.q, wl.dt, wl.K, eta_of(wl.bath, wl.K), wl.rho0, mask=wl.mask,
                                 theta=wl.theta, mode=quapi.QUAPI_PRE, max_steps=wl.n_steps,
                                 stream=stream.cuda_stream, max_groups=spec["max_groups"], precision=precision)
@@ -234,6 +243,11 @@ def main():
     record_bytes = info["record_bytes"]
     n_inst = info["n_instances"]
     n_t = wl.n_steps
+
+    if wl.M == 2:
+        system = {"eps": 0.5, "Delta": 1.0}
+    else:
+        system = {"H_S": "seeded random Hermitian, entries ~ N(0, 0.5), seed 7", "q": [float(x) for x in wl.q]}
 
     chunk_run = 1
     if n_inst > 1:
@@ -291,7 +305,7 @@ def main():
             "theta": wl.theta, "time_steps": n_t, "mode": "pre-merging",
             "bath": {"ohmic_alpha": b.ohmic_alpha, "ohmic_wc": b.ohmic_wc,
                      "peaks_w0_gamma_lambda": [list(p) for p in b.peaks]},
-            "beta": wl.beta, "dt": wl.dt, "eps": 0.5, "Delta": 1.0,
+            "beta": wl.beta, "dt": wl.dt, **system,
             "precision": args.precision, "merge": "hash table" if info["hash_merge"] else "bucketed store",
             "record_bytes": record_bytes, "instances": n_inst, "chunk_run": chunk_run,
             "hip_graph": bool(args.graph),
