@@ -78,6 +78,8 @@ def lib():
         L.oracle_destroy.argtypes = [vp]
         L.oracle_propagator.argtypes = [ci, vp, cd, vp]
         L.oracle_merge_demo.argtypes = [vp, vp, ci, ci, vp, ci, ci, vp, vp]
+        L.oracle_could_flip.argtypes = [vp, vp, ci, cd]
+        L.oracle_flag_demo.argtypes = [vp, vp, ci, ci, vp, ci, ci, cd, vp, vp]
         _lib = L
     return _lib
 
@@ -188,3 +190,24 @@ def merge_demo(hist, w, positions, qbits=DEFAULT_QBITS):
     ng = lib().oracle_merge_demo(hist.ctypes.data, w.ctypes.data, n, L, pos.ctypes.data,
                                  len(pos), int(qbits), rep.ctypes.data, sums.ctypes.data)
     return rep[:ng], sums[:ng]
+
+
+def could_flip(winner, other, qbits=DEFAULT_QBITS, eps=DEFAULT_AMB_EPS) -> bool:
+    """Whether a relative perturbation eps of |winner|^2 and |other|^2 could
+    change the representative choice between them (the oracle's decision log)."""
+    a = np.array([complex(winner).real, complex(winner).imag])
+    b = np.array([complex(other).real, complex(other).imag])
+    return bool(lib().oracle_could_flip(a.ctypes.data, b.ctypes.data, int(qbits), float(eps)))
+
+
+def flag_demo(hist, w, positions, qbits=DEFAULT_QBITS, eps=DEFAULT_AMB_EPS):
+    """Merge explicit paths on `positions`; returns (rep index, ambiguous flag) per group."""
+    hist = np.ascontiguousarray(np.asarray(hist, dtype=np.uint8))
+    w = _c128(w)
+    n, L = hist.shape
+    pos = np.ascontiguousarray(np.asarray(positions, dtype=np.int32))
+    rep = np.zeros(n, dtype=np.int32)
+    amb = np.zeros(n, dtype=np.int32)
+    ng = lib().oracle_flag_demo(hist.ctypes.data, w.ctypes.data, n, L, pos.ctypes.data, len(pos),
+                                int(qbits), float(eps), rep.ctypes.data, amb.ctypes.data)
+    return rep[:ng], amb[:ng].astype(bool)

@@ -489,3 +489,39 @@ int oracle_merge_demo(const unsigned char* hist, const double* w, int n, int L,
 }
 
 }  // extern "C"
+
+extern "C" {
+
+// Test hooks of the decision log (Sec. 3.1.2 representative choice, with the
+// quantised comparison and tie rule of the header).  could_flip for two
+// amplitudes given as (re, im) pairs; returns 1 when a relative perturbation
+// eps of the two |w|^2 could change which one wins.
+int oracle_could_flip(const double* winner, const double* other, int qbits, double eps) {
+    return could_flip(cplx(winner[0], winner[1]), cplx(other[0], other[1]), qbits, eps) ? 1 : 0;
+}
+
+// Merge explicit paths on the given positions and flag the groups whose
+// representative choice a perturbation eps could flip.  Writes, per group in
+// order of first appearance, the representative's index and the flag (0/1);
+// returns the number of groups.
+int oracle_flag_demo(const unsigned char* hist, const double* w, int n, int L, const int* positions,
+                     int n_pos, int qbits, double eps, int* rep_index, int* amb) {
+    std::vector<Path> paths(n);
+    for (int i = 0; i < n; ++i) {
+        paths[i].h.assign((const char*)hist + (size_t)i * L, L);
+        paths[i].w = cplx(w[2 * i], w[2 * i + 1]);
+    }
+    std::vector<int> pos(positions, positions + n_pos);
+    std::vector<Group> groups = merge_on(paths, pos, qbits);
+    flag_ambiguous(groups, paths, pos, qbits, eps);
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+        int idx = -1;
+        for (int i = 0; i < n; ++i)
+            if (paths[i].h == groups[gi].rep.h) { idx = i; break; }
+        rep_index[gi] = idx;
+        amb[gi] = groups[gi].amb ? 1 : 0;
+    }
+    return (int)groups.size();
+}
+
+}  // extern "C"

@@ -305,3 +305,79 @@ def test_norm_loss_shrinks_with_theta(oracle_mod):
         o.step(40)
         losses.append(abs(1.0 - np.trace(o.rho(40)).real))
     assert losses[0] > losses[1] > losses[2]
+
+
+# ----------------------------------------------------------------- decision log
+# The oracle counts representative choices (Sec. 3.1.2) and filter decisions
+# (Sec. 2.1) that a relative perturbation of 1e-12 of |w|^2 could flip; every
+# parity test requires zero of them.  These worked examples pin that log.  At
+# qbits = 32 the compared |w|^2 keeps 20 mantissa bits: in [1, 2) the quanta
+# are [1 + k 2^-20, 1 + (k+1) 2^-20).
+_Q1 = 1.0 + 2.0 ** -20          # a quantum boundary
+_MID = 1.0 + 2.0 ** -21         # the middle of the quantum [1, _Q1)
+
+
+def _amp(v, split=False):
+    """An amplitude with |w|^2 = v (to a few ulp): real, or split evenly over re and im."""
+    if split:
+        a = math.sqrt(v / 2.0)
+        return complex(a, a)
+    return complex(math.sqrt(v), 0.0)
+
+
+@pytest.mark.parametrize("vw,vo,split,qbits,eps,want", [
+    (1.5, 1.0, False, 32, 1e-12, False),                         # clear winner
+    (_Q1 * (1 + 1e-14), _Q1 * (1 - 1e-14), False, 32, 1e-12, True),   # near tie across a boundary
+    (_MID * (1 + 1e-14), _MID * (1 - 1e-14), False, 32, 1e-12, False),  # same quantum, far from its edges
+    (_Q1 * (1 - 1e-13), _Q1 * (1 - 2e-13), False, 32, 1e-12, True),   # same quantum, eps reaches the edge
+    (_MID, _MID, False, 32, 1e-12, False),                       # exact tie: decided by the history
+    (_Q1 * (1 + 5e-11), _Q1 * (1 - 5e-11), False, 32, 1e-12, False),  # adjacent quanta, eps too small to cross
+    (1.5, 1.0, True, 32, 1e-12, False),                          # |w|^2 takes both components
+    (1.5 * (1 + 1e-14), 1.5, False, 0, 1e-12, True),             # unquantised compare: a near tie
+    (1.5 * (1 + 1e-14), 1.5, False, 0, 0.0, False),              # no perturbation: a strict winner
+])
+def test_could_flip_worked_examples(oracle_mod, vw, vo, split, qbits, eps, want):
+    assert oracle.could_flip(_amp(vw, split), _amp(vo), qbits=qbits, eps=eps) is want
+
+
+def test_flag_ambiguous_worked_example(oracle_mod):
+    """Three groups merged on position 0: a near tie across a quantum boundary is
+    flagged; an exact tie in the middle of a quantum, decided by the history,
+    and a lone member are not."""
+    hist = np.array([[0, 1], [0, 2], [0, 3],     # group of point 0 = 0
+                     [1, 1], [1, 0],             # point 0 = 1: exact tie
+                     [2, 0]], dtype=np.uint8)    # point 0 = 2: alone
+    w = np.array([_amp(_Q1 * (1 + 1e-14)), _amp(_Q1 * (1 - 1e-14)), _amp(0.25),
+                  _amp(1.25 + 2.0 ** -21), _amp(1.25 + 2.0 ** -21), _amp(0.3)])
+    rep, amb = oracle.flag_demo(hist, w, [0])
+    assert list(rep) == [0, 4, 5]        # the tie goes to the smaller oldest point (member 4)
+    assert list(amb) == [True, False, False]
+    # moving both members 1e-9 away from the boundary clears the flag (with the
+    # winner still within 1e-12 of it, a perturbation could make the two tie)
+    w2 = w.copy()
+    w2[0] = _amp(_Q1 * (1 + 1e-9))
+    w2[1] = _amp(_Q1 * (1 - 1e-9))
+    _, amb2 = oracle.flag_demo(hist, w2, [0])
+    assert list(amb2) == [False, False, False]
+
+
+def test_theta_margin_is_counted(oracle_mod):
+    """With no coupling the step-1 children are rho0 times K4 = U (x) conj(U)
+    (eq. SysP).  A threshold equal to |U00 U10| -- the modulus of the children
+    of pairs (0,1) and (1,0) -- puts both within the ambiguity margin; one
+    1e-6 above it drops both with no ambiguity (Sec. 2.1, path filtering).
+    Here |U00| > |U10|."""
+    K, dt = 3, 0.2
+    H = W.tls_hamiltonian(0.5, 1.0)
+    U = expm(-1j * H * dt)
+    th = abs(U[0, 0]) * abs(U[1, 0])
+    eta = np.zeros((3, K + 1), dtype=complex)
+    o = oracle.Oracle(H, [1, -1], dt, K, eta, W.ground_projector(2), theta=th, mode=PRE)
+    o.step(1)
+    s = o.stats(1)
+    assert s["n_amb_theta"] == 2 and s["theta_margin"] < 1e-12
+    o2 = oracle.Oracle(H, [1, -1], dt, K, eta, W.ground_projector(2), theta=th * (1 + 1e-6), mode=PRE)
+    o2.step(1)
+    s2 = o2.stats(1)
+    # only (0,0) survives: |U10|^2 < |U00 U10| drops (1,1) too
+    assert s2["n_amb_theta"] == 0 and s2["n_survivors"] == 1 and 1e-7 < s2["theta_margin"] < 1e-5
