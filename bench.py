@@ -9,10 +9,15 @@ timing and stay resident in HBM with the path store.
 
 Prints one JSON line:  value = path-steps/s over the timed propagations
 (path-step = one child, i.e. one group extended by one forward/backward pair
-in one time step), a roofline object for the step kernel (algorithmic bytes =
-32 B per group read + 32 B per group written, over the kernel's mean launch
-time from HIP events the library records on its stream around each launch),
-and the CPU oracle timed on a bounded sample of the same workload.
+in one time step), a roofline object for the step kernel, and the CPU oracle
+timed on a bounded steady-state sample of the same workload.
+
+Roofline: the algorithmic bytes of a time step are one record per group
+extended plus one per surviving child (32 B each in FP64: every merged group
+is read once and every survivor is emitted once towards the merge), divided
+by the kernel's mean launch time from HIP events the library records on its
+stream around each launch.  The stricter state-only floor (one record per
+group read + one per group stored) is reported beside it.
 
 --copy-mib N adds one plain device-to-device copy of N MiB after the timed
 work: a kernel of known traffic against which the PMC byte counters of a
@@ -23,13 +28,17 @@ bath parameter points (peak frequency w0 uniform in [0.5, 2], width gamma in
 {0.02, 0.05, 0.1}, seeded), all propagated together for 1000 steps, one
 step-kernel launch per time step; value counts the path-steps of all of them.
 
+--workload spin-boson measures the correctness/latency configuration: an
+unbiased two-level system in an Ohmic bath (alpha 0.1, wc 5, beta 5), dt 0.25,
+dk_max 8, no mask (exact iQUAPI by post-merging on every lag), no filter, 100
+time steps: 4^8 = 65536 groups per step at steady state.
+
 --workload long-memory measures the long-memory configuration instead: the
 same structured bath with dk_max = 40, theta = 1e-9, the mask keeping lags
 0..11 exact and lags 16, 24 and 32 of the tail (80-bit histories, hash-table
 merge), 1000 time steps.  Its roofline object covers the expand kernel, the
-largest share of that step (algorithmic bytes = one stored group read per
-group extended + one written per group stored).  --precision fp32 runs the
-FP32 log-domain form on either workload.
+largest share of that step, with the same algorithmic bytes per step.
+--precision fp32 runs the FP32 log-domain form on either workload.
 """
 from __future__ import annotations
 
@@ -52,24 +61,31 @@ CSRC = "paper_2506_03127_amd/csrc/"
 
 # per workload: the kernel the roofline object covers, the sources it is built
 # from, the committed PMC traffic record, and the oracle sample for the CPU baseline
+# (cpu_skip, cpu_steps): the oracle runs steps 1..cpu_skip untimed, then times the
+# next cpu_steps (a steady-state window where the workload has one)
 WORKLOADS = {
     "structured-bath": {
         "kernel": "step_kernel", "kernel_label": "step_kernel<4,2>",
         "sources": [CSRC + "quapi_step.hip", CSRC + "quapi_device.h", CSRC + "quapi_host.h"],
-        "traffic": "step_kernel_traffic.json", "cpu_steps": 22, "max_groups": 0},
+        "traffic": "step_kernel_traffic.json", "cpu_skip": 25, "cpu_steps": 8, "max_groups": 0},
     "batched-scan": {
         "kernel": "step_kernel", "kernel_label": "step_kernel<4,2,batched>",
         "sources": [CSRC + "quapi_step.hip", CSRC + "quapi_device.h", CSRC + "quapi_host.h"],
-        "traffic": "step_kernel_batched_scan_traffic.json", "cpu_steps": 22, "max_groups": 0},
+        "traffic": "step_kernel_batched_scan_traffic.json", "cpu_skip": 25, "cpu_steps": 8, "max_groups": 0},
     "three-level": {
         "kernel": "step_kernel", "kernel_label": "step_kernel<9,4>",
         "sources": [CSRC + "quapi_step.hip", CSRC + "quapi_device.h", CSRC + "quapi_host.h"],
-        "traffic": "step_kernel_three_level_traffic.json", "cpu_steps": 100, "max_groups": 0},
+        "traffic": "step_kernel_three_level_traffic.json", "cpu_skip": 17, "cpu_steps": 100, "max_groups": 0},
+    "spin-boson": {
+        "kernel": "step_kernel", "kernel_label": "step_kernel<4,2>",
+        "sources": [CSRC + "quapi_step.hip", CSRC + "quapi_device.h", CSRC + "quapi_host.h"],
+        "traffic": "step_kernel_spin_boson_traffic.json", "cpu_skip": 9, "cpu_steps": 91, "max_groups": 0},
     "long-memory": {
         "kernel": "sparse_expand", "kernel_label": "sparse_expand<4,2,2>",
         "sources": [CSRC + "quapi_sparse.hip", CSRC + "quapi_sparse.h", CSRC + "quapi_device.h",
                     CSRC + "quapi_host.h"],
-        "traffic": "sparse_expand_long_memory_traffic.json", "cpu_steps": 15, "max_groups": 48 << 20},
+        "traffic": "sparse_expand_long_memory_traffic.json", "cpu_skip": 0, "cpu_steps": 15,
+        "max_groups": 48 << 20},
 }
 
 
@@ -115,21 +131,25 @@ def cpu_model() -> str:
     return platform.processor() or "unknown"
 
 
-def cpu_baseline(wl, steps: int) -> dict:
-    """The oracle as it stands, single-threaded, on the first `steps` time steps."""
+def cpu_baseline(wl, skip: int, steps: int) -> dict:
+    """The oracle as it stands, single-threaded: steps 1..skip untimed, then the
+    next `steps` time steps timed."""
     import oracle
     from oracle.eta import Bath, eta_columns
     b = wl.bath
     eta = eta_columns(Bath(b.ohmic_alpha, b.ohmic_wc, b.peaks), wl.beta, wl.dt, wl.K)
     o = oracle.Oracle(wl.H, wl.q, wl.dt, wl.K, eta, wl.rho0, mask=wl.mask, theta=wl.theta,
-                      mode=oracle.PRE)
+                      mode=oracle.PRE if wl.mode == "pre" else oracle.POST)
+    if skip > 0:
+        o.step(skip)
     t0 = time.perf_counter()
     o.step(steps)
     el = time.perf_counter() - t0
-    children = sum(o.stats(t)["n_children"] for t in range(1, steps + 1))
+    children = sum(o.stats(t)["n_children"] for t in range(skip + 1, skip + steps + 1))
     return {"value": children / el, "unit": "path-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"time steps 1..{steps} of the same workload ({children} path-steps, "
-                      f"{el:.1f} s, single thread, {cpu_model()})"}
+            "time_per_rho_us": 1e6 * el / steps,
+            "sample": f"time steps {skip + 1}..{skip + steps} of the same workload, after {skip} untimed "
+                      f"({children} path-steps, {el:.1f} s, single thread, {cpu_model()})"}
 
 
 def traffic_from_counters(fetch_csv: str, write_csv: str, spec: dict, copy_mib: int) -> dict:
@@ -179,8 +199,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5, help="timed propagations")
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cpu-steps", type=int, default=-1,
-                    help="time steps of the oracle sample for the CPU baseline (0: skip; "
-                         "default: 22 for the structured bath, 15 for the long-memory workload)")
+                    help="timed time steps of the oracle sample for the CPU baseline (0: skip; "
+                         "default per workload, after an untimed run into the steady state)")
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="structured-bath")
     ap.add_argument("--chunk-run", type=int, default=0,
@@ -231,12 +251,15 @@ def main():
     else:
         if args.workload == "structured-bath":
             wl = workloads.structured_bath()
+        elif args.workload == "spin-boson":
+            wl = workloads.spin_boson_ohmic(mode="post")
         elif args.workload == "three-level":
             wl = workloads.three_level(K=16, n_exact=6, theta=1e-8, n_steps=200)
         else:
             wl = workloads.long_memory()
         prop = quapi.Propagator(wl.H, wl.q, wl.dt, wl.K, eta_of(wl.bath, wl.K), wl.rho0, mask=wl.mask,
-                                theta=wl.theta, mode=quapi.QUAPI_PRE, max_steps=wl.n_steps,
+                                theta=wl.theta, mode=quapi.QUAPI_PRE if wl.mode == "pre" else quapi.QUAPI_POST,
+                                max_steps=wl.n_steps,
                                 stream=stream.cuda_stream, max_groups=spec["max_groups"], precision=precision)
     b = wl.bath
     info = prop.info()
@@ -245,7 +268,7 @@ def main():
     n_t = wl.n_steps
 
     if wl.M == 2:
-        system = {"eps": 0.5, "Delta": 1.0}
+        system = {"eps": float(2 * wl.H[0, 0].real), "Delta": float(2 * wl.H[0, 1].real)}
     else:
         system = {"H_S": "seeded random Hermitian, entries ~ N(0, 0.5), seed 7", "q": [float(x) for x in wl.q]}
 
@@ -282,10 +305,13 @@ def main():
     children = sum(s["n_children"] for st in sts for s in st)
     groups_in = np.sum([[s["n_groups"] for s in st] for st in sts], axis=0, dtype=np.float64)
     groups_out = np.sum([[s["n_stored"] for s in st] for st in sts], axis=0, dtype=np.float64)
+    surv = np.sum([[s["n_survivors"] for s in st] for st in sts], axis=0, dtype=np.float64)
     total = sum(times)
     ms_per_step = 1e3 * total / len(times)
     value = children * len(times) / total
-    alg_bytes = record_bytes * (groups_in + groups_out)
+    # algorithmic bytes per time step: a record per group extended + one per surviving child
+    alg_bytes = record_bytes * (groups_in + surv)
+    floor_bytes = record_bytes * (groups_in + groups_out)      # state only: read + stored
 
     out = {
         "metric": METRIC,
@@ -301,11 +327,12 @@ def main():
         "dtype": "f64" if args.precision == "fp64" else "f32 (log domain) + f64 sums",
         "data": "synthetic (model Hamiltonian and spectral density; no dataset)",
         "config": {
-            "workload": wl.name, "M": wl.M, "dk_max": wl.K, "mask": list(wl.mask),
-            "theta": wl.theta, "time_steps": n_t, "mode": "pre-merging",
+            "workload": wl.name, "M": wl.M, "dk_max": wl.K,
+            "mask": list(range(wl.K)) if wl.mask is None else list(wl.mask),
+            "theta": wl.theta, "time_steps": n_t,
             "bath": {"ohmic_alpha": b.ohmic_alpha, "ohmic_wc": b.ohmic_wc,
                      "peaks_w0_gamma_lambda": [list(p) for p in b.peaks]},
-            "beta": wl.beta, "dt": wl.dt, **system,
+            "beta": wl.beta, "dt": wl.dt, **system, "mode": wl.mode + "-merging",
             "precision": args.precision, "merge": "hash table" if info["hash_merge"] else "bucketed store",
             "record_bytes": record_bytes, "instances": n_inst, "chunk_run": chunk_run,
             "hip_graph": bool(args.graph),
@@ -313,6 +340,7 @@ def main():
         "time_per_rho_us": 1e3 * ms_per_step / n_t,
         "path_steps_per_propagation": children,
         "mean_groups_per_step": float(groups_in.mean()),
+        "mean_survivors_per_step": float(surv.mean()),
         "run_hbm_fraction": float(alg_bytes.sum() / (total / len(times)) / (HBM_PEAK_GBS * 1e9)),
         "trace_final": float(np.trace(rho[-1][0]).real),
     }
@@ -332,13 +360,19 @@ def main():
         mean_s = float(step_ms.mean()) * 1e-3
         per_launch_bytes = float(alg_bytes.mean())
         achieved = per_launch_bytes / mean_s / 1e9
+        floor_gbs = float(floor_bytes.mean()) / mean_s / 1e9
         out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(spec),
                            "kernel": spec["kernel_label"], "launches": n_t,
                            "mean_launch_us": mean_s * 1e6,
                            ("rest_of_step_mean_us" if info["hash_merge"] else "planner_mean_launch_us"):
                                float(plan_ms.mean()) * 1e3,
-                           "alg_bytes_per_launch": per_launch_bytes}
+                           "alg_bytes_per_launch": per_launch_bytes,
+                           "alg_bytes": f"{record_bytes} B x (groups extended + surviving children) per step",
+                           "mean_groups_per_launch": float(groups_in.mean()),
+                           "mean_survivors_per_launch": float(surv.mean()),
+                           "state_floor_bytes_per_launch": float(floor_bytes.mean()),
+                           "state_floor_frac": floor_gbs / HBM_PEAK_GBS}
 
     if args.copy_mib > 0:
         import torch
@@ -351,7 +385,7 @@ def main():
         out["copy_calibration_bytes"] = nb
 
     if args.cpu_steps > 0:
-        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(wl, spec["cpu_skip"], args.cpu_steps)
 
     prop.close()
     print(json.dumps(out), flush=True)

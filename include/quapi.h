@@ -23,7 +23,9 @@
  *
  * Conventions (all functions):
  *   - return QUAPI_OK (0) or a negative QUAPI_E* code; quapi_strerror() names it;
- *   - a context is used by one host thread at a time; there is no global state;
+ *   - a context is used by one host thread at a time; the only state shared
+ *     between contexts is, per device, the library stream of contexts that pass
+ *     no stream and the event that orders step kernels (both thread-safe);
  *   - complex numbers are quapi_c64 {re, im}; matrices are row-major;
  *   - pair index p = a*M + b for forward state a and backward state b;
  *   - hbar = 1.
@@ -63,7 +65,7 @@ typedef struct quapi_ctx quapi_ctx;
 /* Problem definition, copied by quapi_create (the caller keeps ownership of
  * every pointer and may free it after the call). */
 typedef struct {
-    int M;                    /* number of system (DVR) states, 2..4                                    */
+    int M;                    /* number of system (DVR) states, 2..3 (M > 3: QUAPI_EUNSUPPORTED)        */
     const quapi_c64* H;       /* M*M Hermitian system Hamiltonian H_S (eq. tot_ham), used as given;     */
                               /* rejected if |H_ij - conj(H_ji)| > 1e-12 max(1, max|H|)                  */
     const double* q;          /* M coupling eigenvalues q_i of the DVR states (eq. tot_ham)             */
@@ -96,8 +98,9 @@ typedef struct {
     int max_steps;            /* initial capacity of the rho(t) history; grows on demand; <= 0: 1024    */
     void* stream;             /* hipStream_t to run on (e.g. a torch stream); NULL: the library's      */
                               /* stream of the device, shared by every context that passes NULL.  A     */
-                              /* step kernel needs the whole GPU resident: contexts on streams of their */
-                              /* own must not step side by side (the look-back then reports EDEVICE)    */
+                              /* step kernel needs the whole GPU resident, so the library orders the    */
+                              /* step kernels of one device across all streams: each waits for the one */
+                              /* enqueued before it (an event per device); other work overlaps freely   */
     int precision;            /* QUAPI_FP64 (0) or QUAPI_FP32_LOG                                       */
 } quapi_params;
 

@@ -69,6 +69,7 @@ struct quapi_ctx {
     hipStream_t stream = nullptr;
     bool own_stream = false;                 // the device's shared library stream, released at destroy
     int stream_dev = 0;
+    int dev = 0;                             // device the context was created on
     GroupBuf buf[2] = {};
     unsigned int* counts[2] = {nullptr, nullptr};
     double* d_tables = nullptr;
@@ -406,6 +407,46 @@ void release_shared_stream(int dev) {
     }
 }
 
+// Step kernels of one device run one after another, whatever stream they are
+// on: each waits for the event recorded after the one enqueued before it (by
+// any context on the device) and records the event anew.  The event's state is
+// taken when the wait is enqueued, so the lock only has to cover the pair.
+struct StepOrder {
+    std::mutex mu;
+    hipEvent_t last = nullptr;
+};
+std::mutex g_order_mu;
+std::map<int, StepOrder*> g_order;   // never freed: lives until the process ends
+
+StepOrder* step_order(int dev) {
+    std::lock_guard<std::mutex> lk(g_order_mu);
+    StepOrder*& o = g_order[dev];
+    if (!o) o = new (std::nothrow) StepOrder();
+    return o;
+}
+
+// Enqueue `launch` on `stream` after every step kernel enqueued before it on
+// the device, and make it the one the next waits for.
+template <class F>
+hipError_t ordered_launch(int dev, hipStream_t stream, F&& launch) {
+    StepOrder* o = step_order(dev);
+    if (!o) return hipErrorOutOfMemory;
+    std::lock_guard<std::mutex> lk(o->mu);
+    if (!o->last) {
+        const hipError_t e = hipEventCreateWithFlags(&o->last, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            o->last = nullptr;
+            return e;
+        }
+    } else {
+        const hipError_t e = hipStreamWaitEvent(stream, o->last, 0);
+        if (e != hipSuccess) return e;
+    }
+    const hipError_t e = launch();
+    if (e != hipSuccess) return e;
+    return hipEventRecord(o->last, stream);
+}
+
 // zero n 64-bit words: a kernel, so that a HIP graph records it as a kernel node
 __global__ __launch_bounds__(256) void clear_words(unsigned long long* p, size_t n) {
     for (size_t k = (size_t)blockIdx.x * 256u + threadIdx.x; k < n; k += (size_t)gridDim.x * 256u) p[k] = 0ull;
@@ -644,16 +685,19 @@ static int create_ctx(const quapi_params* p, int n_inst, const quapi_c64* eta_al
     }
 
     int rc = QUAPI_OK;
+    if (hipGetDevice(&c->dev) != hipSuccess) {
+        delete c;
+        return QUAPI_EDEVICE;
+    }
     if (p->stream) {
         c->stream = (hipStream_t)p->stream;
     } else {
-        int dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess || acquire_shared_stream(dev, &c->stream) != hipSuccess) {
+        if (acquire_shared_stream(c->dev, &c->stream) != hipSuccess) {
             delete c;
             return QUAPI_EDEVICE;
         }
         c->own_stream = true;
-        c->stream_dev = dev;
+        c->stream_dev = c->dev;
     }
 
     const size_t nrec = c->sparse ? 1 : (size_t)c->n_buckets * (size_t)cap;
@@ -817,7 +861,13 @@ int quapi_step(quapi_ctx* c, int n_steps) {
         hipEvent_t* ev = (c->prof_on && !c->capturing && c->prof_n < c->prof_cap)
                              ? &c->prof_ev[3 * (size_t)c->prof_n++] : nullptr;
         if (ev && hipEventRecord(ev[0], c->stream) != hipSuccess) ev = nullptr;
-        if (quapi_dev::launch_step(a, c->grid, c->stream) != (int)hipSuccess) {
+        // (inside a graph capture the whole graph is ordered at its launch instead)
+        const hipError_t le =
+            c->capturing ? (hipError_t)quapi_dev::launch_step(a, c->grid, c->stream)
+                         : ordered_launch(c->dev, c->stream, [&] {
+                               return (hipError_t)quapi_dev::launch_step(a, c->grid, c->stream);
+                           });
+        if (le != hipSuccess) {
             c->err = QUAPI_EDEVICE;
             return c->err;
         }
@@ -881,7 +931,7 @@ int quapi_step_graph(quapi_ctx* c, int n_steps) {
         c->graph_stats = c->d_stats;
         c->graph_epoch_end = c->epoch;
     }
-    const hipError_t e = hipGraphLaunch(c->graph, c->stream);
+    const hipError_t e = ordered_launch(c->dev, c->stream, [&] { return hipGraphLaunch(c->graph, c->stream); });
     if (e != hipSuccess) {
         c->err = QUAPI_EDEVICE;
         return c->err;

@@ -131,6 +131,11 @@ __global__ __launch_bounds__(kPlanThreads) void plan_kernel(const PlanArgs a) {
         return;
     }
 
+    // a failed step leaves the stored groups of the step before it in place: the
+    // lists, the plan and the bucket sizes (counts_next holds the last complete
+    // state's sizes after a failure) stay as they are
+    if (error_word(a.error) != 0u) return;
+
     // ---- this thread's bucket sizes and, in the same batch, those before the region
     const long long b_lo = (long long)w * kRegion + (long long)i * kPlanPer;
     unsigned int cnt[kPlanPer];
@@ -295,6 +300,7 @@ __global__ __launch_bounds__(kPlanThreads) void plan_batch_lists(const PlanArgs 
     const unsigned int lane = lane_id();
     const int B = a.n_inst;
     const int w = (int)blockIdx.x;
+    if (error_word(a.error) != 0u) return;       // keep the last complete state (see plan_kernel)
 
     // ---- where instance w starts: chunks and list entries of the instances before it
     unsigned long long before = 0;                     // (chunks << 32) | list entries

@@ -141,6 +141,14 @@ def test_batch_capacity_overflow_and_reset(Q):
         o = oracle.Oracle(wl.H, wl.q, wl.dt, K, etas[j], wl.rho0, mask=wl.mask, theta=0.0, mode=oracle.PRE)
         o.step(t)
         assert np.abs(g.rho_history(j, 0, t + 1) - o.rho_history()).max() < RHO_TOL
+        # every instance keeps the groups of the last complete step
+        assert sum(o.stats(k)["n_amb_rep"] for k in range(1, t + 1)) == 0
+        ho, wo = o.groups()
+        hg, wg = g.groups(j)
+        assert ho.shape == hg.shape, (j, ho.shape, hg.shape)
+        io, ig = np.lexsort(ho.T[::-1]), np.lexsort(hg.T[::-1])
+        assert np.array_equal(ho[io], hg[ig])
+        assert np.abs(wo[io] - wg[ig]).max() < RHO_TOL
     g.reset()
     g.step(3)
     o = oracle.Oracle(wl.H, wl.q, wl.dt, K, etas[1], wl.rho0, mask=wl.mask, theta=0.0, mode=oracle.PRE)

@@ -309,6 +309,9 @@ def test_capacity_overflow_is_reported(Q, eta_cache):
     o = oracle.Oracle(wl.H, wl.q, wl.dt, wl.K, eta, wl.rho0, mode=oracle.POST)
     o.step(t)
     assert np.abs(Q.quapi_rho(g.ctx, t, 2) - o.rho(t)).max() < RHO_TOL
+    # the stored groups are those of the last complete step, not the failed one's
+    assert ambiguous(o, t) == 0
+    assert_groups(o, g)
     with pytest.raises(Q.QuapiError) as e2:
         g.step(1)
     assert e2.value.code == Q.QUAPI_ESTATE
@@ -415,3 +418,33 @@ def test_merging_study_matches_oracle(Q, eta_cache):
     assert r["pre_path_steps"] == res[oracle.PRE][1]
     assert r["post_path_steps"] == res[oracle.POST][1]
     assert r["post_stored_max"] >= r["pre_stored_max"]
+
+
+def test_contexts_on_caller_streams_step_side_by_side(Q, eta_cache):
+    """Two contexts on two streams of their own step in turn with no
+    synchronisation between them.  The library orders the two persistent step
+    kernels on the device, so both finish and each equals a lone run bit for
+    bit (rho(t), counters, groups)."""
+    import torch
+    wl = W.structured_bath(K=12)
+    eta = eta_cache(wl, 12)
+    cases = [dict(mask=(0, 1, 2, 3, 4, 5), theta=1e-7), dict(mask=(0, 1, 2, 3, 4, 5, 6), theta=1e-8)]
+    n = 60
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    ctx = [Q.Propagator(wl.H, wl.q, wl.dt, 12, eta, wl.rho0, stream=s.cuda_stream, **kw)
+           for s, kw in zip((s1, s2), cases)]
+    print(f"[streams] two contexts on caller streams, {n} steps each", flush=True)
+    for _ in range(n):
+        for c in ctx:
+            c.step(1)
+    for c in ctx:
+        c.sync()
+    for c, kw in zip(ctx, cases):
+        lone = Q.Propagator(wl.H, wl.q, wl.dt, 12, eta, wl.rho0, **kw)
+        lone.step(n)
+        lone.sync()
+        assert np.array_equal(c.rho_history(), lone.rho_history())
+        assert c.stats(1, n) == lone.stats(1, n)
+        hc, wc = c.groups()
+        hl, wlone = lone.groups()
+        assert np.array_equal(hc, hl) and np.array_equal(wc, wlone)
