@@ -99,8 +99,8 @@ typedef struct {
     void* stream;             /* hipStream_t to run on (e.g. a torch stream); NULL: the library's      */
                               /* stream of the device, shared by every context that passes NULL.  A     */
                               /* step kernel needs the whole GPU resident, so the library orders the    */
-                              /* step kernels of one device across all streams: each waits for the one */
-                              /* enqueued before it (an event per device); other work overlaps freely   */
+                              /* step kernels of one device across all streams: a step kernel on     */
+                              /* another stream than the last one waits for it; other work overlaps  */
     int precision;            /* QUAPI_FP64 (0) or QUAPI_FP32_LOG                                       */
 } quapi_params;
 

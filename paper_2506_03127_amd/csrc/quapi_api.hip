@@ -408,12 +408,15 @@ void release_shared_stream(int dev) {
 }
 
 // Step kernels of one device run one after another, whatever stream they are
-// on: each waits for the event recorded after the one enqueued before it (by
-// any context on the device) and records the event anew.  The event's state is
-// taken when the wait is enqueued, so the lock only has to cover the pair.
+// on.  The device remembers the stream of the last step kernel enqueued; a
+// launch from another stream first waits for an event recorded on that stream
+// (after everything enqueued there so far, the step kernel included).  Launches
+// that stay on one stream add nothing to it: stream order already holds.
 struct StepOrder {
     std::mutex mu;
-    hipEvent_t last = nullptr;
+    hipEvent_t ev = nullptr;
+    hipStream_t last = nullptr;   // stream of the last step kernel enqueued, or none
+    bool ev_valid = false;        // ev was recorded on `last` after that kernel
 };
 std::mutex g_order_mu;
 std::map<int, StepOrder*> g_order;   // never freed: lives until the process ends
@@ -426,25 +429,55 @@ StepOrder* step_order(int dev) {
 }
 
 // Enqueue `launch` on `stream` after every step kernel enqueued before it on
-// the device, and make it the one the next waits for.
+// the device.
 template <class F>
 hipError_t ordered_launch(int dev, hipStream_t stream, F&& launch) {
     StepOrder* o = step_order(dev);
     if (!o) return hipErrorOutOfMemory;
     std::lock_guard<std::mutex> lk(o->mu);
-    if (!o->last) {
-        const hipError_t e = hipEventCreateWithFlags(&o->last, hipEventDisableTiming);
-        if (e != hipSuccess) {
-            o->last = nullptr;
-            return e;
+    if (o->last && o->last != stream) {
+        if (!o->ev) {
+            const hipError_t e = hipEventCreateWithFlags(&o->ev, hipEventDisableTiming);
+            if (e != hipSuccess) {
+                o->ev = nullptr;
+                return e;
+            }
         }
-    } else {
-        const hipError_t e = hipStreamWaitEvent(stream, o->last, 0);
+        if (!o->ev_valid) {
+            const hipError_t e = hipEventRecord(o->ev, o->last);
+            if (e != hipSuccess) return e;
+            o->ev_valid = true;
+        }
+        const hipError_t e = hipStreamWaitEvent(stream, o->ev, 0);
         if (e != hipSuccess) return e;
     }
     const hipError_t e = launch();
     if (e != hipSuccess) return e;
-    return hipEventRecord(o->last, stream);
+    o->last = stream;
+    o->ev_valid = false;
+    return hipSuccess;
+}
+
+// Record the device's event on `stream` now when the last step kernel is
+// there and no event follows it yet, so that later launches from other streams
+// wait on that event and never record on `stream` itself: before the stream is
+// captured into a graph (nothing may be recorded on it from outside the
+// capture) and when a context on it is destroyed (the stream may go away).
+hipError_t order_release(int dev, hipStream_t stream) {
+    StepOrder* o = step_order(dev);
+    if (!o) return hipErrorOutOfMemory;
+    std::lock_guard<std::mutex> lk(o->mu);
+    if (o->last != stream || o->ev_valid) return hipSuccess;
+    if (!o->ev) {
+        const hipError_t e = hipEventCreateWithFlags(&o->ev, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            o->ev = nullptr;
+            return e;
+        }
+    }
+    const hipError_t e = hipEventRecord(o->ev, stream);
+    if (e == hipSuccess) o->ev_valid = true;
+    return e;
 }
 
 // zero n 64-bit words: a kernel, so that a HIP graph records it as a kernel node
@@ -899,7 +932,9 @@ int quapi_step_graph(quapi_ctx* c, int n_steps) {
         }
         const int t0 = c->t, cur0 = c->cur;
         hipGraph_t g = nullptr;
-        hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+        hipError_t e = order_release(c->dev, c->stream);
+        if (e != hipSuccess) return hip_to_code(e);
+        e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hip_to_code(e);
         // look-back words of an earlier replay carry the same epochs: clear them first
         const hipError_t lr = launch_clear_words(c->d_chain, (size_t)c->P * c->max_chunks, c->stream);
@@ -1198,7 +1233,10 @@ int quapi_profile_end(quapi_ctx* c, int cap, double* step_ms, double* plan_ms, i
 
 void quapi_destroy(quapi_ctx* c) {
     if (!c) return;
-    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    if (c->stream) {
+        (void)order_release(c->dev, c->stream);
+        (void)hipStreamSynchronize(c->stream);
+    }
     if (c->graph) (void)hipGraphExecDestroy(c->graph);
     for (hipEvent_t e : c->prof_ev) (void)hipEventDestroy(e);
     c->prof_ev.clear();

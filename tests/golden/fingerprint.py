@@ -67,15 +67,19 @@ def fingerprint(hist, w) -> dict:
 
 
 def compare(got: dict, want: dict, wtol: float) -> str:
-    """'' when the fingerprints agree (amplitude sums within wtol), else a reason."""
+    """'' when the fingerprints agree, else a reason.  The amplitude sums must
+    agree within wtol * max(1, sum |w|): wtol bounds each amplitude's error
+    relative to the largest, so the sums' error is bounded by wtol times the
+    sum of the moduli."""
     if got["n"] != want["n"]:
         return f"group count {got['n']} != {want['n']}"
     if got["hsum"] != want["hsum"]:
         return "history sets differ"
+    tol = wtol * max(1.0, want["wabs"])
     dw = abs(complex(*got["wsum"]) - complex(*want["wsum"]))
-    if dw > wtol:
-        return f"amplitude sums differ by {dw:.3e}"
+    if dw > tol:
+        return f"amplitude sums differ by {dw:.3e} (bound {tol:.1e})"
     da = abs(got["wabs"] - want["wabs"])
-    if da > wtol:
-        return f"|w| sums differ by {da:.3e}"
+    if da > tol:
+        return f"|w| sums differ by {da:.3e} (bound {tol:.1e})"
     return ""

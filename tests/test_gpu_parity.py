@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 import oracle
+from golden_runs import GoldenRun, check_fingerprint, check_stats
 from oracle.brute import brute_rho
 from paper_2506_03127_amd import workloads as W
 
@@ -320,55 +321,77 @@ def test_capacity_overflow_is_reported(Q, eta_cache):
 
 
 # ------------------------------------------------------------------ full size, bench launch shape
-def test_structured_bath_full_run(Q, eta_cache):
-    """1000 steps at the full size, launched as the benchmark launches it; the
-    first 16 steps are compared with the oracle element by element, and the
-    counters of every step satisfy the invariants of the method."""
-    wl = W.structured_bath()
-    eta = eta_cache(wl)
-    g = Q.Propagator(wl.H, wl.q, wl.dt, wl.K, eta, wl.rho0, mask=wl.mask, theta=wl.theta,
-                     max_steps=wl.n_steps)
-    g.step(wl.n_steps)
+# These compare with stored oracle runs (tests/golden/oracle_*.json, written by
+# tests/golden/make_oracle_runs.py from oracle/ alone): rho(t) and the counters
+# of every stored step, and fingerprints of the full group sets (history hash,
+# amplitude sums) at every step up to 100 and every tenth after it.
+def _fp_steps(n, every_to=100, stride=10):
+    return [t for t in range(1, n + 1) if t <= every_to or t % stride == 0 or t == n]
+
+
+def _run_against_golden(Q, g, gold, n, groups):
+    """Step g to n in pieces, comparing group fingerprints at the stored steps."""
+    t = 0
+    for tf in _fp_steps(n):
+        if tf not in gold.fp:
+            continue
+        g.step(tf - t)
+        t = tf
+        check_fingerprint(groups(), gold, tf, W_TOL)
+    if t < n:
+        g.step(n - t)
     g.sync()
-    assert g.t == wl.n_steps
+
+
+def test_structured_bath_full_run(Q):
+    """The structured-bath workload (dk_max 24, lags 0..11, theta 1e-8) for all
+    1000 steps, launched as the benchmark launches it (its own stream), against
+    the stored oracle run: rho(t) of every step at 1e-12, every counter, and
+    the group sets up to step 100 and every tenth step after it."""
+    import torch
+    gold = GoldenRun("structured_bath")
+    wl = W.structured_bath()
+    n = wl.n_steps
+    assert gold.steps == n and gold.ambiguous(n) == 0
+    s = torch.cuda.Stream()
+    g = Q.Propagator(wl.H, wl.q, wl.dt, wl.K, gold.eta, wl.rho0, mask=wl.mask, theta=wl.theta,
+                     max_steps=n, stream=s.cuda_stream)
+    print(f"[parity] structured bath, {n} steps against the stored oracle run", flush=True)
+    _run_against_golden(Q, g, gold, n, g.groups)
+    assert g.t == n
     r = g.rho_history()
-    st = g.stats(1, wl.n_steps)
-    n0 = 16
-    o = oracle.Oracle(wl.H, wl.q, wl.dt, wl.K, eta, wl.rho0, mask=wl.mask, theta=wl.theta)
-    o.step(n0)
-    assert np.abs(r[:n0 + 1] - o.rho_history()).max() < RHO_TOL
-    for k, s in enumerate(st):
-        assert s["n_children"] == 4 * s["n_groups"]
-        assert s["n_groups"] <= 4 ** 11
-        if k + 1 < len(st):
-            assert st[k + 1]["n_groups"] == s["n_stored"]
-    tr = np.trace(r, axis1=1, axis2=2)
-    assert np.abs(tr.imag).max() < 1e-12
-    assert tr.real.max() < 1.0 + 1e-12 and tr.real[-1] > 0.9
+    err = np.abs(r - gold.rho).max()
+    print(f"[parity] structured bath: max |drho| over {n} steps = {err:.3e}", flush=True)
+    assert err < RHO_TOL
+    check_stats(g.stats(1, n), gold)
 
 
 def test_long_memory_full_run(Q, eta_cache):
     """The long-memory workload (dk_max 40, lags 0..11, 16, 24 and 32 exact,
     theta 1e-9: 80-bit histories on the hash-table merge, ~1.6e7 groups) for
     1000 steps at the full size, launched as the benchmark launches it: the
-    first 12 steps against the oracle element by element, the counters of
-    every step against the bookkeeping of the method."""
+    stored oracle steps (past K + 1 = 41) element by element -- rho(t),
+    counters, group-set fingerprints -- and the counters of every step against
+    the bookkeeping of the method."""
+    gold = GoldenRun("long_memory")
     wl = W.long_memory()
-    eta = eta_cache(wl)
-    g = Q.Propagator(wl.H, wl.q, wl.dt, wl.K, eta, wl.rho0, mask=wl.mask, theta=wl.theta,
+    n0 = gold.steps
+    assert n0 >= wl.K + 1 and gold.ambiguous(n0) == 0
+    g = Q.Propagator(wl.H, wl.q, wl.dt, wl.K, gold.eta, wl.rho0, mask=wl.mask, theta=wl.theta,
                      max_steps=wl.n_steps, max_groups=48 << 20)
     assert Q.quapi_info(g.ctx)["hash_merge"] == 1
-    print(f"[parity] long memory, {wl.n_steps} steps", flush=True)
-    g.step(wl.n_steps)
+    print(f"[parity] long memory, {n0} stored steps then to {wl.n_steps}", flush=True)
+    _run_against_golden(Q, g, gold, n0, g.groups)
+    r0 = g.rho_history()
+    err = np.abs(r0 - gold.rho).max()
+    print(f"[parity] long memory: max |drho| over {n0} steps = {err:.3e}", flush=True)
+    assert err < RHO_TOL
+    check_stats(g.stats(1, n0), gold)
+    g.step(wl.n_steps - n0)
     g.sync()
     assert g.t == wl.n_steps
     r = g.rho_history()
     st = g.stats(1, wl.n_steps)
-    n0 = 12
-    o = oracle.Oracle(wl.H, wl.q, wl.dt, wl.K, eta, wl.rho0, mask=wl.mask, theta=wl.theta, mode=oracle.PRE)
-    o.step(n0)
-    assert ambiguous(o, n0) == 0
-    assert np.abs(r[:n0 + 1] - o.rho_history()).max() < RHO_TOL
     for k, s in enumerate(st):
         assert s["n_children"] == 4 * s["n_groups"]
         assert s["n_stored"] <= s["n_survivors"] <= s["n_children"]
