@@ -89,8 +89,23 @@ WORKLOADS = {
 }
 
 
-def workload_spec(name: str, precision: str) -> dict:
+# the roofline kernel of each store (the workload's entry above is the bucketed store's)
+STORE_KERNELS = {
+    "direct": {"kernel": "dense_step", "kernel_label": "dense_step<4,2>",
+               "sources": [CSRC + "quapi_dense.hip", CSRC + "quapi_dense.h", CSRC + "quapi_device.h",
+                           CSRC + "quapi_host.h"]},
+    "hash": {"kernel": "sparse_expand", "kernel_label": "sparse_expand",
+             "sources": [CSRC + "quapi_sparse.hip", CSRC + "quapi_sparse.h", CSRC + "quapi_device.h",
+                         CSRC + "quapi_host.h"]},
+}
+STORE_NAMES = {1: "direct", 2: "bucketed", 3: "hash"}
+
+
+def workload_spec(name: str, precision: str, store: str = "bucketed") -> dict:
     spec = dict(WORKLOADS[name])
+    if store in STORE_KERNELS and precision != "fp32":
+        spec.update(STORE_KERNELS[store])
+        spec["traffic"] = f"{spec['kernel']}_{name.replace('-', '_')}_traffic.json"
     if precision == "fp32":
         # the FP32 form runs every mask on the hash-table merge
         spec.update({"kernel": "sparse_expand", "kernel_label": "sparse_expand (FP32 form)",
@@ -209,6 +224,8 @@ def main():
                     help="each propagation as one HIP graph (quapi_step_graph), recorded in the warm-up")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64",
                     help="fp32: the FP32 log-domain form (hash-table merge)")
+    ap.add_argument("--merge", choices=["auto", "direct", "bucketed", "hash"], default="auto",
+                    help="the store (QUAPI_MERGE_*); auto: the library's choice")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="one plain device copy of this size after the timed work (PMC calibration)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -217,7 +234,8 @@ def main():
     args = ap.parse_args()
     if args.graph and args.warmup < 1:
         args.warmup = 1                      # the graph is recorded outside the timed region
-    spec = workload_spec(args.workload, args.precision)
+    # the store is known once the context exists; --traffic-from names it through --merge
+    spec = workload_spec(args.workload, args.precision, args.merge if args.merge != "auto" else "bucketed")
     if args.cpu_steps < 0:
         args.cpu_steps = spec["cpu_steps"]
     if args.traffic_from:
@@ -239,6 +257,8 @@ def main():
 
     stream = torch.cuda.Stream()
     precision = quapi.QUAPI_FP32_LOG if args.precision == "fp32" else quapi.QUAPI_FP64
+    merge = {"auto": quapi.QUAPI_MERGE_AUTO, "direct": quapi.QUAPI_MERGE_DIRECT,
+             "bucketed": quapi.QUAPI_MERGE_BUCKETED, "hash": quapi.QUAPI_MERGE_HASH}[args.merge]
     baths = None
     if args.workload == "batched-scan":
         if args.precision != "fp64":
@@ -247,7 +267,8 @@ def main():
         wl, baths = workloads.batched_scan()
         etas = np.stack([eta_of(b, wl.K) for b in baths])
         prop = quapi.BatchPropagator(wl.H, wl.q, wl.dt, wl.K, etas, wl.rho0, mask=wl.mask, theta=wl.theta,
-                                     mode=quapi.QUAPI_PRE, max_steps=wl.n_steps, stream=stream.cuda_stream)
+                                     mode=quapi.QUAPI_PRE, max_steps=wl.n_steps, stream=stream.cuda_stream,
+                                     merge=merge)
     else:
         if args.workload == "structured-bath":
             wl = workloads.structured_bath()
@@ -260,9 +281,12 @@ def main():
         prop = quapi.Propagator(wl.H, wl.q, wl.dt, wl.K, eta_of(wl.bath, wl.K), wl.rho0, mask=wl.mask,
                                 theta=wl.theta, mode=quapi.QUAPI_PRE if wl.mode == "pre" else quapi.QUAPI_POST,
                                 max_steps=wl.n_steps,
-                                stream=stream.cuda_stream, max_groups=spec["max_groups"], precision=precision)
+                                stream=stream.cuda_stream, max_groups=spec["max_groups"], precision=precision,
+                                merge=merge)
     b = wl.bath
     info = prop.info()
+    store = STORE_NAMES[info["store"]]
+    spec = workload_spec(args.workload, args.precision, store)
     record_bytes = info["record_bytes"]
     n_inst = info["n_instances"]
     n_t = wl.n_steps
@@ -333,7 +357,8 @@ def main():
             "bath": {"ohmic_alpha": b.ohmic_alpha, "ohmic_wc": b.ohmic_wc,
                      "peaks_w0_gamma_lambda": [list(p) for p in b.peaks]},
             "beta": wl.beta, "dt": wl.dt, **system, "mode": wl.mode + "-merging",
-            "precision": args.precision, "merge": "hash table" if info["hash_merge"] else "bucketed store",
+            "precision": args.precision, "merge": {"direct": "direct-mapped store", "bucketed": "bucketed store",
+                                                   "hash": "hash table"}[store],
             "record_bytes": record_bytes, "instances": n_inst, "chunk_run": chunk_run,
             "hip_graph": bool(args.graph),
         },
@@ -365,7 +390,7 @@ def main():
                            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(spec),
                            "kernel": spec["kernel_label"], "launches": n_t,
                            "mean_launch_us": mean_s * 1e6,
-                           ("rest_of_step_mean_us" if info["hash_merge"] else "planner_mean_launch_us"):
+                           ("planner_mean_launch_us" if store == "bucketed" else "rest_of_step_mean_us"):
                                float(plan_ms.mean()) * 1e3,
                            "alg_bytes_per_launch": per_launch_bytes,
                            "alg_bytes": f"{record_bytes} B x (groups extended + surviving children) per step",

@@ -60,6 +60,16 @@ typedef struct { double re, im; } quapi_c64;
                                 /* rounding of each child, and the filter and representative decisions */
                                 /* near their thresholds may differ too                                 */
 
+/* Where the groups live and how they merge (Sec. 3.1.2; quapi_params.merge). */
+#define QUAPI_MERGE_AUTO     0  /* BUCKETED where it applies, else HASH                                   */
+#define QUAPI_MERGE_DIRECT   1  /* a slot per key of the merge positions 0..L-1 (two-level systems,       */
+                                /* 5 <= L <= 13, FP64, lone contexts): the parents that merge are the      */
+                                /* aligned slots of a segment, every merged group has a fixed slot, and a  */
+                                /* step is one kernel whose workgroups never wait on one another           */
+#define QUAPI_MERGE_BUCKETED 2  /* merge positions 0..L-1: groups sorted by key in buckets of their top   */
+                                /* points, merged on chip as runs of neighbours                             */
+#define QUAPI_MERGE_HASH     3  /* any merge positions: an open-addressing hash table in device memory     */
+
 typedef struct quapi_ctx quapi_ctx;
 
 /* Problem definition, copied by quapi_create (the caller keeps ownership of
@@ -94,7 +104,8 @@ typedef struct {
                               /* |w|^2, ~1e-6 relative, must stay well below the compared quantum)      */
     long long max_groups;     /* stored groups to allocate for, spread evenly over the key buckets     */
                               /* (at least one each; an uneven fill reports ENOMEM first); 0: room   */
-                              /* for every key of the merge positions (hash-table merge: up to 2^21) */
+                              /* for every key of the merge positions (hash-table merge: up to 2^21). */
+                              /* The direct-mapped store always holds every key                       */
     int max_steps;            /* initial capacity of the rho(t) history; grows on demand; <= 0: 1024    */
     void* stream;             /* hipStream_t to run on (e.g. a torch stream); NULL: the library's      */
                               /* stream of the device, shared by every context that passes NULL.  A     */
@@ -102,6 +113,8 @@ typedef struct {
                               /* step kernels of one device across all streams: a step kernel on     */
                               /* another stream than the last one waits for it; other work overlaps  */
     int precision;            /* QUAPI_FP64 (0) or QUAPI_FP32_LOG                                       */
+    int merge;                /* QUAPI_MERGE_*: the store (0, AUTO: BUCKETED where it applies, else     */
+                              /* HASH); a store that does not apply returns QUAPI_EUNSUPPORTED          */
 } quapi_params;
 
 /* Per-step counters, available for every step t >= 1 that has completed. */
@@ -119,13 +132,15 @@ typedef struct {
     int M, P, K, L;           /* P = M*M pairs; L = key length in points (merge positions 0..L-1)     */
     int bits_per_point;       /* history bits per point                                                 */
     int record_bytes;         /* bytes of one stored group: 8 key + 8 history tail + 16 weight (32),    */
-                              /* or 8 or 16 history + 16 weight (24 or 32) on the hash-table merge,     */
-                              /* with an 8-byte weight in the FP32 precision form                       */
+                              /* 8 history tail + 16 weight (24) on the direct-mapped store, whose slot  */
+                              /* is the key, or 8 or 16 history + 16 weight (24 or 32) on the hash-table */
+                              /* merge, with an 8-byte weight in the FP32 precision form                 */
     long long capacity;       /* maximum number of stored groups (of one instance)                      */
     size_t device_bytes;      /* device memory held by the context                                      */
     int precision;            /* QUAPI_FP64 or QUAPI_FP32_LOG                                           */
-    int hash_merge;           /* 1: the hash-table merge, 0: the bucketed store                         */
+    int hash_merge;           /* 1: the hash-table merge, 0: a store sorted by key                      */
     int n_instances;          /* instances of a batched context, else 1                                 */
+    int store;                /* QUAPI_MERGE_DIRECT, QUAPI_MERGE_BUCKETED or QUAPI_MERGE_HASH           */
 } quapi_info_t;
 
 /* Create a context and its initial state t = 0 (one path per nonzero
@@ -133,7 +148,9 @@ typedef struct {
  * Errors: EINVAL (bad argument), EUNSUPPORTED (M > 3; merge positions 0..L-1
  * with L bits-per-point > 62 bits or a tail over 64 bits; other merge positions
  * with a history over 128 bits, a key over 62 bits or other positions over 64
- * bits), ENOMEM, EDEVICE.  *out is NULL on error. */
+ * bits; coefficients whose influence phases could reach 1e5 radians in one
+ * step, |q_a - q_b| sum_d |Im eta_d| max|q_a + q_b| >= 1e5, beyond the range
+ * of the kernels' sine and cosine), ENOMEM, EDEVICE.  *out is NULL on error. */
 int quapi_create(const quapi_params* p, quapi_ctx** out);
 
 /* Batched form: n_inst instances of the method (for instance bath parameter

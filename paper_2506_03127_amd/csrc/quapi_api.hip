@@ -14,6 +14,8 @@
 #include <vector>
 
 #include "../../include/quapi.h"
+#include "quapi_dense.h"
+#include "quapi_device.h"
 #include "quapi_host.h"
 #include "quapi_sparse.h"
 
@@ -57,6 +59,21 @@ struct quapi_ctx {
     unsigned long long* sp_cq = nullptr;
     double* sp_partials = nullptr;
     int sp_grid = 0;
+
+    // direct-mapped store (two-level systems, merge positions 0..L-1, short keys)
+    bool dense = false;
+    unsigned long long* dn_bits[2] = {nullptr, nullptr};   // [S/64] by buffer
+    unsigned long long* dn_tail[2] = {nullptr, nullptr};   // [S]
+    double2* dn_w[2] = {nullptr, nullptr};                 // [S]
+    unsigned long long dn_slots = 0;                       // S = P^L
+    unsigned int* dn_nz_word = nullptr;                    // [S/64] nonempty bitmap words ...
+    unsigned int* dn_nz_prefix = nullptr;                  // ... the groups before each ...
+    unsigned long long* dn_nz_bits = nullptr;              // ... and the word
+    unsigned int* dn_desc = nullptr;                       // [dn_max_chunks]
+    quapi_dev::DensePlan* dn_plan = nullptr;               // [2] by step parity
+    double* dn_partials = nullptr;                         // [partial_stride(4)][dn_max_chunks]
+    int dn_max_chunks = 0;
+    int dn_grid = 0;
 
     // batched form: n_inst instances (bath parameter points) in one store
     int n_inst = 1;
@@ -176,15 +193,59 @@ int upload_initial_sparse(quapi_ctx* c) {
     return hip_to_code(e);
 }
 
+// Plan step t+1 on the direct-mapped store from the groups stored after step t
+// (and reduce step t's sums when t >= 1); clears the bitmap step t+1 writes.
+int launch_dense_planner(quapi_ctx* c, int t) {
+    quapi_dev::DensePlanArgs pa;
+    pa.bits = c->dn_bits[c->cur];
+    pa.bits_next = c->dn_bits[1 - c->cur];
+    pa.n_words = (long long)(c->dn_slots / 64);
+    pa.nz_word = c->dn_nz_word;
+    pa.nz_prefix = c->dn_nz_prefix;
+    pa.nz_bits = c->dn_nz_bits;
+    pa.desc = c->dn_desc;
+    pa.plan = c->dn_plan + ((t + 1) & 1);
+    pa.plan_prev = c->dn_plan + (t & 1);
+    pa.max_chunks = c->dn_max_chunks;
+    pa.reduce_t = t;
+    pa.partials = c->dn_partials;
+    pa.rho_hist = c->d_rho;
+    pa.stats_hist = c->d_stats;
+    pa.error = c->d_error;
+    return quapi_dev::launch_dense_plan(pa, c->stream) == (int)hipSuccess ? QUAPI_OK : QUAPI_EDEVICE;
+}
+
+// t = 0 on the direct-mapped store: the initial groups at their slots, the
+// bitmap of the first buffer holding exactly them
+int upload_initial_dense(quapi_ctx* c) {
+    const size_t nw = (size_t)(c->dn_slots / 64);
+    std::vector<unsigned long long> bits(nw, 0ull);
+    const size_t n0 = c->init_key.size();
+    std::vector<unsigned long long> zero(n0 ? n0 : 1, 0ull);
+    for (size_t k = 0; k < n0; ++k) bits[c->init_key[k] / 64] |= 1ull << (c->init_key[k] % 64);
+    hipError_t e = hipMemcpyAsync(c->dn_bits[0], bits.data(), nw * 8, hipMemcpyHostToDevice, c->stream);
+    for (size_t k = 0; k < n0 && e == hipSuccess; ++k) {
+        const unsigned long long sl = c->init_key[k];
+        e = hipMemcpyAsync(c->dn_tail[0] + sl, zero.data(), 8, hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(c->dn_w[0] + sl, &c->init_w[k], 16, hipMemcpyHostToDevice, c->stream);
+    }
+    // the copies read host vectors of this frame: complete them before returning
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    return hip_to_code(e);
+}
+
 int upload_initial(quapi_ctx* c) {
     hipError_t e = hipSuccess;
     if (c->sparse) {
         if (upload_initial_sparse(c) != QUAPI_OK) e = hipErrorLaunchFailure;
+    } else if (c->dense) {
+        if (upload_initial_dense(c) != QUAPI_OK) e = hipErrorLaunchFailure;
     } else {
         e = hipMemsetAsync(c->counts[0], 0, (size_t)c->n_buckets * sizeof(unsigned int), c->stream);
     }
     const size_t n0 = c->init_key.size();
-    for (size_t j = 0; !c->sparse && j < (size_t)c->n_inst && e == hipSuccess; ++j)
+    for (size_t j = 0; !c->sparse && !c->dense && j < (size_t)c->n_inst && e == hipSuccess; ++j)
         for (size_t k = 0; k < n0 && e == hipSuccess; ++k) {
             const long long b = (long long)j * c->inst_buckets + c->init_bucket[k];
             const size_t o = (size_t)b * (size_t)c->cap;
@@ -215,7 +276,8 @@ int upload_initial(quapi_ctx* c) {
     c->t = 0;
     c->cur = 0;
     c->err = QUAPI_OK;
-    if (e == hipSuccess && !c->sparse && launch_planner(c, 0) != QUAPI_OK) e = hipErrorLaunchFailure;
+    if (e == hipSuccess && !c->sparse && !c->dense && launch_planner(c, 0) != QUAPI_OK) e = hipErrorLaunchFailure;
+    if (e == hipSuccess && c->dense && launch_dense_planner(c, 0) != QUAPI_OK) e = hipErrorLaunchFailure;
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     return hip_to_code(e);
 }
@@ -357,6 +419,53 @@ int step_sparse(quapi_ctx* c, int n_steps) {
         if (ev) (void)hipEventRecord(ev[2], c->stream);
         c->t = t;
         c->cur = 1 - c->cur;
+    }
+    return QUAPI_OK;
+}
+
+// n time steps on the direct-mapped store: the step kernel, then the planner
+// of the next step (which reduces this one's sums)
+int step_dense(quapi_ctx* c, int n_steps) {
+    quapi_dev::DenseArgs a;
+    a.nz_word = c->dn_nz_word;
+    a.nz_prefix = c->dn_nz_prefix;
+    a.nz_bits = c->dn_nz_bits;
+    a.desc = c->dn_desc;
+    a.partials = c->dn_partials;
+    a.max_chunks = c->dn_max_chunks;
+    a.tables = c->d_tables;
+    a.L = c->L;
+    a.K = c->K;
+    a.theta2 = c->theta * c->theta;
+    a.qmask = c->qbits >= 64 ? 0ull : ~((1ull << c->qbits) - 1ull);
+    a.error = c->d_error;
+    const int n = c->K + 1;
+    for (int k = 0; k < n_steps; ++k) {
+        const int t = c->t + 1;
+        a.bits_in = c->dn_bits[c->cur];
+        a.tail_in = c->dn_tail[c->cur];
+        a.w_in = c->dn_w[c->cur];
+        a.bits_out = c->dn_bits[1 - c->cur];
+        a.tail_out = c->dn_tail[1 - c->cur];
+        a.w_out = c->dn_w[1 - c->cur];
+        a.plan = c->dn_plan + (t & 1);
+        a.t = t;
+        a.coef = c->d_coef + (size_t)(std::min(t, c->K + 1) - 1) * 4 * n;
+        hipEvent_t* ev = (c->prof_on && !c->capturing && c->prof_n < c->prof_cap)
+                             ? &c->prof_ev[3 * (size_t)c->prof_n++] : nullptr;
+        if (ev && hipEventRecord(ev[0], c->stream) != hipSuccess) ev = nullptr;
+        if (quapi_dev::launch_dense_step(a, c->dn_grid, c->stream) != (int)hipSuccess) {
+            c->err = QUAPI_EDEVICE;
+            return c->err;
+        }
+        if (ev) (void)hipEventRecord(ev[1], c->stream);
+        c->t = t;
+        c->cur = 1 - c->cur;
+        if (launch_dense_planner(c, t) != QUAPI_OK) {
+            c->err = QUAPI_EDEVICE;
+            return c->err;
+        }
+        if (ev) (void)hipEventRecord(ev[2], c->stream);
     }
     return QUAPI_OK;
 }
@@ -588,6 +697,23 @@ static int create_ctx(const quapi_params* p, int n_inst, const quapi_c64* eta_al
     }
     // the batched form is built on the bucketed store (FP64, merge positions 0..L-1)
     if (batch && !contiguous) return QUAPI_EUNSUPPORTED;
+    // store: merge positions 0..L-1 of a two-level system with 5 <= L <= 13 (at most
+    // 4^13 slots of 24 B) take the direct-mapped store unless the caller asks for
+    // another; the bucketed store serves every contiguous mask, the hash table every mask
+    const int merge = p->merge;
+    if (merge < QUAPI_MERGE_AUTO || merge > QUAPI_MERGE_HASH) return QUAPI_EINVAL;
+    const bool dense_ok =
+        contiguous && !batch && M == 2 && L >= quapi_dev::kDenseMinL && L <= quapi_dev::kDenseMaxL;
+    if (merge == QUAPI_MERGE_DIRECT && !dense_ok) return QUAPI_EUNSUPPORTED;
+    if (merge == QUAPI_MERGE_BUCKETED && !contiguous) return QUAPI_EUNSUPPORTED;
+    if (merge == QUAPI_MERGE_HASH && batch) return QUAPI_EUNSUPPORTED;
+    if (merge == QUAPI_MERGE_HASH && contiguous) {
+        // the hash table takes any merge positions
+        if (K * bits > 128 || L * bits > 62 || (K - L) * bits > 64) return QUAPI_EUNSUPPORTED;
+        contiguous = false;
+    }
+    // (AUTO takes the bucketed store for merge positions 0..L-1: measured, it is still the faster)
+    const bool use_dense = dense_ok && merge == QUAPI_MERGE_DIRECT;
     const quapi_c64* const eta0 = eta_all;                // instance 0
 
     quapi_ctx* c = new (std::nothrow) quapi_ctx();
@@ -604,6 +730,7 @@ static int create_ctx(const quapi_params* p, int n_inst, const quapi_c64* eta_al
     c->dt = p->dt;
     c->theta = p->theta;
     c->sparse = !contiguous;
+    c->dense = use_dense;
     c->f32 = p->precision == QUAPI_FP32_LOG;
     c->qpos = pos;
     if (c->sparse) {
@@ -625,14 +752,14 @@ static int create_ctx(const quapi_params* p, int n_inst, const quapi_c64* eta_al
     // batched form: one planner workgroup per instance takes all of its buckets
     if (batch) max_super = std::min(max_super, (long long)quapi_dev::plan_batch_max_buckets() / P);
     int dm1 = 0;
-    while (!c->sparse && dm1 + 1 <= L - 1 && ipow(P, dm1 + 1) <= max_super) ++dm1;
+    while (!c->sparse && !c->dense && dm1 + 1 <= L - 1 && ipow(P, dm1 + 1) <= max_super) ++dm1;
     c->D = dm1 + 1;
     c->n_super = (int)ipow(P, dm1);
     c->n_inst = n_inst;
     c->batch = batch;
     c->inst_buckets = ipow(P, c->D);
     c->n_buckets = c->inst_buckets * n_inst;
-    long long cap = c->sparse ? 1 : ipow(P, L - c->D);
+    long long cap = (c->sparse || c->dense) ? 1 : ipow(P, L - c->D);
     // (max_groups counts one instance)
     if (p->max_groups > 0) cap = std::max(1ll, std::min(cap, (p->max_groups + c->inst_buckets - 1) / c->inst_buckets));
     // group indices are 32-bit: keep the whole store below 2^31 groups
@@ -695,6 +822,28 @@ static int create_ctx(const quapi_params* p, int n_inst, const quapi_c64* eta_al
         }
     }
 
+    // the kernels' sin/cos take phases below kTrigArgMax: bound every phase a
+    // child or an end-point correction can get, |ds_p| sum_d |Im c_d| max|ss|
+    {
+        double ds_max = 0.0, ss_max = 0.0;
+        for (int pp = 0; pp < P; ++pp) {
+            ds_max = std::max(ds_max, std::fabs(c->tables[TableLayout::ds(P) + pp]));
+            ss_max = std::max(ss_max, std::fabs(c->tables[TableLayout::ss(P) + pp]));
+        }
+        double worst = 0.0;
+        for (size_t set = 0; set < (size_t)(K + 1) * n_inst; ++set)
+            for (int col = 1; col <= 3; col += 2) {          // Im of the coefficients and of the corrections
+                const double* cs = c->coef.data() + set * 4 * n + (size_t)col * n;
+                double sum = 0.0;
+                for (int d = 0; d <= K; ++d) sum += std::fabs(cs[d]);
+                worst = std::max(worst, ds_max * sum * ss_max);
+            }
+        if (!(worst < quapi_dev::kTrigArgMax)) {
+            delete c;
+            return QUAPI_EUNSUPPORTED;
+        }
+    }
+
     // t = 0: one group per nonzero element of rho0 with the initial point's self term
     c->rho0.resize(2 * P);
     for (int pp = 0; pp < P; ++pp) {
@@ -733,7 +882,7 @@ static int create_ctx(const quapi_params* p, int n_inst, const quapi_c64* eta_al
         c->stream_dev = c->dev;
     }
 
-    const size_t nrec = c->sparse ? 1 : (size_t)c->n_buckets * (size_t)cap;
+    const size_t nrec = (c->sparse || c->dense) ? 1 : (size_t)c->n_buckets * (size_t)cap;
     for (int b = 0; b < 2 && rc == QUAPI_OK; ++b) {
         rc = dev_alloc(c, &c->buf[b].key, nrec);
         if (!rc) rc = dev_alloc(c, &c->buf[b].tail, nrec);
@@ -756,6 +905,22 @@ static int create_ctx(const quapi_params* p, int n_inst, const quapi_c64* eta_al
     if (!rc) rc = dev_alloc(c, &c->d_plan, 2);
     if (!rc) rc = dev_alloc(c, &c->d_chain, (size_t)P * c->max_chunks);
     if (!rc) rc = dev_alloc(c, &c->d_error, 1);
+    if (!rc && c->dense) {
+        c->dn_slots = (unsigned long long)ipow(P, L);
+        const size_t nw = (size_t)(c->dn_slots / 64);
+        c->dn_max_chunks = (int)(c->dn_slots / quapi_dev::dense_chunk_heads() + 2);
+        for (int b = 0; b < 2 && !rc; ++b) {
+            rc = dev_alloc(c, &c->dn_bits[b], nw);
+            if (!rc) rc = dev_alloc(c, &c->dn_tail[b], (size_t)c->dn_slots);
+            if (!rc) rc = dev_alloc(c, &c->dn_w[b], (size_t)c->dn_slots);
+        }
+        if (!rc) rc = dev_alloc(c, &c->dn_nz_word, nw + 1);
+        if (!rc) rc = dev_alloc(c, &c->dn_nz_prefix, nw + 1);
+        if (!rc) rc = dev_alloc(c, &c->dn_nz_bits, nw + 1);
+        if (!rc) rc = dev_alloc(c, &c->dn_desc, (size_t)c->dn_max_chunks);
+        if (!rc) rc = dev_alloc(c, &c->dn_plan, 2);
+        if (!rc) rc = dev_alloc(c, &c->dn_partials, (size_t)c->dn_max_chunks * quapi_dev::partial_stride(4));
+    }
     if (!rc && c->sparse) {
         // capacity: max_groups, else every key of the merge positions up to 2^21 groups;
         // the table holds twice the children a step can insert
@@ -818,6 +983,16 @@ static int create_ctx(const quapi_params* p, int n_inst, const quapi_c64* eta_al
         quapi_destroy(c);
         return QUAPI_EDEVICE;
     }
+    if (c->dense) {
+        // persistent workgroups, as many as are resident (their chunks never wait on one another)
+        c->dn_grid = quapi_dev::dense_step_grid(std::max(ncu, 1));
+        if (per_cu > 0) c->dn_grid = std::min(c->dn_grid, per_cu * std::max(ncu, 1));
+        if (c->dn_grid < 1 ||
+            hipMemsetAsync(c->dn_plan, 0, 2 * sizeof(quapi_dev::DensePlan), c->stream) != hipSuccess) {
+            quapi_destroy(c);
+            return QUAPI_EDEVICE;
+        }
+    }
     if (c->sparse) {
         c->sp_grid = 4 * std::max(ncu, 1);
         if (dev_alloc(c, &c->sp_partials, (size_t)c->sp_grid * quapi_dev::partial_stride(P)) != QUAPI_OK) {
@@ -854,6 +1029,7 @@ int quapi_step(quapi_ctx* c, int n_steps) {
     int rc = grow_history(c, c->t + n_steps);
     if (rc) return rc;
     if (c->sparse) return step_sparse(c, n_steps);
+    if (c->dense) return step_dense(c, n_steps);
     StepArgs a;
     a.cap = c->cap;
     a.P = c->P;
@@ -1131,6 +1307,38 @@ int quapi_batch_groups(quapi_ctx* c, int inst, long long cap, unsigned char* his
         }
         return QUAPI_OK;
     }
+    if (c->dense) {
+        const size_t S = (size_t)c->dn_slots;
+        std::vector<unsigned long long> bits(S / 64);
+        hipError_t e = hipMemcpy(bits.data(), c->dn_bits[c->cur], bits.size() * 8, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_to_code(e);
+        long long n = 0;
+        for (unsigned long long b : bits) n += __builtin_popcountll(b);
+        *n_out = n;
+        if (cap == 0 || n == 0) return QUAPI_OK;
+        std::vector<unsigned long long> tl(S);
+        std::vector<double2> ww(S);
+        e = hipMemcpy(tl.data(), c->dn_tail[c->cur], S * 8, hipMemcpyDeviceToHost);
+        if (e == hipSuccess) e = hipMemcpy(ww.data(), c->dn_w[c->cur], S * 16, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_to_code(e);
+        const unsigned long long dm = (1ull << c->bits) - 1;
+        long long written = 0;
+        for (size_t wd = 0; wd < bits.size() && written < cap; ++wd)
+            for (unsigned long long b = bits[wd]; b && written < cap; b &= b - 1) {
+                const size_t o = wd * 64 + (size_t)__builtin_ctzll(b);
+                unsigned char* row = hist + (size_t)written * c->K;
+                for (int j = 0; j < c->K; ++j) {
+                    unsigned long long d;
+                    if (j < c->L) d = ((unsigned long long)o >> (c->bits * (c->L - 1 - j))) & dm;
+                    else d = (tl[o] >> (c->bits * (j - c->L))) & dm;
+                    row[j] = (unsigned char)d;
+                }
+                w[written].re = ww[o].x;
+                w[written].im = ww[o].y;
+                ++written;
+            }
+        return QUAPI_OK;
+    }
     // the instance's buckets
     const size_t nb = (size_t)c->inst_buckets, b0 = (size_t)inst * nb;
     std::vector<unsigned int> cnt(nb);
@@ -1184,11 +1392,12 @@ int quapi_info(quapi_ctx* c, quapi_info_t* out) {
     out->K = c->K;
     out->L = c->L;
     out->bits_per_point = c->bits;
-    out->record_bytes = c->sparse ? (c->f32 ? 8 : 16) + 8 * c->sp_hw : 32;
-    out->capacity = c->sparse ? c->sp_cap : c->inst_buckets * c->cap;
+    out->record_bytes = c->sparse ? (c->f32 ? 8 : 16) + 8 * c->sp_hw : c->dense ? 24 : 32;
+    out->capacity = c->sparse ? c->sp_cap : c->dense ? (long long)c->dn_slots : c->inst_buckets * c->cap;
     out->device_bytes = c->device_bytes;
     out->precision = c->f32 ? QUAPI_FP32_LOG : QUAPI_FP64;
     out->hash_merge = c->sparse ? 1 : 0;
+    out->store = c->sparse ? QUAPI_MERGE_HASH : c->dense ? QUAPI_MERGE_DIRECT : QUAPI_MERGE_BUCKETED;
     out->n_instances = c->n_inst;
     return QUAPI_OK;
 }

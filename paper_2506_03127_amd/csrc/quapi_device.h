@@ -88,6 +88,103 @@ __device__ inline void st_relaxed(unsigned long long* p, unsigned long long v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// ---------------------------------------------------------------- FP64 exp and sincos
+// The influence factors need exp and sin/cos of one FP64 argument per child
+// pair.  The general library sin/cos also carries the reduction for huge
+// arguments (Payne-Hanek), which the compiler evaluates beside the common path
+// when it turns their branch into selects.  These use Cody-Waite reduction and
+// truncated Taylor series instead, each within a few ulp of the correctly
+// rounded value: exp for every argument (clamped where the result under- or
+// overflows anyway), sin/cos for |y| < kTrigArgMax.  The host checks before a
+// run that no phase the coefficient table can produce reaches that bound.
+//
+// Split constants: ln 2 = kLn2Hi + kLn2Lo and pi/2 = kPio2A + kPio2B + kPio2C,
+// each leading part holding at most 33 significant bits, so that k times it is
+// exact for the k these arguments take.
+constexpr double kLog2e = 1.4426950408889634;           // 1 / ln 2
+constexpr double kLn2Hi = 0.69314718060195446;          // 0x3fe62e42ff000000
+constexpr double kLn2Lo = -4.2009150726810846e-11;      // ln 2 - kLn2Hi
+constexpr double kTwoOverPi = 0.63661977236758138;
+constexpr double kPio2A = 1.5707963267341256;           // 0x3ff921fb54400000
+constexpr double kPio2B = 6.077100506303966e-11;        // 0x3dd0b4611a600000
+constexpr double kPio2C = 2.0222662487959506e-21;       // pi/2 - kPio2A - kPio2B
+constexpr double kTrigArgMax = 1.0e5;                   // sincos_fast: |y| below this
+
+// exp(r) for |r| <= ln2/2 by its Taylor series through r^13 (the next term is
+// below 1e-17 relative there), coefficients 1/n!.
+__host__ __device__ inline double exp_poly(double r) {
+    double p = 1.0 / 6227020800.0;                       // 1/13!
+    p = __builtin_fma(p, r, 1.0 / 479001600.0);
+    p = __builtin_fma(p, r, 1.0 / 39916800.0);
+    p = __builtin_fma(p, r, 1.0 / 3628800.0);
+    p = __builtin_fma(p, r, 1.0 / 362880.0);
+    p = __builtin_fma(p, r, 1.0 / 40320.0);
+    p = __builtin_fma(p, r, 1.0 / 5040.0);
+    p = __builtin_fma(p, r, 1.0 / 720.0);
+    p = __builtin_fma(p, r, 1.0 / 120.0);
+    p = __builtin_fma(p, r, 1.0 / 24.0);
+    p = __builtin_fma(p, r, 1.0 / 6.0);
+    p = __builtin_fma(p, r, 0.5);
+    p = __builtin_fma(p, r, 1.0);
+    return __builtin_fma(p, r, 1.0);
+}
+
+// exp(x) = 2^k exp(r), k = rint(x / ln 2), r = x - k ln 2 (Cody-Waite).
+__host__ __device__ inline double exp_reduced(double x) {
+    const double k = __builtin_rint(x * kLog2e);
+    double r = __builtin_fma(-k, kLn2Hi, x);
+    r = __builtin_fma(-k, kLn2Lo, r);
+    return __builtin_ldexp(exp_poly(r), (int)k);
+}
+
+// exp for any argument: below -746 the result is zero and above 710 infinite,
+// which the clamped arguments still give
+__host__ __device__ inline double exp_fast(double x) {
+    return exp_reduced(__builtin_fmin(__builtin_fmax(x, -746.0), 710.0));
+}
+
+// sin and cos of r, |r| <= pi/4: Taylor series through r^17 and r^16 (the next
+// terms are below 1e-17 relative), Horner in z = r^2, coefficients 1/n!.
+__host__ __device__ inline void sincos_poly(double r, double& sn, double& cs) {
+    const double z = r * r;
+    double ps = -1.0 / 355687428096000.0;                // -1/17!  (times r^17)
+    ps = __builtin_fma(ps, z, 1.0 / 1307674368000.0);    //  1/15!
+    ps = __builtin_fma(ps, z, -1.0 / 6227020800.0);      // -1/13!
+    ps = __builtin_fma(ps, z, 1.0 / 39916800.0);         //  1/11!
+    ps = __builtin_fma(ps, z, -1.0 / 362880.0);          // -1/9!
+    ps = __builtin_fma(ps, z, 1.0 / 5040.0);             //  1/7!
+    ps = __builtin_fma(ps, z, -1.0 / 120.0);             // -1/5!
+    ps = __builtin_fma(ps, z, 1.0 / 6.0);                //  1/3!
+    sn = __builtin_fma(-(r * z), ps, r);                 // r - r^3 (1/3! - z/5! + ...)
+    double pc = 1.0 / 20922789888000.0;                  //  1/16!
+    pc = __builtin_fma(pc, z, -1.0 / 87178291200.0);     // -1/14!
+    pc = __builtin_fma(pc, z, 1.0 / 479001600.0);        //  1/12!
+    pc = __builtin_fma(pc, z, -1.0 / 3628800.0);         // -1/10!
+    pc = __builtin_fma(pc, z, 1.0 / 40320.0);            //  1/8!
+    pc = __builtin_fma(pc, z, -1.0 / 720.0);             // -1/6!
+    pc = __builtin_fma(pc, z, 1.0 / 24.0);               //  1/4!
+    pc = __builtin_fma(pc, z, -0.5);                     // -1/2!
+    cs = __builtin_fma(pc, z, 1.0);
+}
+
+__host__ __device__ inline void sincos_reduced(double y, double& sn, double& cs) {
+    const double k = __builtin_rint(y * kTwoOverPi);
+    double r = __builtin_fma(-k, kPio2A, y);
+    r = __builtin_fma(-k, kPio2B, r);
+    r = __builtin_fma(-k, kPio2C, r);
+    double s0, c0;
+    sincos_poly(r, s0, c0);
+    // quadrant q of y = q pi/2 + r: (sin, cos) = (s, c), (c, -s), (-s, -c), (-c, s)
+    const int q = (int)k & 3;
+    const double a = (q & 1) ? c0 : s0;
+    const double b = (q & 1) ? s0 : c0;
+    sn = (q & 2) ? -a : a;
+    cs = ((q + 1) & 2) ? -b : b;
+}
+
+// |y| < kTrigArgMax (checked on the host for every phase of a run)
+__device__ inline void sincos_fast(double y, double* sn, double* cs) { sincos_reduced(y, *sn, *cs); }
+
 // The error word holds (failing step << 4) | code; the first error wins.
 __device__ inline void raise_error(unsigned int* err, int t, unsigned int code) {
     atomicCAS(err, 0u, ((unsigned int)t << 4) | code);

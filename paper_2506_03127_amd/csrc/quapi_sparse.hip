@@ -367,11 +367,11 @@ __global__ __launch_bounds__(kSparseThreads) void sparse_expand(const SparseArgs
                 const double D = ds[1], Sg = ss[1];
                 const double x = D * A, y = D * __builtin_fma(cim[0], Sg, B);
                 const double xc = D * Ac, yc = D * __builtin_fma(dim[0], Sg, Bc);
-                const double ex = exp(x), exc = exp(xc);
+                const double ex = exp_fast(x), exc = exp_fast(xc);
                 const double iex = recip(ex), iexc = recip(exc);
                 double sy, cy, syc, cyc;
-                sincos(y, &sy, &cy);
-                sincos(yc, &syc, &cyc);
+                sincos_fast(y, &sy, &cy);
+                sincos_fast(yc, &syc, &cyc);
                 const double e0 = e0f0[0], f0 = e0f0[1];
                 er1 = e0 * iex * cy;  ei1 = -(e0 * iex * sy);
                 er2 = e0 * ex * cy;   ei2 = e0 * ex * sy;
@@ -407,14 +407,14 @@ __global__ __launch_bounds__(kSparseThreads) void sparse_expand(const SparseArgs
                     } else {
                         const double dsp = ds[p], ssp = ss[p];
                         if (dsp != 0.0) {
-                            const double e = exp(-dsp * (cre[0] * dsp + A));
+                            const double e = exp_fast(-dsp * (cre[0] * dsp + A));
                             double sn, cs2;
-                            sincos(-dsp * (cim[0] * ssp + B), &sn, &cs2);
+                            sincos_fast(-dsp * (cim[0] * ssp + B), &sn, &cs2);
                             er = e * cs2;
                             ei = e * sn;
-                            const double f = exp(-dsp * (dre[0] * dsp + Ac));
+                            const double f = exp_fast(-dsp * (dre[0] * dsp + Ac));
                             double fs, fc;
-                            sincos(-dsp * (dim[0] * ssp + Bc), &fs, &fc);
+                            sincos_fast(-dsp * (dim[0] * ssp + Bc), &fs, &fc);
                             fr = f * fc;
                             fi = f * fs;
                         }

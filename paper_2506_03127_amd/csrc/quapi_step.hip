@@ -813,11 +813,11 @@ __global__ __launch_bounds__(kThreads, P == 4 ? 4 : 1) void step_kernel(const St
                 const double D = s.ds[1], Sg = s.ss[1];
                 const double x = D * A, y = D * __builtin_fma(s.cim[0], Sg, B);
                 const double xc = D * Ac, yc = D * __builtin_fma(s.dim[0], Sg, Bc);
-                const double ex = exp(x), exc = exp(xc);
+                const double ex = exp_fast(x), exc = exp_fast(xc);
                 const double iex = recip(ex), iexc = recip(exc);
                 double sy, cy, syc, cyc;
-                sincos(y, &sy, &cy);
-                sincos(yc, &syc, &cyc);
+                sincos_fast(y, &sy, &cy);
+                sincos_fast(yc, &syc, &cyc);
                 const double e0 = s.e0, f0 = s.f0;    // exp(-D^2 Re c_0), exp(-D^2 Re delta_0)
                 er[0] = 1.0; ei[0] = 0.0; fr[0] = 1.0; fi[0] = 0.0;
                 er[3] = 1.0; ei[3] = 0.0; fr[3] = 1.0; fi[3] = 0.0;
@@ -831,14 +831,14 @@ __global__ __launch_bounds__(kThreads, P == 4 ? 4 : 1) void step_kernel(const St
                     const double dsp = s.ds[p], ssp = s.ss[p];
                     er[p] = 1.0; ei[p] = 0.0; fr[p] = 1.0; fi[p] = 0.0;
                     if (dsp != 0.0) {
-                        const double e = exp(-dsp * (s.cre[0] * dsp + A));
+                        const double e = exp_fast(-dsp * (s.cre[0] * dsp + A));
                         double sn, cs2;
-                        sincos(-dsp * (s.cim[0] * ssp + B), &sn, &cs2);
+                        sincos_fast(-dsp * (s.cim[0] * ssp + B), &sn, &cs2);
                         er[p] = e * cs2;
                         ei[p] = e * sn;
-                        const double f = exp(-dsp * (s.dre[0] * dsp + Ac));
+                        const double f = exp_fast(-dsp * (s.dre[0] * dsp + Ac));
                         double fs, fc;
-                        sincos(-dsp * (s.dim[0] * ssp + Bc), &fs, &fc);
+                        sincos_fast(-dsp * (s.dim[0] * ssp + Bc), &fs, &fc);
                         fr[p] = f * fc;
                         fi[p] = f * fs;
                     }

@@ -27,6 +27,10 @@ QUAPI_PRE = 0
 QUAPI_POST = 1
 QUAPI_FP64 = 0
 QUAPI_FP32_LOG = 1
+QUAPI_MERGE_AUTO = 0
+QUAPI_MERGE_DIRECT = 1
+QUAPI_MERGE_BUCKETED = 2
+QUAPI_MERGE_HASH = 3
 
 
 class c64(ctypes.Structure):
@@ -39,7 +43,7 @@ class quapi_params(ctypes.Structure):
                 ("mask", ctypes.c_void_p), ("n_mask", ctypes.c_int), ("theta", ctypes.c_double),
                 ("rho0", ctypes.c_void_p), ("mode", ctypes.c_int), ("qbits", ctypes.c_int),
                 ("max_groups", ctypes.c_longlong), ("max_steps", ctypes.c_int),
-                ("stream", ctypes.c_void_p), ("precision", ctypes.c_int)]
+                ("stream", ctypes.c_void_p), ("precision", ctypes.c_int), ("merge", ctypes.c_int)]
 
 
 class quapi_stepstat_t(ctypes.Structure):
@@ -52,7 +56,8 @@ class quapi_info_t(ctypes.Structure):
     _fields_ = [("M", ctypes.c_int), ("P", ctypes.c_int), ("K", ctypes.c_int), ("L", ctypes.c_int),
                 ("bits_per_point", ctypes.c_int), ("record_bytes", ctypes.c_int),
                 ("capacity", ctypes.c_longlong), ("device_bytes", ctypes.c_size_t),
-                ("precision", ctypes.c_int), ("hash_merge", ctypes.c_int), ("n_instances", ctypes.c_int)]
+                ("precision", ctypes.c_int), ("hash_merge", ctypes.c_int), ("n_instances", ctypes.c_int),
+                ("store", ctypes.c_int)]
 
 
 class quapi_bath(ctypes.Structure):
@@ -143,7 +148,7 @@ def _c128(a, shape=None):
 
 # ------------------------------------------------------------------ C ABI, one to one
 def _params(H, q, dt, dk_max, eta, rho0, mask, theta, mode, qbits, max_groups, max_steps, stream,
-            precision):
+            precision, merge=QUAPI_MERGE_AUTO):
     """quapi_params and the arrays its pointers refer to (kept alive by the caller)."""
     H = _c128(H)
     M = H.shape[0]
@@ -168,26 +173,27 @@ def _params(H, q, dt, dk_max, eta, rho0, mask, theta, mode, qbits, max_groups, m
     p.max_steps = int(max_steps)
     p.stream = None if stream is None else int(stream)
     p.precision = int(precision)
+    p.merge = int(merge)
     return p, (H, q, eta, rho0, m)
 
 
 def quapi_create(H, q, dt, dk_max, eta, rho0, mask=None, theta=0.0, mode=QUAPI_PRE, qbits=-1,
-                 max_groups=0, max_steps=0, stream=None, precision=QUAPI_FP64) -> int:
+                 max_groups=0, max_steps=0, stream=None, precision=QUAPI_FP64, merge=QUAPI_MERGE_AUTO) -> int:
     p, keep = _params(H, q, dt, dk_max, eta, rho0, mask, theta, mode, qbits, max_groups, max_steps,
-                      stream, precision)
+                      stream, precision, merge)
     h = ctypes.c_void_p()
     _check(lib().quapi_create(ctypes.byref(p), ctypes.byref(h)), "quapi_create")
     return h.value
 
 
 def quapi_create_batch(H, q, dt, dk_max, etas, rho0, mask=None, theta=0.0, mode=QUAPI_PRE, qbits=-1,
-                       max_groups=0, max_steps=0, stream=None, H_batch=None) -> int:
+                       max_groups=0, max_steps=0, stream=None, H_batch=None, merge=QUAPI_MERGE_AUTO) -> int:
     """etas: (n_inst, 3, dk_max + 1) complex, one eta table per instance; H_batch:
     (n_inst, M, M) complex, one Hamiltonian per instance, or None (H for all)."""
     etas = _c128(etas)
     etas = etas.reshape(-1, 3, int(dk_max) + 1)
     p, keep = _params(H, q, dt, dk_max, None, rho0, mask, theta, mode, qbits, max_groups, max_steps,
-                      stream, QUAPI_FP64)
+                      stream, QUAPI_FP64, merge)
     hb = None if H_batch is None else _c128(H_batch).reshape(etas.shape[0], p.M, p.M)
     h = ctypes.c_void_p()
     _check(lib().quapi_create_batch(ctypes.byref(p), int(etas.shape[0]), etas.ctypes.data,

@@ -146,6 +146,10 @@ int main() {
         c3.p.mask = c3.mask.data();
         c3.p.n_mask = 3;
         expect(create(c3.p) == QUAPI_EUNSUPPORTED, "three levels, history over 128 bits");
+        // phases beyond the range of the kernels' sine and cosine
+        Case cp(2, 8);
+        for (auto& z : cp.eta) z.im = 1e4;
+        expect(create(cp.p) == QUAPI_EUNSUPPORTED, "phase bound");
         // batched create
         quapi_ctx* bo = nullptr;
         expect(quapi_create_batch(&c.p, 0, c.eta.data(), nullptr, &bo) == QUAPI_EINVAL && !bo, "batch n = 0");

@@ -75,8 +75,8 @@ def test_traffic_from_counters_and_the_source_hash(tmp_path, monkeypatch):
 
 def test_every_workload_names_existing_sources():
     for name in bench.WORKLOADS:
-        for prec in ("fp64", "fp32"):
-            spec = bench.workload_spec(name, prec)
+        for prec, store in (("fp64", "bucketed"), ("fp64", "direct"), ("fp64", "hash"), ("fp32", "hash")):
+            spec = bench.workload_spec(name, prec, store)
             for f in spec["sources"]:
                 assert os.path.exists(os.path.join(ROOT, f)), (name, prec, f)
             assert len(bench.kernel_source_hash(spec)) == 64

@@ -40,7 +40,8 @@ def _singles_like(Q, monkeypatch, g, wl, etas, K, mode, **kw):
     """Lone contexts with the batch's bucket depth (the batched form caps a
     super-bucket count per instance at 4096 / P)."""
     monkeypatch.setenv("QUAPI_MAX_SUPER", str(4096 // (wl.M * wl.M)))
-    return [Q.Propagator(wl.H, wl.q, wl.dt, K, e, wl.rho0, mask=wl.mask, theta=wl.theta, mode=mode, **kw)
+    return [Q.Propagator(wl.H, wl.q, wl.dt, K, e, wl.rho0, mask=wl.mask, theta=wl.theta, mode=mode,
+                         merge=Q.QUAPI_MERGE_BUCKETED, **kw)
             for e in etas]
 
 
@@ -203,7 +204,8 @@ def test_batch_per_instance_hamiltonians(Q, monkeypatch):
     print(f"[batch] 4 instances with their own H_S K={K} n={n}", flush=True)
     g = Q.BatchPropagator(wl.H, wl.q, wl.dt, K, etas, wl.rho0, mask=wl.mask, theta=wl.theta, H_batch=Hs)
     monkeypatch.setenv("QUAPI_MAX_SUPER", "1024")
-    singles = [Q.Propagator(Hs[j], wl.q, wl.dt, K, etas[j], wl.rho0, mask=wl.mask, theta=wl.theta)
+    singles = [Q.Propagator(Hs[j], wl.q, wl.dt, K, etas[j], wl.rho0, mask=wl.mask, theta=wl.theta,
+                            merge=Q.QUAPI_MERGE_BUCKETED)
                for j in range(4)]
     g.step(n)
     for s in singles:

@@ -471,3 +471,54 @@ def test_contexts_on_caller_streams_step_side_by_side(Q, eta_cache):
         hc, wc = c.groups()
         hl, wlone = lone.groups()
         assert np.array_equal(hc, hl) and np.array_equal(wc, wlone)
+
+
+# ------------------------------------------------------------------ the three stores
+@pytest.mark.parametrize("store", ["DIRECT", "BUCKETED", "HASH"])
+@pytest.mark.parametrize("mode,K,mask,theta,n", [
+    ("pre", 12, (0, 1, 2, 3, 4, 5, 6), 1e-7, 60),     # L = 6
+    ("post", 10, (0, 1, 2, 3, 4, 5), 1e-8, 40),       # L = 6
+])
+def test_every_store_matches_the_oracle(Q, eta_cache, store, mode, K, mask, theta, n):
+    """The direct-mapped store, the bucketed store and the hash table on the
+    same contiguous masks: each against the oracle (rho, counters, groups)."""
+    wl = W.structured_bath(K=K)
+    eta = eta_cache(wl, K)
+    merge = getattr(Q, f"QUAPI_MERGE_{store}")
+    o, g = run_both(Q, wl.H, wl.q, wl.dt, K, eta, wl.rho0, n, mode=mode, mask=mask, theta=theta, merge=merge)
+    assert Q.quapi_info(g.ctx)["store"] == merge
+    assert ambiguous(o, n) == 0
+    assert_rho(o, g, n)
+    assert_stats(o, g, n)
+    assert_groups(o, g)
+
+
+def test_direct_store_full_memory_spin_boson(Q, eta_cache):
+    """Exact iQUAPI (post-merging on every lag, K = 8, no filter) on the
+    direct-mapped store: 4^8 slots, all of them holding a group at steady state."""
+    wl = W.spin_boson_ohmic(mode="post")
+    eta = eta_cache(wl)
+    o, g = run_both(Q, wl.H, wl.q, wl.dt, wl.K, eta, wl.rho0, wl.n_steps, mode="post",
+                    merge=Q.QUAPI_MERGE_DIRECT)
+    assert Q.quapi_info(g.ctx)["store"] == Q.QUAPI_MERGE_DIRECT
+    assert_rho(o, g, wl.n_steps)
+    assert_stats(o, g, wl.n_steps)
+    if ambiguous(o, wl.n_steps) == 0:
+        assert_groups(o, g)
+    assert len(g.groups()[0]) == 4 ** 8
+
+
+def test_store_requests_that_do_not_apply(Q, eta_cache):
+    wl = W.structured_bath(K=12)
+    eta = eta_cache(wl, 12)
+    # the direct-mapped store needs merge positions 0..L-1 with L >= 5
+    for mask in ((0, 1, 2, 3), (0, 1, 2, 3, 4, 5, 9)):
+        with pytest.raises(Q.QuapiError) as e:
+            Q.Propagator(wl.H, wl.q, wl.dt, 12, eta, wl.rho0, mask=mask, merge=Q.QUAPI_MERGE_DIRECT)
+        assert e.value.code == Q.QUAPI_EUNSUPPORTED
+    with pytest.raises(Q.QuapiError) as e:
+        Q.Propagator(wl.H, wl.q, wl.dt, 12, eta, wl.rho0, mask=(0, 1, 2, 5), merge=Q.QUAPI_MERGE_BUCKETED)
+    assert e.value.code == Q.QUAPI_EUNSUPPORTED
+    with pytest.raises(Q.QuapiError) as e:
+        Q.Propagator(wl.H, wl.q, wl.dt, 12, eta, wl.rho0, mask=(0, 1, 2, 5), merge=7)
+    assert e.value.code == Q.QUAPI_EINVAL
