@@ -268,6 +268,25 @@ int quapi_profile_end(quapi_ctx* c, int cap, double* step_ms, double* plan_ms, i
 /* Free the context and its device memory (synchronises first).  NULL is a no-op. */
 void quapi_destroy(quapi_ctx* c);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): the propagation of
+ * quapi_create + quapi_step(n_steps) on the direct-mapped store
+ * (QUAPI_MERGE_DIRECT) as one call that allocates nothing.  Every buffer of the
+ * run lives in one 64 MiB file-scope device array that each device holds
+ * until the process ends; the host tables reach the device as kernel
+ * arguments.  Enqueues on p->stream (NULL: the null stream) and returns
+ * without waiting; rho_out is a caller-owned DEVICE buffer of
+ * (n_steps+1)*M*M quapi_c64, filled with rho(0..n_steps) when the stream
+ * reaches the end of the run.  The results equal those of a context created
+ * with merge = QUAPI_MERGE_DIRECT.  Calls that overlap on one device share the
+ * array and race: order them (one stream, or events).
+ * Takes M = 2, FP64, dk_max <= 40, merge positions 0..L-1 with 6 <= L <= 10,
+ * p->merge AUTO or DIRECT; p->max_groups and p->max_steps are not read.
+ * Errors: EINVAL (bad argument, as quapi_create), EUNSUPPORTED (a problem
+ * outside that range), ENOMEM (the run needs more than the 64 MiB array:
+ * about 48 B per slot of 4^L plus 48 B per step), EDEVICE. */
+int quapi_run_static(const quapi_params* p, int n_steps, quapi_c64* rho_out);
+
 /* ---------------------------------------------------------------- host utilities */
 
 /* Spectral density of eq. SD as an Ohmic part plus Brownian-oscillator peaks:

@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libquapi.so")
-SOURCES = ["quapi_api.hip", "quapi_step.hip", "quapi_dense.hip", "quapi_sparse.hip", "quapi_mlp.hip", "host_math.cpp"]
+SOURCES = ["quapi_api.hip", "quapi_step.hip", "quapi_dense.hip", "quapi_static.hip", "quapi_sparse.hip", "quapi_mlp.hip",
+           "host_math.cpp"]
 ARCH = os.environ.get("QUAPI_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

@@ -33,14 +33,16 @@
 namespace quapi_host {
 
 // ------------------------------------------------------------------ Jacobi
-// Eigen-decomposition of a real symmetric n x n matrix A (row-major, destroyed).
-// On return d[k] are the eigenvalues and column k of V the eigenvectors.
-static void jacobi_symmetric(std::vector<double>& A, int n, std::vector<double>& d,
-                             std::vector<double>& V) {
-    V.assign(n * n, 0.0);
+// Eigen-decomposition of a real symmetric n x n matrix A (row-major, destroyed),
+// n <= kJacobiMax.  On return d[k] are the eigenvalues and column k of V the
+// eigenvectors.  Works in the caller's arrays: no heap memory.
+constexpr int kJacobiMax = 16;
+
+static void jacobi_symmetric(double* A, int n, double* d, double* V) {
+    for (int i = 0; i < n * n; ++i) V[i] = 0.0;
     for (int i = 0; i < n; ++i) V[i * n + i] = 1.0;
     double scale = 0.0;
-    for (double x : A) scale = std::max(scale, std::fabs(x));
+    for (int i = 0; i < n * n; ++i) scale = std::max(scale, std::fabs(A[i]));
     if (scale == 0.0) scale = 1.0;
     for (int sweep = 0; sweep < 100; ++sweep) {
         double off = 0.0;
@@ -74,7 +76,6 @@ static void jacobi_symmetric(std::vector<double>& A, int n, std::vector<double>&
             }
         }
     }
-    d.resize(n);
     for (int i = 0; i < n; ++i) d[i] = A[i * n + i];
 }
 
@@ -90,9 +91,11 @@ bool hermitian_ok(int M, const double* H /* 2*M*M */) {
     return true;
 }
 
+// U = exp(-i H dt) for M <= 8, from the real symmetric 2M x 2M form of H
+// (no heap memory)
 void propagator(int M, const double* H, double dt, double* U /* 2*M*M */) {
     const int n = 2 * M;
-    std::vector<double> S(n * n), d, V;
+    double S[kJacobiMax * kJacobiMax] = {}, d[kJacobiMax], V[kJacobiMax * kJacobiMax];
     for (int i = 0; i < M; ++i)
         for (int j = 0; j < M; ++j) {
             const double re = H[2 * (i * M + j)], im = H[2 * (i * M + j) + 1];

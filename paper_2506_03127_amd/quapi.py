@@ -202,6 +202,16 @@ def quapi_create_batch(H, q, dt, dk_max, etas, rho0, mask=None, theta=0.0, mode=
     return h.value
 
 
+def quapi_run_static(H, q, dt, dk_max, eta, rho0, n_steps: int, rho_out_ptr: int, mask=None, theta=0.0,
+                     mode=QUAPI_PRE, qbits=-1, stream=None):
+    """The propagation with no device allocation (see include/quapi.h): rho(0..n_steps)
+    into the device buffer at rho_out_ptr ((n_steps+1) * M * M complex128), enqueued on
+    stream; returns without waiting."""
+    p, keep = _params(H, q, dt, dk_max, eta, rho0, mask, theta, mode, qbits, 0, 0, stream, QUAPI_FP64)
+    _check(lib().quapi_run_static(ctypes.byref(p), int(n_steps), ctypes.c_void_p(int(rho_out_ptr))),
+           "quapi_run_static")
+
+
 def quapi_step(ctx, n_steps: int):
     _check(lib().quapi_step(ctx, int(n_steps)), "quapi_step")
 
