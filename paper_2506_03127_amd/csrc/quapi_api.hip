@@ -74,6 +74,8 @@ struct quapi_ctx {
     double* dn_partials = nullptr;                         // [partial_stride(4)][dn_max_chunks]
     int dn_max_chunks = 0;
     int dn_grid = 0;
+    unsigned long long* dn_agg = nullptr;                  // [kDenseMaxRegions] planner region totals
+    unsigned int dn_epoch = 0;                             // tag of the last planner launch
 
     // batched form: n_inst instances (bath parameter points) in one store
     int n_inst = 1;
@@ -209,9 +211,14 @@ int launch_dense_planner(quapi_ctx* c, int t) {
     pa.max_chunks = c->dn_max_chunks;
     pa.reduce_t = t;
     pa.partials = c->dn_partials;
+    pa.n_parts = c->dn_grid;
     pa.rho_hist = c->d_rho;
     pa.stats_hist = c->d_stats;
     pa.error = c->d_error;
+    pa.agg = c->dn_agg;
+    c->dn_epoch = (c->dn_epoch + 1u) & 0xffffffu;
+    if (c->dn_epoch == 0u) c->dn_epoch = 1u;             // 0 is the cleared buffer's tag
+    pa.epoch = c->dn_epoch;
     return quapi_dev::launch_dense_plan(pa, c->stream) == (int)hipSuccess ? QUAPI_OK : QUAPI_EDEVICE;
 }
 
@@ -919,7 +926,7 @@ static int create_ctx(const quapi_params* p, int n_inst, const quapi_c64* eta_al
         if (!rc) rc = dev_alloc(c, &c->dn_nz_bits, nw + 1);
         if (!rc) rc = dev_alloc(c, &c->dn_desc, (size_t)c->dn_max_chunks);
         if (!rc) rc = dev_alloc(c, &c->dn_plan, 2);
-        if (!rc) rc = dev_alloc(c, &c->dn_partials, (size_t)c->dn_max_chunks * quapi_dev::partial_stride(4));
+        if (!rc) rc = dev_alloc(c, &c->dn_agg, (size_t)quapi_dev::kDenseMaxRegions);
     }
     if (!rc && c->sparse) {
         // capacity: max_groups, else every key of the merge positions up to 2^21 groups;
@@ -988,7 +995,9 @@ static int create_ctx(const quapi_params* p, int n_inst, const quapi_c64* eta_al
         c->dn_grid = quapi_dev::dense_step_grid(std::max(ncu, 1));
         if (per_cu > 0) c->dn_grid = std::min(c->dn_grid, per_cu * std::max(ncu, 1));
         if (c->dn_grid < 1 ||
-            hipMemsetAsync(c->dn_plan, 0, 2 * sizeof(quapi_dev::DensePlan), c->stream) != hipSuccess) {
+            dev_alloc(c, &c->dn_partials, (size_t)c->dn_grid * quapi_dev::partial_stride(4)) != QUAPI_OK ||
+            hipMemsetAsync(c->dn_plan, 0, 2 * sizeof(quapi_dev::DensePlan), c->stream) != hipSuccess ||
+            hipMemsetAsync(c->dn_agg, 0, quapi_dev::kDenseMaxRegions * 8, c->stream) != hipSuccess) {
             quapi_destroy(c);
             return QUAPI_EDEVICE;
         }

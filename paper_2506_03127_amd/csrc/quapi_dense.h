@@ -21,10 +21,11 @@ namespace quapi_dev {
 // word holding each chunk's first group.
 constexpr int kDenseThreads = 256;             // threads per chunk = parents loaded per chunk
 constexpr int kDenseMinL = 6;                  // 4^L slots; short keys take the bucketed store
-constexpr int kDenseMaxL = 12;                 // 4^12 slots (the planner's reach)
-constexpr int kDensePlanThreads = 1024;
+constexpr int kDenseMaxL = 12;                 // 4^12 slots: 64 planner regions
+constexpr int kDensePlanThreads = 256;
 constexpr int kDensePlanPer = 16;              // bitmap words per planner thread
-constexpr int kDenseRegion = kDensePlanThreads * kDensePlanPer;
+constexpr int kDenseRegion = kDensePlanThreads * kDensePlanPer;   // words per planner workgroup
+constexpr int kDenseMaxRegions = 64;           // the planner's regions, all resident at once
 
 struct DensePlan {
     unsigned int n_groups;      // groups stored (input of the planned step)
@@ -45,7 +46,7 @@ struct DenseArgs {
     const unsigned long long* nz_bits;   // ... and the word itself
     const unsigned int* desc;            // [n_chunks] rank of the word holding the chunk's first group
     const DensePlan* plan;
-    double* partials;                    // [partial_stride(4)][max_chunks]
+    double* partials;                    // [partial_stride(4)][grid] each workgroup's sums
     int max_chunks;
     const double* tables;                // TableLayout
     const double* coef;                  // this step's coefficients: cre, cim, dre, dim [4][K+1]
@@ -67,10 +68,13 @@ struct DensePlanArgs {
     const DensePlan* plan_prev;          // plan of the step just done (for its counters)
     int max_chunks;
     int reduce_t;                        // step whose partials to reduce, 0: none
-    const double* partials;
+    const double* partials;              // [partial_stride(4)][n_parts]
+    int n_parts;                         // workgroups of the step kernel
+    unsigned long long* agg;             // [kDenseMaxRegions] region totals, tagged with the epoch
+    unsigned int epoch;                  // this launch's tag (nonzero in its low 24 bits)
     double2* rho_hist;
     StepStatsDev* stats_hist;
-    const unsigned int* error;
+    unsigned int* error;
 };
 
 int dense_chunk_heads();

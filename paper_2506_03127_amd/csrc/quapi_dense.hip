@@ -14,7 +14,7 @@
 // nonempty words with the groups before each (and the word itself), and, for
 // each chunk of C consecutive groups, the word holding its first group; it
 // clears the next step's output bitmap and reduces the finished step's
-// per-chunk sums of rho(t) and counters in chunk order (deterministic).
+// per-workgroup sums of rho(t) and counters in workgroup order (deterministic).
 //
 // Step: persistent workgroups take chunks round-robin and fetch each chunk's
 // parents one chunk ahead (a parent's slot is the rank of its bit in its
@@ -24,8 +24,10 @@
 // (Sec. 2.1), merges each segment of consecutive parents per pair (sum of the
 // surviving weights; representative of largest quantised |w|^2, ties to the
 // smaller history read from the oldest point), writes the merged groups to
-// their slots, and sets their bits (one atomic OR per output word and wave).
-// Chunks never wait on one another.
+// their slots, and sets their bits (LDS atomics into the chunk's window of
+// output words, then one device atomic OR per word).  Chunks never wait on one
+// another.  Each workgroup sums rho(t), the dropped |w| and the survivors over
+// its chunks; the next planner adds the workgroups' sums in workgroup order.
 
 #include <hip/hip_runtime.h>
 
@@ -44,6 +46,7 @@ constexpr int kTabPtsD = 2;
 constexpr int kTabEntriesD = 16;
 constexpr int kMaxTabsD = 16;
 constexpr int kPlanWavesD = kDensePlanThreads / 64;
+constexpr int kOutWin = 8;                     // output bitmap words per pair staged per chunk
 
 // position of the r-th set bit (r < popcount) of v
 __device__ inline unsigned int select_bit(unsigned long long v, unsigned int r) {
@@ -63,33 +66,15 @@ __device__ inline unsigned int select_bit(unsigned long long v, unsigned int r) 
     return pos;
 }
 
-// OR of a 64-bit value over the 64 lanes of a wave, returned to every lane
-template <int CTRL>
-__device__ inline unsigned long long dpp_u64(unsigned long long v) {
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned int)v, CTRL, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned int)(v >> 32), CTRL, 0xf, 0xf, false);
-    return ((unsigned long long)(unsigned int)hi << 32) | (unsigned int)lo;
-}
-
-__device__ inline unsigned long long readlane_u64(unsigned long long v, int l) {
-    const unsigned int lo = (unsigned int)__builtin_amdgcn_readlane((int)(unsigned int)v, l);
-    const unsigned int hi = (unsigned int)__builtin_amdgcn_readlane((int)(unsigned int)(v >> 32), l);
-    return ((unsigned long long)hi << 32) | lo;
-}
-
-__device__ inline unsigned long long wave_or(unsigned long long v) {
-    v |= dpp_u64<0xB1>(v);      // quad_perm [1,0,3,2]
-    v |= dpp_u64<0x4E>(v);      // quad_perm [2,3,0,1]
-    v |= dpp_u64<0x141>(v);     // row_half_mirror
-    v |= dpp_u64<0x140>(v);     // row_mirror
-    return (readlane_u64(v, 0) | readlane_u64(v, 16)) | (readlane_u64(v, 32) | readlane_u64(v, 48));
-}
-
 // ------------------------------------------------------------------ planner
 // Workgroup w < n_regions plans the words [w * kDenseRegion, (w + 1) * kDenseRegion)
-// (thread i owns kDensePlanPer consecutive ones) and finds the groups and nonempty
-// words before its region by counting there with coalesced loads; the last
-// workgroup reduces the finished step's per-chunk sums.
+// (thread i owns kDensePlanPer consecutive ones, read as 16-byte pairs), publishes
+// its region's totals (groups, nonempty words) tagged with the launch's epoch,
+// and adds up the totals of the regions before it in one wave-wide read (every
+// region workgroup is resident: there are at most 64); the last workgroup
+// reduces the finished step's per-workgroup sums.
+constexpr unsigned long long kAggTag = 1ull << 40;   // epoch field of a region total: bits 40..63
+
 __device__ inline unsigned long long pack_sizes_d(unsigned int groups, unsigned int nz) {
     return ((unsigned long long)groups << 32) | nz;       // (groups << 32) | nonempty words
 }
@@ -97,7 +82,7 @@ __device__ inline unsigned long long pack_sizes_d(unsigned int groups, unsigned 
 __global__ __launch_bounds__(kDensePlanThreads) void dense_plan(const DensePlanArgs a) {
     constexpr int S = partial_stride(P4);
     __shared__ unsigned long long wsum[kPlanWavesD];
-    __shared__ unsigned long long wpre[kPlanWavesD];
+    __shared__ unsigned long long before_s;
     __shared__ double wred[kPlanWavesD][S];
     const int i = threadIdx.x;
     const int wave = i >> 6;
@@ -107,18 +92,17 @@ __global__ __launch_bounds__(kDensePlanThreads) void dense_plan(const DensePlanA
     const int w = (int)blockIdx.x;
 
     if (w == n_regions) {
-        // ---- counters and rho(t) of the step just finished, summed in chunk order
+        // ---- counters and rho(t) of the step just finished, summed in workgroup order
         if (a.reduce_t <= 0) return;
-        const unsigned int nc = a.plan_prev->n_chunks;
+        const unsigned int nc = (unsigned int)a.n_parts;
         const unsigned int err = error_word(a.error);
         if (err != 0u && (int)(err >> 4) <= a.reduce_t) return;
         double acc[S];
 #pragma unroll
         for (int k = 0; k < S; ++k) acc[k] = 0.0;
-#pragma unroll 2
         for (unsigned int c = i; c < nc; c += kDensePlanThreads)
 #pragma unroll
-            for (int k = 0; k < S; ++k) acc[k] += a.partials[(size_t)k * a.max_chunks + c];
+            for (int k = 0; k < S; ++k) acc[k] += a.partials[(size_t)k * a.n_parts + c];
 #pragma unroll
         for (int k = 0; k < S; ++k) {
             const double v = wave_sum(acc[k]);
@@ -147,22 +131,20 @@ __global__ __launch_bounds__(kDensePlanThreads) void dense_plan(const DensePlanA
     }
     if (error_word(a.error) != 0u) return;               // keep the last complete state
 
-    // ---- this thread's words and, in the same batch, the counts before the region
+    // ---- this thread's words, as 16-byte pairs
     const long long b_lo = (long long)w * kDenseRegion + (long long)i * kDensePlanPer;
     unsigned long long wd[kDensePlanPer];
+    if (b_lo + kDensePlanPer <= NW) {
+        const ulonglong2* src = reinterpret_cast<const ulonglong2*>(a.bits + b_lo);
 #pragma unroll
-    for (int k = 0; k < kDensePlanPer; ++k) wd[k] = b_lo + k < NW ? a.bits[b_lo + k] : 0ull;
-    unsigned long long before = 0;                        // this thread's share of the earlier regions
-    for (int r = 0; r < w; ++r) {
-        const long long q = (long long)r * kDenseRegion + (long long)i * kDensePlanPer;
-        unsigned int g = 0, nz = 0;
-#pragma unroll
-        for (int k = 0; k < kDensePlanPer; ++k) {
-            const unsigned long long v = a.bits[q + k];
-            g += (unsigned int)__popcll(v);
-            nz += v != 0ull;
+        for (int k = 0; k < kDensePlanPer / 2; ++k) {
+            const ulonglong2 v = src[k];
+            wd[2 * k] = v.x;
+            wd[2 * k + 1] = v.y;
         }
-        before += pack_sizes_d(g, nz);
+    } else {
+#pragma unroll
+        for (int k = 0; k < kDensePlanPer; ++k) wd[k] = b_lo + k < NW ? a.bits[b_lo + k] : 0ull;
     }
     unsigned int cnt[kDensePlanPer];
     unsigned int g_mine = 0, nz_mine = 0;
@@ -173,23 +155,46 @@ __global__ __launch_bounds__(kDensePlanThreads) void dense_plan(const DensePlanA
         nz_mine += wd[k] != 0ull;
     }
 
-    // ---- block sums: exclusive scan of this region, plus the earlier regions' total
+    // ---- block scan of this region; publish its totals; the regions before it
     const unsigned long long mine = pack_sizes_d(g_mine, nz_mine);
-    unsigned long long incl = mine, bsum = before;
+    unsigned long long incl = mine;
     for (int off = 1; off < 64; off <<= 1) {
         const unsigned long long v = (unsigned long long)__shfl_up((long long)incl, off, 64);
         if ((int)lane >= off) incl += v;
     }
-    for (int off = 32; off > 0; off >>= 1) bsum += (unsigned long long)__shfl_xor((long long)bsum, off, 64);
     if (lane == 63) wsum[wave] = incl;
-    if (lane == 0) wpre[wave] = bsum;
     __syncthreads();
     unsigned long long base = incl - mine, region = 0;
     for (int q = 0; q < kPlanWavesD; ++q) {
         if (q < wave) base += wsum[q];
-        base += wpre[q];
-        region += wsum[q] + wpre[q];
+        region += wsum[q];
     }
+    const unsigned long long tag = (unsigned long long)(a.epoch & 0xffffffu) * kAggTag;
+    if (i == 0)   // region totals < 2^20 groups and 2^16 words: (groups << 16) | nonempty
+        st_relaxed(a.agg + w, tag | ((region >> 32) << 16) | (region & 0xffffull));
+    if (wave == 0) {
+        unsigned long long g = 0, nz = 0;
+        if ((int)lane < w) {
+            unsigned long long v;
+            unsigned int spins = 0;
+            while (((v = ld_relaxed(a.agg + lane)) & ~(kAggTag - 1ull)) != tag) {
+                if (++spins == (1u << 24)) {   // a region never published: fail the step, do not hang
+                    raise_error(a.error, a.reduce_t + 1, kErrSpin);
+                    v = 0ull;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+            g = (v >> 16) & 0xffffffull;
+            nz = v & 0xffffull;
+        }
+        unsigned long long b = (g << 32) | nz;
+        for (int off = 32; off > 0; off >>= 1) b += (unsigned long long)__shfl_xor((long long)b, off, 64);
+        if (lane == 0) before_s = b;
+    }
+    __syncthreads();
+    base += before_s;
+    const unsigned long long total = before_s + region;
 
     // ---- nonempty words; each chunk's first group lies in the one of rank desc[c]
     unsigned int run = (unsigned int)(base >> 32), rank = (unsigned int)base;
@@ -207,19 +212,23 @@ __global__ __launch_bounds__(kDensePlanThreads) void dense_plan(const DensePlanA
     }
 
     // ---- clear the next step's output bitmap
+    if (b_lo + kDensePlanPer <= NW) {
+        ulonglong2* dst = reinterpret_cast<ulonglong2*>(a.bits_next + b_lo);
 #pragma unroll
-    for (int k = 0; k < kDensePlanPer; ++k)
-        if (b_lo + k < NW) a.bits_next[b_lo + k] = 0ull;
+        for (int k = 0; k < kDensePlanPer / 2; ++k) dst[k] = make_ulonglong2(0ull, 0ull);
+    } else {
+        for (long long b = b_lo; b < NW; ++b) a.bits_next[b] = 0ull;
+    }
 
     // ---- the last region knows the totals
     if (w == n_regions - 1 && i == 0) {
-        const unsigned int N = (unsigned int)(region >> 32);
+        const unsigned int N = (unsigned int)(total >> 32);
         if (a.reduce_t > 0) a.stats_hist[a.reduce_t].n_stored = N;
         DensePlan pl;
         pl.n_groups = N;
         pl.n_chunks = (N + kC - 1) / kC;
         pl.pad = 0u;
-        pl.n_nonempty = (unsigned int)region;
+        pl.n_nonempty = (unsigned int)total;
         *a.plan = pl;
     }
 }
@@ -232,6 +241,7 @@ struct DLds {
     double tab[kMaxTabsD][kTabEntriesD][4];     // subset sums of the coefficients (A, B, Ac, Bc)
     double e0, f0;
     double2 cw[P4][kDenseThreads];              // child weights
+    unsigned int cq[P4][kDenseThreads];         // their quantised |w|^2, high word (qbits >= 32)
     unsigned long long ctail[kDenseThreads];    // child history tails
     unsigned int surv[kDenseThreads];           // bit p: child p survives
     unsigned long long win_b[kWinD];            // nonempty words around the next chunk ...
@@ -239,6 +249,8 @@ struct DLds {
     unsigned int win_p[kWinD];                  // ... and the groups before them
     unsigned long long hmask[kWavesD];          // segment heads, one word per wave
     unsigned long long vmask[kWavesD];          // loaded parents
+    unsigned long long obits[P4][kOutWin];      // output bitmap words of the chunk, by pair
+    unsigned long long obase;                   // word (within a pair) of obits[.][0]
     double wrho[kWavesD][4][8];                 // rho sums per wave and row of 16 lanes
     double wdrop[kWavesD];
     unsigned int wsurv[kWavesD];
@@ -321,7 +333,18 @@ __device__ inline DParent fetch_parent_d(const DenseArgs& a, const DLds& s, unsi
     return r;
 }
 
-__global__ __launch_bounds__(kDenseThreads) void dense_step(const DenseArgs a) {
+// thread i < P * kOutWin: word i % kOutWin of pair i / kOutWin of the chunk's
+// window, ORed into the bitmap and cleared
+__device__ inline void flush_bits(const DenseArgs& a, DLds& s, int i, int pair_words) {
+    const int p = i / kOutWin, k = i % kOutWin;
+    const unsigned long long v = s.obits[p][k];
+    if (v) {
+        atomicOr(a.bits_out + (((unsigned long long)p << pair_words) | (s.obase + k)), v);
+        s.obits[p][k] = 0ull;
+    }
+}
+
+__global__ __launch_bounds__(kDenseThreads, 4) void dense_step(const DenseArgs a) {
     constexpr int P = P4, BP = BP2, C = kC;
     constexpr int S = partial_stride(P);
     constexpr unsigned long long DM = (1ull << BP) - 1;
@@ -336,7 +359,10 @@ __global__ __launch_bounds__(kDenseThreads) void dense_step(const DenseArgs a) {
     const unsigned int n_nz = a.plan->n_nonempty;
     const unsigned int G = gridDim.x;
     unsigned int c = blockIdx.x;
-    if (c >= n_chunks) return;
+    if (c >= n_chunks) {
+        if (i < S) a.partials[(size_t)i * G + blockIdx.x] = 0.0;   // no chunk: zero sums
+        return;
+    }
 
     // ---- the first chunk's window and the next one's, in flight during the set-up
     DWin wr = load_window_d(a, a.desc[c], n_nz, N, i);
@@ -360,6 +386,7 @@ __global__ __launch_bounds__(kDenseThreads) void dense_step(const DenseArgs a) {
         dst[d] = a.coef[k];
     }
     store_window_d(s, wr, i);
+    if (i < P * kOutWin) s.obits[i / kOutWin][i % kOutWin] = 0ull;
     __syncthreads();
     DParent cur = fetch_parent_d(a, s, c, N, i, lane);
     const int nk = (L + kTabPtsD - 1) / kTabPtsD, nt = (K - L + kTabPtsD - 1) / kTabPtsD;
@@ -397,7 +424,17 @@ __global__ __launch_bounds__(kDenseThreads) void dense_step(const DenseArgs a) {
     const unsigned long long tail_mask =
         tail_pts <= 0 ? 0ull : (tail_pts * BP >= 64 ? ~0ull : ((1ull << (tail_pts * BP)) - 1));
     const int top_shift = BP * (L - 1);
+    const int pair_words = top_shift - 6;              // log2 of the bitmap words of one pair
     const unsigned long long lane_le = (lane == 63u) ? ~0ull : ((2ull << lane) - 1ull);   // lanes 0..lane
+    const bool q32 = (a.qmask & 0xffffffffull) == 0ull;   // the quantised |w|^2 fits its high word
+
+    // the workgroup's sums over its chunks, per wave (row sums of rho by pair,
+    // dropped |w|, survivors), added chunk by chunk in chunk order
+    if (i < kWavesD * 4 * 8) (&s.wrho[0][0][0])[i] = 0.0;
+    if (i < kWavesD) {
+        s.wdrop[i] = 0.0;
+        s.wsurv[i] = 0u;
+    }
 
     for (;;) {
         // ---- fetch the next chunk's parents now; they arrive while this chunk computes
@@ -405,6 +442,7 @@ __global__ __launch_bounds__(kDenseThreads) void dense_step(const DenseArgs a) {
         const bool has_next = c1 < n_chunks;
         DParent nxt = cur;
         __syncthreads();                                   // the chunk before is done with the LDS
+        if (i < P * kOutWin) flush_bits(a, s, i, pair_words);
         if (has_next) {
             store_window_d(s, wn, i);
             __syncthreads();                               // (also publishes the tables)
@@ -428,6 +466,7 @@ __global__ __launch_bounds__(kDenseThreads) void dense_step(const DenseArgs a) {
             s.hmask[wave] = hm;
             s.vmask[wave] = vm;
         }
+        if (i == 0) s.obase = valid ? (key >> BP) >> 6 : 0ull;   // the chunk's first output word
         __syncthreads();
 
         // a parent belongs to this chunk when its segment head does
@@ -455,9 +494,9 @@ __global__ __launch_bounds__(kDenseThreads) void dense_step(const DenseArgs a) {
         }
 
         // ---- extend: influence sums of the parent over lags 1..dmax
-        double rho_re[P], rho_im[P];
+        double rho_v[2 * P];
 #pragma unroll
-        for (int p = 0; p < P; ++p) { rho_re[p] = 0.0; rho_im[p] = 0.0; }
+        for (int k = 0; k < 2 * P; ++k) rho_v[k] = 0.0;
         double dropped = 0.0;
         unsigned int surv_bits = 0;
         unsigned long long ctail = 0;
@@ -523,50 +562,37 @@ __global__ __launch_bounds__(kDenseThreads) void dense_step(const DenseArgs a) {
                 const bool keep = (a.theta2 == 0.0) || !(n2 < a.theta2);
                 if (keep) {
                     surv_bits |= 1u << p;
-                    rho_re[p] = wr2 * fr[p] - wi2 * fi[p];
-                    rho_im[p] = wr2 * fi[p] + wi2 * fr[p];
+                    rho_v[2 * p] = wr2 * fr[p] - wi2 * fi[p];
+                    rho_v[2 * p + 1] = wr2 * fi[p] + wi2 * fr[p];
                 } else {
                     dropped += sqrt(n2);
                 }
                 s.cw[p][i] = make_double2(wr2, wi2);
+                s.cq[p][i] = (unsigned int)(((unsigned long long)__double_as_longlong(n2) & a.qmask) >> 32);
             }
         }
         s.surv[i] = surv_bits;
         s.ctail[i] = ctail;
-
-        // ---- partial sums of rho, dropped weight and survivor count
         {
-            const double v[8] = {rho_re[0], rho_im[0], rho_re[1], rho_im[1],
-                                 rho_re[2], rho_im[2], rho_re[3], rho_im[3]};
+            // this chunk's rho, dropped |w| and survivors, added to the wave's sums
             double x0, x1;
-            row_sums8(v, lane, x0, x1);
+            row_sums8(rho_v, lane, x0, x1);
             if ((lane & 15u) >= 12u) {
                 const unsigned int r = lane & 3u;
                 const int k = 4 * (int)(r & 1u) + 2 * (int)(r >> 1);
-                s.wrho[wave][lane >> 4][k] = x0;
-                s.wrho[wave][lane >> 4][k + 1] = x1;
+                s.wrho[wave][lane >> 4][k] += x0;
+                s.wrho[wave][lane >> 4][k + 1] += x1;
             }
             const double dsum = wave_sum(dropped);
             unsigned int ns = 0u;
 #pragma unroll
             for (int p = 0; p < P; ++p) ns += (unsigned int)__popcll(__ballot((surv_bits >> p) & 1u));
-            if (lane == 0u) { s.wdrop[wave] = dsum; s.wsurv[wave] = ns; }
+            if (lane == 0u) {
+                s.wdrop[wave] += dsum;
+                s.wsurv[wave] += ns;
+            }
         }
         __syncthreads();
-        if (i < S) {                                       // this chunk's partial sums
-            double v = 0.0;
-            if (i < 2 * P) {
-                for (int w = 0; w < kWavesD; ++w)
-                    for (int r = 0; r < 4; ++r) v += s.wrho[w][r][i];
-            } else if (i == 2 * P) {
-                for (int w = 0; w < kWavesD; ++w) v += s.wdrop[w];
-            } else {
-                unsigned int ns = 0u;
-                for (int w = 0; w < kWavesD; ++w) ns += s.wsurv[w];
-                v = (double)ns;
-            }
-            a.partials[(size_t)i * a.max_chunks + c] = v;
-        }
 
         // ---- merge each segment per pair (sum of the surviving weights and the
         //      representative), write the merged group to its slot, set its bit
@@ -578,7 +604,7 @@ __global__ __launch_bounds__(kDenseThreads) void dense_step(const DenseArgs a) {
             msurv[m] = m < len ? s.surv[j] : 0u;
             mtail[m] = s.ctail[j];
         }
-#pragma unroll
+#pragma unroll 1
         for (int p = 0; p < P; ++p) {
             bool any = false;
             double sr = 0.0, si = 0.0;
@@ -586,11 +612,13 @@ __global__ __launch_bounds__(kDenseThreads) void dense_step(const DenseArgs a) {
 #pragma unroll
             for (int m = 0; m < P; ++m) {
                 if (!((msurv[m] >> p) & 1u)) continue;
-                const double2 w = s.cw[p][min(i + m, kDenseThreads - 1)];
+                const int j = min(i + m, kDenseThreads - 1);
+                const double2 w = s.cw[p][j];
                 sr += w.x;
                 si += w.y;
                 const unsigned long long q =
-                    (unsigned long long)__double_as_longlong(norm2_nocontract(w.x, w.y)) & a.qmask;
+                    q32 ? ((unsigned long long)s.cq[p][j] << 32)
+                        : ((unsigned long long)__double_as_longlong(norm2_nocontract(w.x, w.y)) & a.qmask);
                 if (!any || q > bq || (q == bq && mtail[m] < bt)) { bq = q; bt = mtail[m]; }
                 any = true;
             }
@@ -599,23 +627,35 @@ __global__ __launch_bounds__(kDenseThreads) void dense_step(const DenseArgs a) {
                 a.tail_out[so] = bt;
                 a.w_out[so] = make_double2(sr, si);
             }
-            // bits: the wave's heads are in slot order, so each output word's bits
-            // come from a run of lanes; one atomic OR per word
-            const unsigned long long wi = so >> 6;
-            const unsigned long long bit = any ? (1ull << (so & 63ull)) : 0ull;
-            unsigned long long todo = __ballot(any);
-            while (todo) {
-                const int leader = __builtin_ctzll(todo);
-                const unsigned long long wl = readlane_u64(wi, leader);
-                const unsigned long long same = __ballot(any && wi == wl);
-                const unsigned long long val = wave_or(((same >> lane) & 1ull) ? bit : 0ull);
-                if ((int)lane == leader) atomicOr(a.bits_out + wl, val);
-                todo &= ~same;
+            // its bit: into the chunk's window of output words, or straight to the bitmap
+            if (any) {
+                const unsigned long long wi = (key >> BP) >> 6, idx = wi - s.obase;
+                const unsigned long long bit = 1ull << ((key >> BP) & 63ull);
+                if (idx < (unsigned long long)kOutWin) atomicOr(&s.obits[p][idx], bit);
+                else atomicOr(a.bits_out + (((unsigned long long)p << pair_words) | wi), bit);
             }
         }
         if (!has_next) break;
         cur = nxt;
         c = c1;
+    }
+    __syncthreads();
+    if (i < P * kOutWin) flush_bits(a, s, i, pair_words);
+
+    // ---- the workgroup's sums: rows and waves in order
+    if (i < S) {
+        double v = 0.0;
+        if (i < 2 * P) {
+            for (int w = 0; w < kWavesD; ++w)
+                for (int r = 0; r < 4; ++r) v += s.wrho[w][r][i];
+        } else if (i == 2 * P) {
+            for (int w = 0; w < kWavesD; ++w) v += s.wdrop[w];
+        } else {
+            unsigned int ns = 0u;
+            for (int w = 0; w < kWavesD; ++w) ns += s.wsurv[w];
+            v = (double)ns;
+        }
+        a.partials[(size_t)i * G + blockIdx.x] = v;
     }
 }
 

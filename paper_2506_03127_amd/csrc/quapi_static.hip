@@ -81,6 +81,7 @@ struct StaticSetup {
     double2* rho_hist;
     StepStatsDev* stats;
     quapi_dev::DensePlan* plan;                 // [2]
+    unsigned long long* agg;                    // [kDenseMaxRegions] planner region totals
     unsigned int* error;
 };
 
@@ -96,6 +97,7 @@ __global__ __launch_bounds__(256) void static_tables(const StaticSetup a) {
     }
     if (blockIdx.x != 0) return;
     const int i = threadIdx.x;
+    if (i < quapi_dev::kDenseMaxRegions) a.agg[i] = 0ull;   // no tag of an earlier call survives
     if (i < 32) a.tables[i] = a.k4[i];
     if (i < 4) {
         a.tables[TableLayout::ds(4) + i] = a.ds[i];
@@ -181,6 +183,11 @@ extern "C" int quapi_run_static(const quapi_params* p, int n_steps, quapi_c64* r
     }
     if (L < quapi_dev::kDenseMinL || L > kStaticMaxL) return QUAPI_EUNSUPPORTED;
 
+    unsigned char* base = nullptr;
+    int grid = 0;
+    const int rc = device_scratch(&base, &grid);
+    if (rc != QUAPI_OK) return rc;
+
     // ---- the run's buffers in scratch
     const unsigned long long S = 1ull << (2 * L);
     const size_t nw = (size_t)(S / 64);
@@ -194,7 +201,8 @@ extern "C" int quapi_run_static(const quapi_params* p, int n_steps, quapi_c64* r
     const size_t o_nzw = take((nw + 1) * 4), o_nzp = take((nw + 1) * 4), o_nzb = take((nw + 1) * 8);
     const size_t o_desc = take((size_t)max_chunks * 4);
     const size_t o_plan = take(2 * sizeof(quapi_dev::DensePlan));
-    const size_t o_part = take((size_t)max_chunks * quapi_dev::partial_stride(4) * 8);
+    const size_t o_agg = take(quapi_dev::kDenseMaxRegions * 8);
+    const size_t o_part = take((size_t)grid * quapi_dev::partial_stride(4) * 8);
     const size_t o_tab = take(n_tab * 8), o_coef = take(n_coef * 8);
     const size_t o_stats = take((size_t)(n_steps + 1) * sizeof(StepStatsDev));
     const size_t o_err = take(4);
@@ -252,10 +260,6 @@ extern "C" int quapi_run_static(const quapi_params* p, int n_steps, quapi_c64* r
         ++su.n_init;
     }
 
-    unsigned char* base = nullptr;
-    int grid = 0;
-    const int rc = device_scratch(&base, &grid);
-    if (rc != QUAPI_OK) return rc;
     hipStream_t stream = (hipStream_t)p->stream;
     su.K = K;
     su.n_words = (long long)nw;
@@ -268,6 +272,7 @@ extern "C" int quapi_run_static(const quapi_params* p, int n_steps, quapi_c64* r
     su.rho_hist = (double2*)rho_out;
     su.stats = (StepStatsDev*)(base + o_stats);
     su.plan = (quapi_dev::DensePlan*)(base + o_plan);
+    su.agg = (unsigned long long*)(base + o_agg);
     su.error = (unsigned int*)(base + o_err);
     const unsigned int tgrid = (unsigned int)std::min<size_t>(std::max<size_t>((nw + 255) / 256, 1), 1024);
     hipLaunchKernelGGL(static_tables, dim3(tgrid), dim3(256), 0, stream, su);
@@ -286,9 +291,11 @@ extern "C" int quapi_run_static(const quapi_params* p, int n_steps, quapi_c64* r
     pa.desc = (unsigned int*)(base + o_desc);
     pa.max_chunks = max_chunks;
     pa.partials = (double*)(base + o_part);
+    pa.n_parts = grid;
     pa.rho_hist = su.rho_hist;
     pa.stats_hist = su.stats;
     pa.error = su.error;
+    pa.agg = su.agg;
     quapi_dev::DenseArgs sa;
     sa.nz_word = pa.nz_word;
     sa.nz_prefix = pa.nz_prefix;
@@ -324,6 +331,7 @@ extern "C" int quapi_run_static(const quapi_params* p, int n_steps, quapi_c64* r
         pa.plan = su.plan + ((t + 1) & 1);
         pa.plan_prev = su.plan + (t & 1);
         pa.reduce_t = t;
+        pa.epoch = (unsigned int)(t % 0xffffff) + 1u;   // nonzero, distinct from the last 2^24 - 2 launches
         if (quapi_dev::launch_dense_plan(pa, stream) != (int)hipSuccess) return QUAPI_EDEVICE;
     }
     return QUAPI_OK;
