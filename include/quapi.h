@@ -272,7 +272,7 @@ void quapi_destroy(quapi_ctx* c);
  * tight serving loops, harnesses that forbid allocation): the propagation of
  * quapi_create + quapi_step(n_steps) on the direct-mapped store
  * (QUAPI_MERGE_DIRECT) as one call that allocates nothing.  Every buffer of the
- * run lives in one 64 MiB file-scope device array that each device holds
+ * run lives in one 96 MiB file-scope device array that each device holds
  * until the process ends; the host tables reach the device as kernel
  * arguments.  Enqueues on p->stream (NULL: the null stream) and returns
  * without waiting; rho_out is a caller-owned DEVICE buffer of
@@ -283,8 +283,8 @@ void quapi_destroy(quapi_ctx* c);
  * Takes M = 2, FP64, dk_max <= 40, merge positions 0..L-1 with 6 <= L <= 10,
  * p->merge AUTO or DIRECT; p->max_groups and p->max_steps are not read.
  * Errors: EINVAL (bad argument, as quapi_create), EUNSUPPORTED (a problem
- * outside that range), ENOMEM (the run needs more than the 64 MiB array:
- * about 48 B per slot of 4^L plus 48 B per step), EDEVICE. */
+ * outside that range), ENOMEM (the run needs more than the 96 MiB array:
+ * about 70 B per slot of 4^L plus 48 B per step), EDEVICE. */
 int quapi_run_static(const quapi_params* p, int n_steps, quapi_c64* rho_out);
 
 /* ---------------------------------------------------------------- host utilities */

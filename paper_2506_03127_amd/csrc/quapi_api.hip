@@ -62,19 +62,16 @@ struct quapi_ctx {
 
     // direct-mapped store (two-level systems, merge positions 0..L-1, short keys)
     bool dense = false;
-    unsigned long long* dn_bits[2] = {nullptr, nullptr};   // [S/64] by buffer
-    unsigned long long* dn_tail[2] = {nullptr, nullptr};   // [S]
-    double2* dn_w[2] = {nullptr, nullptr};                 // [S]
+    unsigned char* dn_flag[2] = {nullptr, nullptr};        // [S] occupancy bytes by buffer
+    quapi_dev::DenseRec* dn_rec[2] = {nullptr, nullptr};   // [S] records by buffer
+    double* dn_tabs = nullptr;                             // [K+1] lag-sum table sets
     unsigned long long dn_slots = 0;                       // S = P^L
-    unsigned int* dn_nz_word = nullptr;                    // [S/64] nonempty bitmap words ...
-    unsigned int* dn_nz_prefix = nullptr;                  // ... the groups before each ...
-    unsigned long long* dn_nz_bits = nullptr;              // ... and the word
-    unsigned int* dn_desc = nullptr;                       // [dn_max_chunks]
+    unsigned int* dn_seg = nullptr;                        // [4][S/4] the planner's segment lists
     quapi_dev::DensePlan* dn_plan = nullptr;               // [2] by step parity
-    double* dn_partials = nullptr;                         // [partial_stride(4)][dn_max_chunks]
-    int dn_max_chunks = 0;
+    double* dn_partials = nullptr;                         // [partial_stride(4)][dn_grid]
     int dn_grid = 0;
-    unsigned long long* dn_agg = nullptr;                  // [kDenseMaxRegions] planner region totals
+    int dn_lds = 0;                                        // the step kernel's table bytes
+    unsigned long long* dn_agg = nullptr;                  // [kDenseMaxRegions] planner region counts
     unsigned int dn_epoch = 0;                             // tag of the last planner launch
 
     // batched form: n_inst instances (bath parameter points) in one store
@@ -199,16 +196,12 @@ int upload_initial_sparse(quapi_ctx* c) {
 // (and reduce step t's sums when t >= 1); clears the bitmap step t+1 writes.
 int launch_dense_planner(quapi_ctx* c, int t) {
     quapi_dev::DensePlanArgs pa;
-    pa.bits = c->dn_bits[c->cur];
-    pa.bits_next = c->dn_bits[1 - c->cur];
-    pa.n_words = (long long)(c->dn_slots / 64);
-    pa.nz_word = c->dn_nz_word;
-    pa.nz_prefix = c->dn_nz_prefix;
-    pa.nz_bits = c->dn_nz_bits;
-    pa.desc = c->dn_desc;
+    pa.flags = reinterpret_cast<const unsigned int*>(c->dn_flag[c->cur]);
+    pa.flags_spent = reinterpret_cast<unsigned int*>(c->dn_flag[1 - c->cur]);
+    pa.seg = c->dn_seg;
+    pa.n_segs = (long long)(c->dn_slots / 4);
     pa.plan = c->dn_plan + ((t + 1) & 1);
     pa.plan_prev = c->dn_plan + (t & 1);
-    pa.max_chunks = c->dn_max_chunks;
     pa.reduce_t = t;
     pa.partials = c->dn_partials;
     pa.n_parts = c->dn_grid;
@@ -216,28 +209,29 @@ int launch_dense_planner(quapi_ctx* c, int t) {
     pa.stats_hist = c->d_stats;
     pa.error = c->d_error;
     pa.agg = c->dn_agg;
-    c->dn_epoch = (c->dn_epoch + 1u) & 0xffffffu;
-    if (c->dn_epoch == 0u) c->dn_epoch = 1u;             // 0 is the cleared buffer's tag
+    c->dn_epoch = c->dn_epoch % 4095u + 1u;               // 1..4095; 0 is the cleared buffer's tag
     pa.epoch = c->dn_epoch;
     return quapi_dev::launch_dense_plan(pa, c->stream) == (int)hipSuccess ? QUAPI_OK : QUAPI_EDEVICE;
 }
 
 // t = 0 on the direct-mapped store: the initial groups at their slots, the
-// bitmap of the first buffer holding exactly them
+// occupancy of the first buffer holding exactly them and that of the second none
 int upload_initial_dense(quapi_ctx* c) {
-    const size_t nw = (size_t)(c->dn_slots / 64);
-    std::vector<unsigned long long> bits(nw, 0ull);
+    const size_t S = (size_t)c->dn_slots;
     const size_t n0 = c->init_key.size();
-    std::vector<unsigned long long> zero(n0 ? n0 : 1, 0ull);
-    for (size_t k = 0; k < n0; ++k) bits[c->init_key[k] / 64] |= 1ull << (c->init_key[k] % 64);
-    hipError_t e = hipMemcpyAsync(c->dn_bits[0], bits.data(), nw * 8, hipMemcpyHostToDevice, c->stream);
+    std::vector<quapi_dev::DenseRec> rec(n0 ? n0 : 1);
+    const unsigned char one = 1u;
+    hipError_t e = hipMemsetAsync(c->dn_flag[0], 0, S, c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c->dn_flag[1], 0, S, c->stream);
     for (size_t k = 0; k < n0 && e == hipSuccess; ++k) {
         const unsigned long long sl = c->init_key[k];
-        e = hipMemcpyAsync(c->dn_tail[0] + sl, zero.data(), 8, hipMemcpyHostToDevice, c->stream);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(c->dn_w[0] + sl, &c->init_w[k], 16, hipMemcpyHostToDevice, c->stream);
+        rec[k].w = c->init_w[k];
+        rec[k].tail = 0ull;
+        rec[k].pad = 0ull;
+        e = hipMemcpyAsync(c->dn_rec[0] + sl, &rec[k], sizeof(quapi_dev::DenseRec), hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(c->dn_flag[0] + sl, &one, 1, hipMemcpyHostToDevice, c->stream);
     }
-    // the copies read host vectors of this frame: complete them before returning
+    // the copies read host values of this frame: complete them before returning
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     return hip_to_code(e);
 }
@@ -434,12 +428,9 @@ int step_sparse(quapi_ctx* c, int n_steps) {
 // of the next step (which reduces this one's sums)
 int step_dense(quapi_ctx* c, int n_steps) {
     quapi_dev::DenseArgs a;
-    a.nz_word = c->dn_nz_word;
-    a.nz_prefix = c->dn_nz_prefix;
-    a.nz_bits = c->dn_nz_bits;
-    a.desc = c->dn_desc;
+    a.seg = c->dn_seg;
     a.partials = c->dn_partials;
-    a.max_chunks = c->dn_max_chunks;
+    a.n_segs = (long long)(c->dn_slots / 4);
     a.tables = c->d_tables;
     a.L = c->L;
     a.K = c->K;
@@ -449,19 +440,17 @@ int step_dense(quapi_ctx* c, int n_steps) {
     const int n = c->K + 1;
     for (int k = 0; k < n_steps; ++k) {
         const int t = c->t + 1;
-        a.bits_in = c->dn_bits[c->cur];
-        a.tail_in = c->dn_tail[c->cur];
-        a.w_in = c->dn_w[c->cur];
-        a.bits_out = c->dn_bits[1 - c->cur];
-        a.tail_out = c->dn_tail[1 - c->cur];
-        a.w_out = c->dn_w[1 - c->cur];
+        a.rec_in = c->dn_rec[c->cur];
+        a.rec_out = c->dn_rec[1 - c->cur];
+        a.flag_out = c->dn_flag[1 - c->cur];
         a.plan = c->dn_plan + (t & 1);
         a.t = t;
         a.coef = c->d_coef + (size_t)(std::min(t, c->K + 1) - 1) * 4 * n;
+        a.tabset = c->dn_tabs + (size_t)(std::min(t, c->K + 1) - 1) * quapi_dev::dense_tabset_doubles(c->L, c->K);
         hipEvent_t* ev = (c->prof_on && !c->capturing && c->prof_n < c->prof_cap)
                              ? &c->prof_ev[3 * (size_t)c->prof_n++] : nullptr;
         if (ev && hipEventRecord(ev[0], c->stream) != hipSuccess) ev = nullptr;
-        if (quapi_dev::launch_dense_step(a, c->dn_grid, c->stream) != (int)hipSuccess) {
+        if (quapi_dev::launch_dense_step(a, c->dn_grid, c->dn_lds, c->stream) != (int)hipSuccess) {
             c->err = QUAPI_EDEVICE;
             return c->err;
         }
@@ -914,18 +903,13 @@ static int create_ctx(const quapi_params* p, int n_inst, const quapi_c64* eta_al
     if (!rc) rc = dev_alloc(c, &c->d_error, 1);
     if (!rc && c->dense) {
         c->dn_slots = (unsigned long long)ipow(P, L);
-        const size_t nw = (size_t)(c->dn_slots / 64);
-        c->dn_max_chunks = (int)(c->dn_slots / quapi_dev::dense_chunk_heads() + 2);
         for (int b = 0; b < 2 && !rc; ++b) {
-            rc = dev_alloc(c, &c->dn_bits[b], nw);
-            if (!rc) rc = dev_alloc(c, &c->dn_tail[b], (size_t)c->dn_slots);
-            if (!rc) rc = dev_alloc(c, &c->dn_w[b], (size_t)c->dn_slots);
+            rc = dev_alloc(c, &c->dn_flag[b], (size_t)c->dn_slots);
+            if (!rc) rc = dev_alloc(c, &c->dn_rec[b], (size_t)c->dn_slots);
         }
-        if (!rc) rc = dev_alloc(c, &c->dn_nz_word, nw + 1);
-        if (!rc) rc = dev_alloc(c, &c->dn_nz_prefix, nw + 1);
-        if (!rc) rc = dev_alloc(c, &c->dn_nz_bits, nw + 1);
-        if (!rc) rc = dev_alloc(c, &c->dn_desc, (size_t)c->dn_max_chunks);
+        if (!rc) rc = dev_alloc(c, &c->dn_seg, (size_t)c->dn_slots);   // four lists of S/4
         if (!rc) rc = dev_alloc(c, &c->dn_plan, 2);
+        if (!rc) rc = dev_alloc(c, &c->dn_tabs, (size_t)(K + 1) * quapi_dev::dense_tabset_doubles(L, K));
         if (!rc) rc = dev_alloc(c, &c->dn_agg, (size_t)quapi_dev::kDenseMaxRegions);
     }
     if (!rc && c->sparse) {
@@ -963,6 +947,9 @@ static int create_ctx(const quapi_params* p, int n_inst, const quapi_c64* eta_al
     if (e == hipSuccess)
         e = hipMemcpyAsync(c->d_coef, c->coef.data(), c->coef.size() * sizeof(double), hipMemcpyHostToDevice,
                            c->stream);
+    if (e == hipSuccess && c->dense &&
+        quapi_dev::launch_dense_tables(c->d_coef, c->d_tables, L, K, K + 1, c->dn_tabs, c->stream) != (int)hipSuccess)
+        e = hipErrorLaunchFailure;
     if (e == hipSuccess && c->d_k4_batch)
         e = hipMemcpyAsync(c->d_k4_batch, c->k4_batch.data(), c->k4_batch.size() * sizeof(double),
                            hipMemcpyHostToDevice, c->stream);
@@ -992,7 +979,8 @@ static int create_ctx(const quapi_params* p, int n_inst, const quapi_c64* eta_al
     }
     if (c->dense) {
         // persistent workgroups, as many as are resident (their chunks never wait on one another)
-        c->dn_grid = quapi_dev::dense_step_grid(std::max(ncu, 1));
+        c->dn_lds = quapi_dev::dense_lds_bytes(L, K);
+        c->dn_grid = quapi_dev::dense_step_grid(std::max(ncu, 1), c->dn_lds);
         if (per_cu > 0) c->dn_grid = std::min(c->dn_grid, per_cu * std::max(ncu, 1));
         if (c->dn_grid < 1 ||
             dev_alloc(c, &c->dn_partials, (size_t)c->dn_grid * quapi_dev::partial_stride(4)) != QUAPI_OK ||
@@ -1318,34 +1306,31 @@ int quapi_batch_groups(quapi_ctx* c, int inst, long long cap, unsigned char* his
     }
     if (c->dense) {
         const size_t S = (size_t)c->dn_slots;
-        std::vector<unsigned long long> bits(S / 64);
-        hipError_t e = hipMemcpy(bits.data(), c->dn_bits[c->cur], bits.size() * 8, hipMemcpyDeviceToHost);
+        std::vector<unsigned char> flag(S);
+        hipError_t e = hipMemcpy(flag.data(), c->dn_flag[c->cur], S, hipMemcpyDeviceToHost);
         if (e != hipSuccess) return hip_to_code(e);
         long long n = 0;
-        for (unsigned long long b : bits) n += __builtin_popcountll(b);
+        for (unsigned char f : flag) n += f != 0u;
         *n_out = n;
         if (cap == 0 || n == 0) return QUAPI_OK;
-        std::vector<unsigned long long> tl(S);
-        std::vector<double2> ww(S);
-        e = hipMemcpy(tl.data(), c->dn_tail[c->cur], S * 8, hipMemcpyDeviceToHost);
-        if (e == hipSuccess) e = hipMemcpy(ww.data(), c->dn_w[c->cur], S * 16, hipMemcpyDeviceToHost);
+        std::vector<quapi_dev::DenseRec> rec(S);
+        e = hipMemcpy(rec.data(), c->dn_rec[c->cur], S * sizeof(quapi_dev::DenseRec), hipMemcpyDeviceToHost);
         if (e != hipSuccess) return hip_to_code(e);
         const unsigned long long dm = (1ull << c->bits) - 1;
         long long written = 0;
-        for (size_t wd = 0; wd < bits.size() && written < cap; ++wd)
-            for (unsigned long long b = bits[wd]; b && written < cap; b &= b - 1) {
-                const size_t o = wd * 64 + (size_t)__builtin_ctzll(b);
-                unsigned char* row = hist + (size_t)written * c->K;
-                for (int j = 0; j < c->K; ++j) {
-                    unsigned long long d;
-                    if (j < c->L) d = ((unsigned long long)o >> (c->bits * (c->L - 1 - j))) & dm;
-                    else d = (tl[o] >> (c->bits * (j - c->L))) & dm;
-                    row[j] = (unsigned char)d;
-                }
-                w[written].re = ww[o].x;
-                w[written].im = ww[o].y;
-                ++written;
+        for (size_t o = 0; o < S && written < cap; ++o) {
+            if (!flag[o]) continue;
+            unsigned char* row = hist + (size_t)written * c->K;
+            for (int j = 0; j < c->K; ++j) {
+                unsigned long long d;
+                if (j < c->L) d = ((unsigned long long)o >> (c->bits * (c->L - 1 - j))) & dm;
+                else d = (rec[o].tail >> (c->bits * (j - c->L))) & dm;
+                row[j] = (unsigned char)d;
             }
+            w[written].re = rec[o].w.x;
+            w[written].im = rec[o].w.y;
+            ++written;
+        }
         return QUAPI_OK;
     }
     // the instance's buckets

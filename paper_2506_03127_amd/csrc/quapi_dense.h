@@ -7,49 +7,60 @@
 namespace quapi_dev {
 
 // Every key of the L merge positions owns a slot: slot = key, the points read
-// as a base-P number with point 0 most significant, so slots are in key order.
-// A slot holds the rest of the representative's history (points L..K-1, point
-// L lowest) and the group amplitude; a bitmap (one 64-bit word per 64 slots)
-// says which slots hold a group.
+// as a base-4 number with point 0 most significant, so slots are in key order.
+// A slot holds a 32-byte record -- the group amplitude and the rest of the
+// representative's history (points L..K-1, point L lowest) -- and an occupancy
+// byte (1: the slot holds a group) in an array of its own.
 //
-// The parents whose children merge (same points 0..L-2) are the P slots
-// [P j, P j + P) of segment j, and the merged child of segment j by pair p has
-// the fixed slot p * Q + j, Q = P^(L-1): an output position never depends on
-// other groups, so chunks of parents need no offsets from one another.  The
-// planner between steps turns the bitmap into chunks of equal size: the list
-// of nonempty bitmap words with the number of groups before each, and the
-// word holding each chunk's first group.
-constexpr int kDenseThreads = 256;             // threads per chunk = parents loaded per chunk
+// Segment j is the four slots [4 j, 4 j + 4): the parents whose children merge
+// (same points 0..L-2, Sec. 3.1.2).  The merged child of segment j by pair p
+// has the fixed slot p * Q + j, Q = 4^(L-1), so an output position never
+// depends on other groups.  Between steps the planner lists the nonempty
+// segments by how many groups they hold (lists 0..3 for 1..4 groups; entry
+// (j << 4) | the segment's four occupancy bits); a step takes 64 segments of
+// one list per wave, one segment per lane, so every lane of a wave extends the
+// same number of parents.
+constexpr int kDenseThreads = 256;             // step workgroup: four independent waves
 constexpr int kDenseMinL = 6;                  // 4^L slots; short keys take the bucketed store
-constexpr int kDenseMaxL = 12;                 // 4^12 slots: 64 planner regions
+constexpr int kDenseMaxL = 12;
+constexpr int kDenseChunk = 64;                // segments per chunk (one wave)
 constexpr int kDensePlanThreads = 256;
-constexpr int kDensePlanPer = 16;              // bitmap words per planner thread
-constexpr int kDenseRegion = kDensePlanThreads * kDensePlanPer;   // words per planner workgroup
-constexpr int kDenseMaxRegions = 64;           // the planner's regions, all resident at once
+constexpr int kDensePlanIters = 4;             // 16-byte loads (four segments) per planner thread
+constexpr int kDenseRegion = kDensePlanThreads * kDensePlanIters * 4;   // segments per planner workgroup
+constexpr int kDenseMaxRegions = (1 << (2 * (kDenseMaxL - 1))) / kDenseRegion;
+
+struct alignas(32) DenseRec {
+    double2 w;                   // group amplitude
+    unsigned long long tail;     // points L..K-1 of the representative, point L lowest
+    unsigned long long pad;
+};
+
+// Lag-sum tables of one coefficient set: per table 64 entries of (A, B, Ac, Bc),
+// the sums over the table's points of (cre ds, cim ss, dre ds, dim ss), then
+// exp(-D^2 Re c_0) and exp(-D^2 Re delta_0); tables 0.. cover the segment's
+// key points 0..L-2 three at a time (the first point the high digit), the
+// rest the tail points L..K-1 three at a time (the first point the low digit).
+int dense_tab_count(int L, int K);
+size_t dense_tabset_doubles(int L, int K);   // one set, padded to 32 bytes
 
 struct DensePlan {
+    unsigned int n_seg[4];      // nonempty segments holding 1, 2, 3, 4 groups
     unsigned int n_groups;      // groups stored (input of the planned step)
-    unsigned int n_chunks;
-    unsigned int pad;
-    unsigned int n_nonempty;    // nonempty bitmap words
+    unsigned int n_chunks;      // chunks of 64 segments: list 3 first, then 2, 1, 0
+    unsigned int pad[2];
 };
 
 struct DenseArgs {
-    const unsigned long long* bits_in;   // [S/64] slots holding a group (state at t-1)
-    const unsigned long long* tail_in;   // [S]
-    const double2* w_in;                 // [S]
-    unsigned long long* bits_out;        // [S/64] cleared by the planner, set here
-    unsigned long long* tail_out;
-    double2* w_out;
-    const unsigned int* nz_word;         // [n_nonempty] nonempty words of bits_in, in order ...
-    const unsigned int* nz_prefix;       // ... the groups before each ...
-    const unsigned long long* nz_bits;   // ... and the word itself
-    const unsigned int* desc;            // [n_chunks] rank of the word holding the chunk's first group
+    const unsigned int* seg;             // [4][S/4] the planner's lists
+    const DenseRec* rec_in;              // [S] the stored groups
+    DenseRec* rec_out;                   // [S] the step's merged children
+    unsigned char* flag_out;             // [S] set here (all zero before the step)
     const DensePlan* plan;
     double* partials;                    // [partial_stride(4)][grid] each workgroup's sums
-    int max_chunks;
     const double* tables;                // TableLayout
     const double* coef;                  // this step's coefficients: cre, cim, dre, dim [4][K+1]
+    const double* tabset;                // this step's lag-sum tables (dense_tabset_doubles)
+    long long n_segs;                    // S/4
     int L, K, t;
     double theta2;
     unsigned long long qmask;
@@ -57,29 +68,30 @@ struct DenseArgs {
 };
 
 struct DensePlanArgs {
-    const unsigned long long* bits;      // [n_words] the stored groups
-    unsigned long long* bits_next;       // [n_words] cleared for the planned step's output
-    long long n_words;
-    unsigned int* nz_word;
-    unsigned int* nz_prefix;
-    unsigned long long* nz_bits;
-    unsigned int* desc;
+    const unsigned int* flags;           // [S/4] occupancy of the stored groups, a byte per slot
+    unsigned int* flags_spent;           // [S/4] occupancy of the step before, cleared here for the next
+    unsigned int* seg;                   // [4][S/4] lists for the planned step
+    long long n_segs;                    // S/4
     DensePlan* plan;                     // plan of the step to plan
     const DensePlan* plan_prev;          // plan of the step just done (for its counters)
-    int max_chunks;
     int reduce_t;                        // step whose partials to reduce, 0: none
     const double* partials;              // [partial_stride(4)][n_parts]
     int n_parts;                         // workgroups of the step kernel
-    unsigned long long* agg;             // [kDenseMaxRegions] region totals, tagged with the epoch
-    unsigned int epoch;                  // this launch's tag (nonzero in its low 24 bits)
+    unsigned long long* agg;             // [kDenseMaxRegions] region counts, tagged with the epoch
+    unsigned int epoch;                  // this launch's tag, 1..4095
     double2* rho_hist;
     StepStatsDev* stats_hist;
     unsigned int* error;
 };
 
-int dense_chunk_heads();
-int launch_dense_step(const DenseArgs& a, int grid, void* stream);
+int dense_lds_bytes(int L, int K);        // dynamic LDS of the step kernel (lag-sum tables)
+// the lag-sum table sets of coefficient sets 0..n_sets-1 (coef: [n_sets][4][K+1],
+// tables: TableLayout) into out [n_sets][dense_tabset_doubles]
+int launch_dense_tables(const double* coef, const double* tables, int L, int K, int n_sets, double* out,
+                        void* stream);
+int launch_dense_step(const DenseArgs& a, int grid, int lds_bytes, void* stream);
 int launch_dense_plan(const DensePlanArgs& a, void* stream);
-int dense_step_grid(int n_cu);            // persistent workgroups resident at once
+int dense_step_grid(int n_cu, int lds_bytes);   // persistent workgroups resident at once
+int dense_max_chunks(long long n_segs);
 
 }  // namespace quapi_dev

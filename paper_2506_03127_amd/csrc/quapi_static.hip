@@ -23,7 +23,7 @@
 #include "quapi_host.h"
 
 // every buffer of a run; each device holds its own copy until the process ends
-static __device__ __align__(256) unsigned char scratch[64ull << 20];
+static __device__ __align__(256) unsigned char scratch[96ull << 20];
 
 namespace {
 
@@ -52,7 +52,8 @@ int device_scratch(unsigned char** ptr, int* grid) {
         }
         int ncu = 0;
         if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return QUAPI_EDEVICE;
-        const int grid = quapi_dev::dense_step_grid(std::max(ncu, 1));
+        // resident step workgroups with the largest lag-sum tables a run here can need
+        const int grid = quapi_dev::dense_step_grid(std::max(ncu, 1), quapi_dev::dense_lds_bytes(kStaticMaxL, kStaticMaxK));
         if (grid < 1) return QUAPI_EDEVICE;
         g_scratch[dev] = (unsigned char*)p;
         g_grid[dev] = grid;
@@ -71,33 +72,32 @@ struct StaticSetup {
     double rho0[8];
     unsigned long long init_slot[4];
     int K, n_init;
-    long long n_words;
+    long long n_segs;                           // S/4: occupancy words (four bytes) per buffer
     double* tables;
     double* coef;                               // [(K+1)][4][K+1]
-    unsigned long long* bits0;
-    unsigned long long* bits1;
-    unsigned long long* tail0;
-    double2* w0;
+    unsigned int* flag0;                        // occupancy bytes of the two buffers, by segment
+    unsigned int* flag1;
+    quapi_dev::DenseRec* rec0;
     double2* rho_hist;
     StepStatsDev* stats;
     quapi_dev::DensePlan* plan;                 // [2]
-    unsigned long long* agg;                    // [kDenseMaxRegions] planner region totals
+    unsigned long long* agg;                    // [kDenseMaxRegions] planner region counts
     unsigned int* error;
 };
 
 // tables, coefficient sets (as quapi_create forms them: interior partners take
 // the interior column, the time-0 partner the half-window one; the end-point
-// correction swaps the final point's coefficients) and both bitmaps cleared
+// correction swaps the final point's coefficients) and both occupancies cleared
 __global__ __launch_bounds__(256) void static_tables(const StaticSetup a) {
     const int K = a.K, n = K + 1;
     const size_t tid = (size_t)blockIdx.x * 256u + threadIdx.x, nth = (size_t)gridDim.x * 256u;
-    for (size_t k = tid; k < (size_t)a.n_words; k += nth) {
-        a.bits0[k] = 0ull;
-        a.bits1[k] = 0ull;
+    for (size_t k = tid; k < (size_t)a.n_segs; k += nth) {
+        a.flag0[k] = 0u;
+        a.flag1[k] = 0u;
     }
     if (blockIdx.x != 0) return;
     const int i = threadIdx.x;
-    if (i < quapi_dev::kDenseMaxRegions) a.agg[i] = 0ull;   // no tag of an earlier call survives
+    for (int k = i; k < quapi_dev::kDenseMaxRegions; k += 256) a.agg[k] = 0ull;   // no tag of an earlier call survives
     if (i < 32) a.tables[i] = a.k4[i];
     if (i < 4) {
         a.tables[TableLayout::ds(4) + i] = a.ds[i];
@@ -127,9 +127,12 @@ __global__ __launch_bounds__(64) void static_initial(const StaticSetup a) {
     if (i == 0) {
         for (int k = 0; k < a.n_init; ++k) {
             const unsigned long long s = a.init_slot[k];
-            a.bits0[s / 64] |= 1ull << (s % 64);
-            a.tail0[s] = 0ull;
-            a.w0[s] = make_double2(a.init_w[2 * k], a.init_w[2 * k + 1]);
+            reinterpret_cast<unsigned char*>(a.flag0)[s] = 1u;
+            quapi_dev::DenseRec r;
+            r.w = make_double2(a.init_w[2 * k], a.init_w[2 * k + 1]);
+            r.tail = 0ull;
+            r.pad = 0ull;
+            a.rec0[s] = r;
         }
         StepStatsDev s0 = {};
         s0.n_stored = (unsigned long long)a.n_init;
@@ -190,20 +193,19 @@ extern "C" int quapi_run_static(const quapi_params* p, int n_steps, quapi_c64* r
 
     // ---- the run's buffers in scratch
     const unsigned long long S = 1ull << (2 * L);
-    const size_t nw = (size_t)(S / 64);
-    const int max_chunks = (int)(S / quapi_dev::dense_chunk_heads() + 2);
+    const size_t ns = (size_t)(S / 4);
     const size_t n_tab = TableLayout::total(4, K), n_coef = (size_t)(K + 1) * 4 * (K + 1);
     size_t off = 0;
     auto take = [&](size_t bytes) { const size_t o = off; off = align256(off + bytes); return o; };
-    const size_t o_bits0 = take(nw * 8), o_bits1 = take(nw * 8);
-    const size_t o_tail0 = take(S * 8), o_tail1 = take(S * 8);
-    const size_t o_w0 = take(S * 16), o_w1 = take(S * 16);
-    const size_t o_nzw = take((nw + 1) * 4), o_nzp = take((nw + 1) * 4), o_nzb = take((nw + 1) * 8);
-    const size_t o_desc = take((size_t)max_chunks * 4);
+    const size_t o_flag0 = take(S), o_flag1 = take(S);
+    const size_t o_rec0 = take(S * sizeof(quapi_dev::DenseRec)), o_rec1 = take(S * sizeof(quapi_dev::DenseRec));
+    const size_t o_seg = take(S * 4);                    // four lists of S/4 segments
     const size_t o_plan = take(2 * sizeof(quapi_dev::DensePlan));
     const size_t o_agg = take(quapi_dev::kDenseMaxRegions * 8);
     const size_t o_part = take((size_t)grid * quapi_dev::partial_stride(4) * 8);
     const size_t o_tab = take(n_tab * 8), o_coef = take(n_coef * 8);
+    const size_t set_d = quapi_dev::dense_tabset_doubles(L, K);
+    const size_t o_sets = take((size_t)(K + 1) * set_d * 8);
     const size_t o_stats = take((size_t)(n_steps + 1) * sizeof(StepStatsDev));
     const size_t o_err = take(4);
     if (off > kScratchBytes) return QUAPI_ENOMEM;       // beyond the static scratch array
@@ -262,34 +264,32 @@ extern "C" int quapi_run_static(const quapi_params* p, int n_steps, quapi_c64* r
 
     hipStream_t stream = (hipStream_t)p->stream;
     su.K = K;
-    su.n_words = (long long)nw;
+    su.n_segs = (long long)ns;
     su.tables = (double*)(base + o_tab);
     su.coef = (double*)(base + o_coef);
-    su.bits0 = (unsigned long long*)(base + o_bits0);
-    su.bits1 = (unsigned long long*)(base + o_bits1);
-    su.tail0 = (unsigned long long*)(base + o_tail0);
-    su.w0 = (double2*)(base + o_w0);
+    su.flag0 = (unsigned int*)(base + o_flag0);
+    su.flag1 = (unsigned int*)(base + o_flag1);
+    su.rec0 = (quapi_dev::DenseRec*)(base + o_rec0);
     su.rho_hist = (double2*)rho_out;
     su.stats = (StepStatsDev*)(base + o_stats);
     su.plan = (quapi_dev::DensePlan*)(base + o_plan);
     su.agg = (unsigned long long*)(base + o_agg);
     su.error = (unsigned int*)(base + o_err);
-    const unsigned int tgrid = (unsigned int)std::min<size_t>(std::max<size_t>((nw + 255) / 256, 1), 1024);
+    const unsigned int tgrid = (unsigned int)std::min<size_t>(std::max<size_t>((ns + 255) / 256, 1), 1024);
     hipLaunchKernelGGL(static_tables, dim3(tgrid), dim3(256), 0, stream, su);
+    double* sets = (double*)(base + o_sets);
+    if (quapi_dev::launch_dense_tables(su.coef, su.tables, L, K, K + 1, sets, stream) != (int)hipSuccess)
+        return QUAPI_EDEVICE;
     hipLaunchKernelGGL(static_initial, dim3(1), dim3(64), 0, stream, su);
     if (hipGetLastError() != hipSuccess) return QUAPI_EDEVICE;
 
     // ---- t = 0 planned, then each step: the step kernel and the next planner
-    unsigned long long* bits[2] = {su.bits0, (unsigned long long*)(base + o_bits1)};
-    unsigned long long* tail[2] = {su.tail0, (unsigned long long*)(base + o_tail1)};
-    double2* w[2] = {su.w0, (double2*)(base + o_w1)};
+    unsigned char* flag[2] = {(unsigned char*)su.flag0, (unsigned char*)su.flag1};
+    quapi_dev::DenseRec* rec[2] = {su.rec0, (quapi_dev::DenseRec*)(base + o_rec1)};
+    const int lds = quapi_dev::dense_lds_bytes(L, K);
     quapi_dev::DensePlanArgs pa;
-    pa.n_words = (long long)nw;
-    pa.nz_word = (unsigned int*)(base + o_nzw);
-    pa.nz_prefix = (unsigned int*)(base + o_nzp);
-    pa.nz_bits = (unsigned long long*)(base + o_nzb);
-    pa.desc = (unsigned int*)(base + o_desc);
-    pa.max_chunks = max_chunks;
+    pa.seg = (unsigned int*)(base + o_seg);
+    pa.n_segs = (long long)ns;
     pa.partials = (double*)(base + o_part);
     pa.n_parts = grid;
     pa.rho_hist = su.rho_hist;
@@ -297,12 +297,9 @@ extern "C" int quapi_run_static(const quapi_params* p, int n_steps, quapi_c64* r
     pa.error = su.error;
     pa.agg = su.agg;
     quapi_dev::DenseArgs sa;
-    sa.nz_word = pa.nz_word;
-    sa.nz_prefix = pa.nz_prefix;
-    sa.nz_bits = pa.nz_bits;
-    sa.desc = pa.desc;
+    sa.seg = pa.seg;
     sa.partials = (double*)(base + o_part);
-    sa.max_chunks = max_chunks;
+    sa.n_segs = (long long)ns;
     sa.tables = su.tables;
     sa.L = L;
     sa.K = K;
@@ -313,25 +310,23 @@ extern "C" int quapi_run_static(const quapi_params* p, int n_steps, quapi_c64* r
     int cur = 0;
     for (int t = 0; t <= n_steps; ++t) {
         if (t > 0) {
-            sa.bits_in = bits[cur];
-            sa.tail_in = tail[cur];
-            sa.w_in = w[cur];
-            sa.bits_out = bits[1 - cur];
-            sa.tail_out = tail[1 - cur];
-            sa.w_out = w[1 - cur];
+            sa.rec_in = rec[cur];
+            sa.rec_out = rec[1 - cur];
+            sa.flag_out = flag[1 - cur];
             sa.plan = su.plan + (t & 1);
             sa.t = t;
             sa.coef = su.coef + (size_t)(std::min(t, K + 1) - 1) * 4 * n;
-            if (quapi_dev::launch_dense_step(sa, grid, stream) != (int)hipSuccess) return QUAPI_EDEVICE;
+            sa.tabset = sets + (size_t)(std::min(t, K + 1) - 1) * set_d;
+            if (quapi_dev::launch_dense_step(sa, grid, lds, stream) != (int)hipSuccess) return QUAPI_EDEVICE;
             cur = 1 - cur;
         }
         // plan step t+1 from the groups after step t (and reduce step t)
-        pa.bits = bits[cur];
-        pa.bits_next = bits[1 - cur];
+        pa.flags = reinterpret_cast<const unsigned int*>(flag[cur]);
+        pa.flags_spent = reinterpret_cast<unsigned int*>(flag[1 - cur]);
         pa.plan = su.plan + ((t + 1) & 1);
         pa.plan_prev = su.plan + (t & 1);
         pa.reduce_t = t;
-        pa.epoch = (unsigned int)(t % 0xffffff) + 1u;   // nonzero, distinct from the last 2^24 - 2 launches
+        pa.epoch = (unsigned int)(t % 4095) + 1u;   // 1..4095: differs from the launch before
         if (quapi_dev::launch_dense_plan(pa, stream) != (int)hipSuccess) return QUAPI_EDEVICE;
     }
     return QUAPI_OK;

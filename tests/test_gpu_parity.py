@@ -343,20 +343,24 @@ def _run_against_golden(Q, g, gold, n, groups):
     g.sync()
 
 
-def test_structured_bath_full_run(Q):
+@pytest.mark.parametrize("store", ["DIRECT", "BUCKETED"])
+def test_structured_bath_full_run(Q, store):
     """The structured-bath workload (dk_max 24, lags 0..11, theta 1e-8) for all
     1000 steps, launched as the benchmark launches it (its own stream), against
     the stored oracle run: rho(t) of every step at 1e-12, every counter, and
-    the group sets up to step 100 and every tenth step after it."""
+    the group sets up to step 100 and every tenth step after it; on the
+    direct-mapped store and on the bucketed one."""
     import torch
     gold = GoldenRun("structured_bath")
     wl = W.structured_bath()
     n = wl.n_steps
     assert gold.steps == n and gold.ambiguous(n) == 0
     s = torch.cuda.Stream()
+    merge = getattr(Q, f"QUAPI_MERGE_{store}")
     g = Q.Propagator(wl.H, wl.q, wl.dt, wl.K, gold.eta, wl.rho0, mask=wl.mask, theta=wl.theta,
-                     max_steps=n, stream=s.cuda_stream)
-    print(f"[parity] structured bath, {n} steps against the stored oracle run", flush=True)
+                     max_steps=n, stream=s.cuda_stream, merge=merge)
+    assert Q.quapi_info(g.ctx)["store"] == merge
+    print(f"[parity] structured bath ({store}), {n} steps against the stored oracle run", flush=True)
     _run_against_golden(Q, g, gold, n, g.groups)
     assert g.t == n
     r = g.rho_history()
