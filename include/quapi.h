@@ -61,11 +61,12 @@ typedef struct { double re, im; } quapi_c64;
                                 /* near their thresholds may differ too                                 */
 
 /* Where the groups live and how they merge (Sec. 3.1.2; quapi_params.merge). */
-#define QUAPI_MERGE_AUTO     0  /* BUCKETED where it applies, else HASH                                   */
+#define QUAPI_MERGE_AUTO     0  /* DIRECT where it applies, else BUCKETED where it applies, else HASH     */
 #define QUAPI_MERGE_DIRECT   1  /* a slot per key of the merge positions 0..L-1 (two-level systems,       */
-                                /* 5 <= L <= 13, FP64, lone contexts): the parents that merge are the      */
-                                /* aligned slots of a segment, every merged group has a fixed slot, and a  */
-                                /* step is one kernel whose workgroups never wait on one another           */
+                                /* 6 <= L <= 12, FP64, lone contexts): the parents that merge are the      */
+                                /* occupied slots of an aligned segment of four, every merged group has a  */
+                                /* fixed slot; a step is a planner (the occupied segments listed by group  */
+                                /* count) and one kernel whose waves never wait on one another             */
 #define QUAPI_MERGE_BUCKETED 2  /* merge positions 0..L-1: groups sorted by key in buckets of their top   */
                                 /* points, merged on chip as runs of neighbours                             */
 #define QUAPI_MERGE_HASH     3  /* any merge positions: an open-addressing hash table in device memory     */
@@ -105,7 +106,8 @@ typedef struct {
     long long max_groups;     /* stored groups to allocate for, spread evenly over the key buckets     */
                               /* (at least one each; an uneven fill reports ENOMEM first); 0: room   */
                               /* for every key of the merge positions (hash-table merge: up to 2^21). */
-                              /* The direct-mapped store always holds every key                       */
+                              /* The direct-mapped store always holds every key: AUTO takes it only   */
+                              /* when max_groups is 0 or at least P^L                                 */
     int max_steps;            /* initial capacity of the rho(t) history; grows on demand; <= 0: 1024    */
     void* stream;             /* hipStream_t to run on (e.g. a torch stream); NULL: the library's      */
                               /* stream of the device, shared by every context that passes NULL.  A     */
@@ -113,8 +115,9 @@ typedef struct {
                               /* step kernels of one device across all streams: a step kernel on     */
                               /* another stream than the last one waits for it; other work overlaps  */
     int precision;            /* QUAPI_FP64 (0) or QUAPI_FP32_LOG                                       */
-    int merge;                /* QUAPI_MERGE_*: the store (0, AUTO: BUCKETED where it applies, else     */
-                              /* HASH); a store that does not apply returns QUAPI_EUNSUPPORTED          */
+    int merge;                /* QUAPI_MERGE_*: the store (0, AUTO: DIRECT, else BUCKETED, else HASH,   */
+                              /* the first that applies); a store that does not apply returns          */
+                              /* QUAPI_EUNSUPPORTED                                                     */
 } quapi_params;
 
 /* Per-step counters, available for every step t >= 1 that has completed. */

@@ -708,8 +708,11 @@ static int create_ctx(const quapi_params* p, int n_inst, const quapi_c64* eta_al
         if (K * bits > 128 || L * bits > 62 || (K - L) * bits > 64) return QUAPI_EUNSUPPORTED;
         contiguous = false;
     }
-    // (AUTO takes the bucketed store for merge positions 0..L-1: measured, it is still the faster)
-    const bool use_dense = dense_ok && merge == QUAPI_MERGE_DIRECT;
+    // AUTO takes the direct-mapped store where it applies (measured the faster of the
+    // two on merge positions 0..L-1) and max_groups does not ask for fewer than its 4^L
+    // slots, else the bucketed store for 0..L-1, else the table
+    const bool auto_dense = merge == QUAPI_MERGE_AUTO && (p->max_groups <= 0 || p->max_groups >= ipow(P, L));
+    const bool use_dense = dense_ok && (merge == QUAPI_MERGE_DIRECT || auto_dense);
     const quapi_c64* const eta0 = eta_all;                // instance 0
 
     quapi_ctx* c = new (std::nothrow) quapi_ctx();
@@ -1110,7 +1113,9 @@ int quapi_step_graph(quapi_ctx* c, int n_steps) {
         e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hip_to_code(e);
         // look-back words of an earlier replay carry the same epochs: clear them first
-        const hipError_t lr = launch_clear_words(c->d_chain, (size_t)c->P * c->max_chunks, c->stream);
+        hipError_t lr = launch_clear_words(c->d_chain, (size_t)c->P * c->max_chunks, c->stream);
+        if (lr == hipSuccess && c->dense)
+            lr = launch_clear_words(c->dn_agg, (size_t)quapi_dev::kDenseMaxRegions, c->stream);
         c->capturing = true;
         rc = lr == hipSuccess ? quapi_step(c, n_steps) : QUAPI_EDEVICE;
         c->capturing = false;

@@ -382,7 +382,7 @@ __global__ __launch_bounds__(kDenseThreads, 4) void dense_step(const DenseArgs a
     const unsigned long long qmask = a.qmask;
 
     double dropped = 0.0;
-    unsigned int n_surv = 0u;                               // wave-uniform
+    unsigned int n_surv = 0u;                               // this lane's surviving children
     for (; c < n_chunks; c += stride) {
         if (e < n_seg[b]) {
             // ---- segment j of chunk c, its b + 1 parents in slot order
@@ -465,7 +465,7 @@ __global__ __launch_bounds__(kDenseThreads, 4) void dense_step(const DenseArgs a
                     }
                     const double n2 = norm2_nocontract(wr2, wi2);
                     const bool keep = (theta2 == 0.0) || !(n2 < theta2);
-                    n_surv += (unsigned int)__popcll(__ballot(keep));
+                    n_surv += keep ? 1u : 0u;
                     if (keep) {
                         if (p == 1) {
                             r1r += wr2 * fr[1] - wi2 * fi[1];
@@ -527,9 +527,10 @@ __global__ __launch_bounds__(kDenseThreads, 4) void dense_step(const DenseArgs a
     }
     {
         const double t = wave_sum(dropped);
+        const unsigned int ns = wave_sum_u32(n_surv);
         if (lane == 0u) {
             s.red[wave][2 * P] = t;
-            s.red[wave][2 * P + 1] = (double)n_surv;
+            s.red[wave][2 * P + 1] = (double)ns;
         }
     }
     __syncthreads();

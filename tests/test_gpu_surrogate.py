@@ -5,8 +5,9 @@ wherever its held-out error exceeds the tolerance.
 
 The network reaches held-out errors of a few 1e-2 in rho(t) on this machine (the
 loss plateaus near 1e-4 with bf16 hidden products), so at the 1e-3 tolerance
-every query goes to the method; at a tolerance it does meet, the accepted
-cells are answered by the network within it, far faster than the method.
+every query goes to the method.  A third set of points, used neither in
+training nor in accepting cells, measures what the surrogate gives at that
+tolerance.
 """
 import time
 
@@ -60,21 +61,37 @@ def test_fallback_at_the_strict_tolerance_is_the_method(trained):
     assert not used_out.any()
 
 
-def test_gain_where_the_network_is_accepted(trained):
+def test_third_set_at_the_strict_tolerance(trained):
+    """At the specified tolerance (1e-3) the cells are accepted from the
+    held-out points; a third set of points, used neither in training nor in
+    the acceptance, measures what the surrogate gives: points in rejected
+    cells get the method's answer exactly, points in accepted cells the
+    network's, whose error and speed against the method are reported.  The
+    held-out error stands against 1e-3 in the output."""
     S, sur, pts, rho, err = trained
-    sur.tol = float(np.nanmax(sur.cell_error)) * 1.01          # a tolerance the network meets everywhere
+    sur.tol = 1e-3
     sur.validate(pts, rho)
-    assert sur.accepted.all()
-    q = pts[:64]
+    n_acc = int(np.count_nonzero(sur.accepted))
+    print(f"[surrogate] held-out error median {np.median(err):.3e} max {err.max():.3e} against tol 1e-3: "
+          f"{n_acc} of {sur.accepted.size} cells accepted", flush=True)
+    third = sur.box.sample(64, seed=57)
     t0 = time.perf_counter()
-    got, used = sur.query(q)
-    t_net = time.perf_counter() - t0
-    assert used.all()
-    assert np.abs(got - rho[:64]).max() <= sur.tol
-    t0 = time.perf_counter()
-    ref = sur.solver.solve(q)
+    ref = sur.solver.solve(third)
     t_method = time.perf_counter() - t0
-    print(f"[surrogate] 64 points x 51 times: network {1e3 * t_net:.1f} ms, method {1e3 * t_method:.1f} ms "
-          f"({t_method / t_net:.0f}x), max |drho| {np.abs(got - ref).max():.3e} within tol {sur.tol:.3e}",
-          flush=True)
-    assert t_method > 10 * t_net
+    t0 = time.perf_counter()
+    got, used = sur.query(third)
+    t_query = time.perf_counter() - t0
+    # the fallback is the method itself
+    assert np.array_equal(got[~used], ref[~used])
+    n_used = int(np.count_nonzero(used))
+    if n_used:
+        e = np.abs(got[used] - ref[used]).reshape(n_used, -1).max(axis=1)
+        print(f"[surrogate] third set: {n_used} of 64 answered by the network, error median {np.median(e):.3e} "
+              f"max {e.max():.3e}; query {1e3 * t_query:.1f} ms vs method {1e3 * t_method:.1f} ms", flush=True)
+    else:
+        print(f"[surrogate] third set: all 64 answered by the method (no cell meets 1e-3); "
+              f"query {1e3 * t_query:.1f} ms, method {1e3 * t_method:.1f} ms", flush=True)
+    # every answer is the method's or comes from a cell accepted at 1e-3
+    for jq in range(len(third)):
+        cw, cg = sur._cell(third[jq:jq + 1])
+        assert used[jq] == bool(sur.accepted[cw[0], cg[0]])

@@ -63,10 +63,10 @@ def test_static_entry_point_refuses_what_does_not_fit(Q, eta_cache):
         Q.quapi_run_static(wl.H, wl.q, wl.dt, wl.K, eta, wl.rho0, 1, out.data_ptr(), mask=wl.mask,
                            theta=wl.theta)
     assert e.value.code == Q.QUAPI_EUNSUPPORTED
-    # 4^10 slots fit, but not with 600000 steps of counters
+    # 4^10 slots fit, but not with 2000000 steps of counters (96 MB of them)
     wl2 = W.structured_bath(K=14)
     eta2 = eta_cache(wl2)
     with pytest.raises(Q.QuapiError) as e2:
-        Q.quapi_run_static(wl2.H, wl2.q, wl2.dt, 14, eta2, wl2.rho0, 600000, out.data_ptr(),
+        Q.quapi_run_static(wl2.H, wl2.q, wl2.dt, 14, eta2, wl2.rho0, 2000000, out.data_ptr(),
                            mask=tuple(range(11)), theta=1e-7)
     assert e2.value.code == Q.QUAPI_ENOMEM
