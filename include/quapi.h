@@ -76,7 +76,8 @@ typedef struct quapi_ctx quapi_ctx;
 /* Problem definition, copied by quapi_create (the caller keeps ownership of
  * every pointer and may free it after the call). */
 typedef struct {
-    int M;                    /* number of system (DVR) states, 2..3 (M > 3: QUAPI_EUNSUPPORTED)        */
+    int M;                    /* number of system (DVR) states, 2..4 (M > 4: QUAPI_EUNSUPPORTED; M = 4, */
+                              /* 16 pairs, runs on the hash-table merge only)                           */
     const quapi_c64* H;       /* M*M Hermitian system Hamiltonian H_S (eq. tot_ham), used as given;     */
                               /* rejected if |H_ij - conj(H_ji)| > 1e-12 max(1, max|H|)                  */
     const double* q;          /* M coupling eigenvalues q_i of the DVR states (eq. tot_ham)             */
@@ -90,10 +91,11 @@ typedef struct {
                               /* eta[1*(K+1)+0] is the end-point self term (eq. inf_fun)                 */
     const int* mask;          /* MACGIC mask (Sec. 2.1): n_mask sorted lags, mask[0]=0, mask[1]=1,      */
                               /* mask[n_mask-1] <= K-1; NULL: every lag 0..K-1.  Merge positions       */
-                              /* 0..L-1 (L >= 2) run on the bucketed store; any other set merges       */
-                              /* through a hash table and needs the history in 128 bits, the merge     */
-                              /* positions in 62 and the other positions in 64 (M = 2: K <= 63,        */
-                              /* at most 31 merge and 32 other positions; M = 3: half of each)          */
+                              /* 0..L-1 (L >= 2, M <= 3) run on the direct-mapped or bucketed store    */
+                              /* (see merge); any other set merges through a hash table and needs the  */
+                              /* history in 128 bits, the merge positions in 62 and the other          */
+                              /* positions in 64 (M = 2: K <= 63, at most 31 merge and 32 other        */
+                              /* positions; M = 3 and 4: half of each)                                 */
     int n_mask;
     double theta;             /* filter: drop a child when |w|^2 < theta^2; 0 disables                  */
     const quapi_c64* rho0;    /* M*M initial reduced density matrix                                     */
@@ -148,7 +150,7 @@ typedef struct {
 
 /* Create a context and its initial state t = 0 (one path per nonzero
  * element of rho0, weighted by the initial point's self term).
- * Errors: EINVAL (bad argument), EUNSUPPORTED (M > 3; merge positions 0..L-1
+ * Errors: EINVAL (bad argument), EUNSUPPORTED (M > 4; merge positions 0..L-1
  * with L bits-per-point > 62 bits or a tail over 64 bits; other merge positions
  * with a history over 128 bits, a key over 62 bits or other positions over 64
  * bits; coefficients whose influence phases could reach 1e5 radians in one

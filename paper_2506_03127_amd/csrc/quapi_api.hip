@@ -646,7 +646,7 @@ static int create_ctx(const quapi_params* p, int n_inst, const quapi_c64* eta_al
     if (!(p->theta >= 0) || !is_finite_d(p->theta)) return QUAPI_EINVAL;
     if (p->mode != QUAPI_PRE && p->mode != QUAPI_POST) return QUAPI_EINVAL;
     if (p->precision != QUAPI_FP64 && p->precision != QUAPI_FP32_LOG) return QUAPI_EINVAL;
-    if (M > 3) return QUAPI_EUNSUPPORTED;
+    if (M > 4) return QUAPI_EUNSUPPORTED;
     if (!quapi_host::hermitian_ok(M, (const double*)p->H)) return QUAPI_EINVAL;
     for (int j = 0; H_all && j < n_inst; ++j)
         if (!quapi_host::hermitian_ok(M, (const double*)(H_all + (size_t)M * M * j))) return QUAPI_EINVAL;
@@ -680,7 +680,8 @@ static int create_ctx(const quapi_params* p, int n_inst, const quapi_c64* eta_al
     // hash-table path, which keeps each history in one or two 64-bit words, the
     // key in 62 bits and the points at the other positions in one 64-bit word
     // (the FP32 precision form is built on the hash-table merge only)
-    bool contiguous = pos.size() >= 2 && p->precision == QUAPI_FP64;
+    // (four levels, 16 pairs of 4-bit points, run on the hash-table merge, which takes any P)
+    bool contiguous = pos.size() >= 2 && p->precision == QUAPI_FP64 && M <= 3;
     for (size_t i = 0; i < pos.size(); ++i)
         if (pos[i] != (int)i) contiguous = false;
     const int L = (int)pos.size();
@@ -975,7 +976,8 @@ static int create_ctx(const quapi_params* p, int n_inst, const quapi_c64* eta_al
     // chunks needs every workgroup of the grid resident); QUAPI_BLOCKS_PER_CU lowers it
     int per_cu = 0;
     if (const char* env = std::getenv("QUAPI_BLOCKS_PER_CU")) per_cu = std::max(1, std::min(16, std::atoi(env)));
-    c->grid = quapi_dev::step_grid(P, std::max(ncu, 1), per_cu, n_inst > 1);
+    // (the bucketed step kernel is built for P = 4 and 9; the hash-table merge has grids of its own)
+    c->grid = c->sparse ? 1 : quapi_dev::step_grid(P, std::max(ncu, 1), per_cu, n_inst > 1);
     if (c->grid < 1) {
         quapi_destroy(c);
         return QUAPI_EDEVICE;

@@ -756,6 +756,8 @@ int launch_sparse_form(const SparseArgs& a, hipStream_t st, hipEvent_t ev) {
     else if (a.P == 4 && a.hw == 2) launch_sparse<4, 2, 2, F32>(a, st, ev);
     else if (a.P == 9 && a.hw == 1) launch_sparse<9, 4, 1, F32>(a, st, ev);
     else if (a.P == 9 && a.hw == 2) launch_sparse<9, 4, 2, F32>(a, st, ev);
+    else if (a.P == 16 && a.hw == 1) launch_sparse<16, 4, 1, F32>(a, st, ev);
+    else if (a.P == 16 && a.hw == 2) launch_sparse<16, 4, 2, F32>(a, st, ev);
     else return (int)hipErrorInvalidValue;
     return (int)hipGetLastError();
 }

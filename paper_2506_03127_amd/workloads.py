@@ -116,6 +116,17 @@ def batched_scan(n_inst: int = 64, seed: int = 11, n_steps: int = 1000, K: int =
     return wl, baths
 
 
+def four_level(seed: int = 11, K: int = 5, n_exact: int = 3, theta: float = 1e-7,
+               n_steps: int = 40) -> Workload:
+    """Four-level system (16 forward/backward pairs) with a seeded random Hermitian
+    H_S (entries ~ N(0, 0.5)) and equally spaced coupling eigenvalues."""
+    return Workload(name=f"four_level_K{K}", H=random_hermitian(4, 0.5, seed),
+                    q=np.array([1.5, 0.5, -0.5, -1.5]),
+                    bath=BathSpec(0.05, 5.0, ((1.0, 0.05, 0.1),)), beta=5.0, dt=0.2, K=K,
+                    mask=tuple(range(n_exact)), theta=theta, rho0=ground_projector(4),
+                    n_steps=n_steps, mode="pre")
+
+
 def three_level(seed: int = 7, K: int = 16, n_exact: int = 6, theta: float = 1e-8,
                 n_steps: int = 200) -> Workload:
     """Three-level system with a seeded random Hermitian H_S (entries ~ N(0, 0.5))."""

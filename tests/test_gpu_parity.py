@@ -166,6 +166,24 @@ def test_three_level_system(Q, eta_cache):
     assert_groups(o, g)
 
 
+@pytest.mark.parametrize("mode,K,mask,theta,n", [
+    ("post", 3, None, 0.0, 12),            # exact iQUAPI: 16^3 groups
+    ("pre", 5, (0, 1, 2), 1e-7, 24),       # MACGIC pre-merging on lags 0..2
+    ("pre", 6, (0, 1, 2, 4), 1e-7, 20),    # a mask with a distant lag
+], ids=["post-K3-full", "pre-K5-lags-0-2", "pre-K6-sparse"])
+def test_four_level_system(Q, eta_cache, mode, K, mask, theta, n):
+    """Four levels (16 pairs of 4-bit points) on the hash-table merge, against
+    the oracle: rho(t), counters and groups."""
+    wl = W.four_level(K=K)
+    eta = eta_cache(wl, K)
+    o, g = run_both(Q, wl.H, wl.q, wl.dt, K, eta, wl.rho0, n, mode=mode, mask=mask, theta=theta)
+    assert Q.quapi_info(g.ctx)["store"] == Q.QUAPI_MERGE_HASH
+    assert ambiguous(o, n) == 0
+    assert_rho(o, g, n)
+    assert_stats(o, g, n)
+    assert_groups(o, g)
+
+
 @pytest.mark.parametrize("make,mode,K,mask,theta,n", [
     # long memory: the two-level history sums take the per-lag loop instead of the tables
     (W.structured_bath, "pre", 40, tuple(range(12)), 1e-8, 14),

@@ -92,12 +92,18 @@ def test_create_rejects_invalid_input_without_device(Q):
     assert _create_code(Q, eta=eta_nan) == Q.QUAPI_EINVAL
     # valid but outside this build: merge positions that are not 0..L-1 with more
     # other points than one 64-bit word holds (38 two-bit points), a key over 62
-    # bits (32 two-bit merge positions), M = 4
+    # bits (32 two-bit merge positions), M = 5, and M = 4 on a store other than the
+    # hash table or with a history over 128 bits (33 four-bit points)
     assert _create_code(Q, dk_max=40, eta=np.zeros((3, 41)), mask=[0, 1, 3]) == Q.QUAPI_EUNSUPPORTED
     mask64 = list(range(31)) + [40, 63]
     assert _create_code(Q, dk_max=64, eta=np.zeros((3, 65)), mask=mask64) == Q.QUAPI_EUNSUPPORTED
+    H5 = W.random_hermitian(5, 0.5, 1)
+    assert _create_code(Q, H=H5, q=[1, 0.5, 0, -0.5, -1], rho0=W.ground_projector(5)) == Q.QUAPI_EUNSUPPORTED
     H4 = W.random_hermitian(4, 0.5, 1)
-    assert _create_code(Q, H=H4, q=[1, 0.5, -0.5, -1], rho0=W.ground_projector(4)) == Q.QUAPI_EUNSUPPORTED
+    four = dict(H=H4, q=[1, 0.5, -0.5, -1], rho0=W.ground_projector(4))
+    for merge in (Q.QUAPI_MERGE_DIRECT, Q.QUAPI_MERGE_BUCKETED):
+        assert _create_code(Q, merge=merge, **four) == Q.QUAPI_EUNSUPPORTED
+    assert _create_code(Q, dk_max=33, eta=np.zeros((3, 34)), **four) == Q.QUAPI_EUNSUPPORTED
 
 
 def _create_batch_code(Q, n_inst=2, **over):

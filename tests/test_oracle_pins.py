@@ -126,6 +126,20 @@ def test_three_level_post_full_mask_brute_force(oracle_mod):
         assert np.abs(o.rho(N) - brute_rho(H, [1, 0, -1], 0.2, K, eta, rho0, N)).max() < 1e-14
 
 
+def test_four_level_post_full_mask_brute_force(oracle_mod):
+    """Four levels (16 forward/backward pairs): post-merging on every lag is the
+    exact path sum of eq. quapi_red_rho, against brute force."""
+    K = 2
+    H = W.random_hermitian(4, 0.5, 9)
+    q = [1.5, 0.5, -0.5, -1.5]
+    eta = structured_eta(K)
+    rho0 = W.ground_projector(4)
+    o = oracle.Oracle(H, q, 0.2, K, eta, rho0, mode=POST)
+    o.step(3)
+    for N in range(4):
+        assert np.abs(o.rho(N) - brute_rho(H, q, 0.2, K, eta, rho0, N)).max() < 1e-14
+
+
 def test_pre_equals_brute_force_before_first_merge(oracle_mod):
     """With mask {0..E-1} the pre-merge first merges at step E+1 (when the paths
     hold more than E-1 points); before that every mode is the exact path sum."""
