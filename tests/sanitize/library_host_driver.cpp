@@ -139,8 +139,11 @@ int main() {
         en[3].re = NAN;
         p.eta = en.data();
         expect(create(p) == QUAPI_EINVAL, "NaN eta");
+        Case c5(5, 6);
+        expect(create(c5.p) == QUAPI_EUNSUPPORTED, "M = 5");
         Case c4(4, 6);
-        expect(create(c4.p) == QUAPI_EUNSUPPORTED, "M = 4");
+        c4.p.merge = QUAPI_MERGE_BUCKETED;
+        expect(create(c4.p) == QUAPI_EUNSUPPORTED, "M = 4 on the bucketed store");
         Case c3(3, 40);
         c3.mask.assign({0, 1, 20});
         c3.p.mask = c3.mask.data();
