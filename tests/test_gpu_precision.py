@@ -83,7 +83,7 @@ def test_fp32_form_against_oracle(Q, eta_cache, make, mode, K, mask, theta, n):
 
 def test_fp32_form_against_fp64_form(Q, eta_cache):
     """Both forms on the same GPU, on the structured bath at dk_max = 24 with lags
-    0..11 kept (the FP64 form on the bucketed store), 200 steps, both comparing
+    0..11 kept (the FP64 form on the direct-mapped store), 200 steps, both comparing
     12 mantissa bits for the representative."""
     wl = W.structured_bath()
     eta = eta_cache(wl, wl.K)
@@ -102,3 +102,38 @@ def test_fp32_form_against_fp64_form(Q, eta_cache):
     assert err < FP32_RHO_TOL
     s64, s32 = g64.stats(1, n), g32.stats(1, n)
     assert all(abs(a["n_groups"] - b["n_groups"]) <= max(2, 1e-3 * a["n_groups"]) for a, b in zip(s64, s32))
+
+
+def test_long_memory_fp64_spread_over_qbits_and_the_fp32_form(Q, eta_cache):
+    """The long-memory workload (dk_max 40, lags 0..11, 16, 24 and 32 exact,
+    theta 1e-9) for 200 steps: its FP64 answer itself depends on how finely the
+    representative's |w|^2 is compared (Sec. 3.1.2; reading A10), because a
+    flipped representative carries other points in its tail.  This records that
+    spread over qbits 32, 40 and 44 and states the FP32 form's difference from
+    the FP64 form (both at qbits 40) against it: on this workload the 1e-5 bar of
+    the precision form cannot be judged by rho(t), the method's own sensitivity
+    being far larger."""
+    wl = W.long_memory()
+    eta = eta_cache(wl, wl.K)
+    n = 200
+    kw = dict(mask=wl.mask, theta=wl.theta, max_steps=n, max_groups=48 << 20)
+    r64 = {}
+    for qb in (32, 40, 44):
+        g = Q.Propagator(wl.H, wl.q, wl.dt, wl.K, eta, wl.rho0, qbits=qb, **kw)
+        g.step(n)
+        r64[qb] = g.rho_history(0, n + 1)
+        g.close()
+    g = Q.Propagator(wl.H, wl.q, wl.dt, wl.K, eta, wl.rho0, qbits=FP32_QBITS, precision=Q.QUAPI_FP32_LOG, **kw)
+    g.step(n)
+    r32 = g.rho_history(0, n + 1)
+    g.close()
+    spread = max(np.abs(r64[a] - r64[b]).max() for a in r64 for b in r64)
+    d32 = np.abs(r32 - r64[FP32_QBITS]).max()
+    print(f"[fp32] long memory, {n} steps: FP64 spread over qbits 32/40/44 = {spread:.3e}; "
+          f"FP32 form vs FP64 form at qbits {FP32_QBITS} = {d32:.3e}; "
+          f"|drho(qbits 32 vs 40)| = {np.abs(r64[32] - r64[40]).max():.3e}, "
+          f"|drho(44 vs 40)| = {np.abs(r64[44] - r64[40]).max():.3e}", flush=True)
+    # the method's own sensitivity to the quantisation is far above the precision
+    # form's bar, and the FP32 form's difference is of that order, not above it
+    assert spread > 100 * FP32_RHO_TOL
+    assert d32 < 3.0 * spread
