@@ -97,15 +97,19 @@ STORE_KERNELS = {
     "hash": {"kernel": "sparse_expand", "kernel_label": "sparse_expand",
              "sources": [CSRC + "quapi_sparse.hip", CSRC + "quapi_sparse.h", CSRC + "quapi_device.h",
                          CSRC + "quapi_host.h"]},
+    "partition": {"kernel": "sparse_expand", "kernel_label": "sparse_expand (partition merge)",
+                  "sources": [CSRC + "quapi_sparse.hip", CSRC + "quapi_sparse.h", CSRC + "quapi_device.h",
+                              CSRC + "quapi_host.h"]},
 }
-STORE_NAMES = {1: "direct", 2: "bucketed", 3: "hash"}
+STORE_NAMES = {1: "direct", 2: "bucketed", 3: "hash", 4: "partition"}
 
 
 def workload_spec(name: str, precision: str, store: str = "bucketed") -> dict:
     spec = dict(WORKLOADS[name])
     if store in STORE_KERNELS and precision != "fp32":
         spec.update(STORE_KERNELS[store])
-        spec["traffic"] = f"{spec['kernel']}_{name.replace('-', '_')}_traffic.json"
+        tag = "_partition" if store == "partition" else ""
+        spec["traffic"] = f"{spec['kernel']}{tag}_{name.replace('-', '_')}_traffic.json"
     if precision == "fp32":
         # the FP32 form runs every mask on the hash-table merge
         spec.update({"kernel": "sparse_expand", "kernel_label": "sparse_expand (FP32 form)",
@@ -224,7 +228,7 @@ def main():
                     help="each propagation as one HIP graph (quapi_step_graph), recorded in the warm-up")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64",
                     help="fp32: the FP32 log-domain form (hash-table merge)")
-    ap.add_argument("--merge", choices=["auto", "direct", "bucketed", "hash"], default="auto",
+    ap.add_argument("--merge", choices=["auto", "direct", "bucketed", "hash", "partition"], default="auto",
                     help="the store (QUAPI_MERGE_*); auto: the library's choice")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="one plain device copy of this size after the timed work (PMC calibration)")
@@ -258,7 +262,8 @@ def main():
     stream = torch.cuda.Stream()
     precision = quapi.QUAPI_FP32_LOG if args.precision == "fp32" else quapi.QUAPI_FP64
     merge = {"auto": quapi.QUAPI_MERGE_AUTO, "direct": quapi.QUAPI_MERGE_DIRECT,
-             "bucketed": quapi.QUAPI_MERGE_BUCKETED, "hash": quapi.QUAPI_MERGE_HASH}[args.merge]
+             "bucketed": quapi.QUAPI_MERGE_BUCKETED, "hash": quapi.QUAPI_MERGE_HASH,
+             "partition": quapi.QUAPI_MERGE_PARTITION}[args.merge]
     baths = None
     if args.workload == "batched-scan":
         if args.precision != "fp64":
@@ -358,7 +363,8 @@ def main():
                      "peaks_w0_gamma_lambda": [list(p) for p in b.peaks]},
             "beta": wl.beta, "dt": wl.dt, **system, "mode": wl.mode + "-merging",
             "precision": args.precision, "merge": {"direct": "direct-mapped store", "bucketed": "bucketed store",
-                                                   "hash": "hash table"}[store],
+                                                   "hash": "hash table",
+                                                   "partition": "hash-table store, partition merge"}[store],
             "record_bytes": record_bytes, "instances": n_inst, "chunk_run": chunk_run,
             "hip_graph": bool(args.graph),
         },

@@ -70,6 +70,10 @@ typedef struct { double re, im; } quapi_c64;
 #define QUAPI_MERGE_BUCKETED 2  /* merge positions 0..L-1: groups sorted by key in buckets of their top   */
                                 /* points, merged on chip as runs of neighbours                             */
 #define QUAPI_MERGE_HASH     3  /* any merge positions: an open-addressing hash table in device memory     */
+#define QUAPI_MERGE_PARTITION 4 /* the hash table's store, merged without a table: each pass's merged      */
+                                /* children go to partitions by the hash of their key, and each partition  */
+                                /* merges in on-chip memory (no device-memory atomics but one counter     */
+                                /* per entry, no table scan)                                               */
 
 typedef struct quapi_ctx quapi_ctx;
 

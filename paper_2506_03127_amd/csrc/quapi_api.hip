@@ -48,17 +48,26 @@ struct quapi_ctx {
     bool f32 = false;            // FP32 precision form: amplitudes as FP32 (ln|w|, arg w)
     float2* sp_wf[2] = {nullptr, nullptr};
     long long sp_cap = 0;        // group capacity
+    unsigned long long sp_seg_cap = 0;           // groups per segment (kSegs segments)
     uint64_t* sp_h[2] = {nullptr, nullptr};
     double2* sp_w[2] = {nullptr, nullptr};
-    unsigned int* sp_count = nullptr;            // [2] by step parity
+    unsigned int* sp_count = nullptr;            // [seg_counter(2, 0)] per segment, by step parity
     quapi_dev::SpSlot* sp_slot = nullptr;        // [sp_tsize] hash table
     unsigned long long sp_tsize = 0;
+    bool sp_part = false;                         // partition merge in place of the table
+    unsigned int sp_n_part = 0;                   // partitions allocated
+    unsigned int* sp_pcount = nullptr;            // [sp_n_part]
+    unsigned long long* sp_pkey = nullptr;        // [sp_n_part * kPartCap] entries ...
+    unsigned long long* sp_pbest = nullptr;
+    unsigned long long* sp_pother = nullptr;      // (unpacked form only)
+    double2* sp_pw = nullptr;
     unsigned long long* sp_tN = nullptr;         // unpacked form only
     unsigned int* sp_cslot = nullptr;
     unsigned long long* sp_cN = nullptr;
     unsigned long long* sp_cq = nullptr;
     double* sp_partials = nullptr;
     int sp_grid = 0;
+    int sp_grid_merge = 0;                       // partition merge
 
     // direct-mapped store (two-level systems, merge positions 0..L-1, short keys)
     bool dense = false;
@@ -167,7 +176,12 @@ int upload_initial_sparse(quapi_ctx* c) {
     const size_t hw = (size_t)c->sp_hw;
     std::vector<uint64_t> h(n0 * hw, 0ull);
     for (size_t k = 0; k < n0; ++k) h[k * hw] = (uint64_t)c->init_pair[k];
-    const unsigned int cnt[2] = {(unsigned int)n0, 0u};
+    // the initial groups fill segments 0, 1, ... in turn
+    std::vector<unsigned int> cnt((size_t)quapi_dev::seg_counter(2, 0), 0u);
+    for (int s = 0; s < quapi_dev::kSegs; ++s) {
+        const unsigned long long lo = (unsigned long long)s * c->sp_seg_cap;
+        if (lo < n0) cnt[quapi_dev::seg_counter(0, s)] = (unsigned int)std::min<unsigned long long>(n0 - lo, c->sp_seg_cap);
+    }
     const size_t ts = (size_t)c->sp_tsize;
     hipError_t e = hipSuccess;
     // the FP32 precision form stores (ln|w|, arg w)
@@ -183,10 +197,13 @@ int upload_initial_sparse(quapi_ctx* c) {
         else if (e == hipSuccess)
             e = hipMemcpyAsync(c->sp_w[0], c->init_w.data(), n0 * sizeof(double2), hipMemcpyHostToDevice, c->stream);
     }
-    if (e == hipSuccess) e = hipMemcpyAsync(c->sp_count, cnt, sizeof cnt, hipMemcpyHostToDevice, c->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(c->sp_slot, 0, ts * sizeof(quapi_dev::SpSlot), c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->sp_count, cnt.data(), cnt.size() * sizeof(unsigned int), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess && c->sp_slot) e = hipMemsetAsync(c->sp_slot, 0, ts * sizeof(quapi_dev::SpSlot), c->stream);
     if (e == hipSuccess && c->sp_tN)
         e = hipMemsetAsync(c->sp_tN, 0xff, ts * sizeof(unsigned long long), c->stream);
+    if (e == hipSuccess && c->sp_pcount)
+        e = hipMemsetAsync(c->sp_pcount, 0, (size_t)c->sp_n_part * sizeof(unsigned int), c->stream);
     // the copies read host vectors of this frame: complete them before returning
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     return hip_to_code(e);
@@ -375,7 +392,16 @@ int step_sparse(quapi_ctx* c, int n_steps) {
     a.cslot = c->sp_cslot;
     a.cN = c->sp_cN;
     a.cq = c->sp_cq;
+    a.part = c->sp_part ? 1 : 0;
+    a.grid_merge = c->sp_grid_merge;
+    a.n_part_max = c->sp_n_part;
+    a.pcount = c->sp_pcount;
+    a.pkey = c->sp_pkey;
+    a.pbest = c->sp_pbest;
+    a.pother = c->sp_pother;
+    a.pw = c->sp_pw;
     a.cap = c->sp_cap;
+    a.seg_cap = c->sp_seg_cap;
     a.P = c->P;
     a.K = c->K;
     a.theta2 = c->theta * c->theta;
@@ -698,13 +724,14 @@ static int create_ctx(const quapi_params* p, int n_inst, const quapi_c64* eta_al
     // 4^13 slots of 24 B) take the direct-mapped store unless the caller asks for
     // another; the bucketed store serves every contiguous mask, the hash table every mask
     const int merge = p->merge;
-    if (merge < QUAPI_MERGE_AUTO || merge > QUAPI_MERGE_HASH) return QUAPI_EINVAL;
+    if (merge < QUAPI_MERGE_AUTO || merge > QUAPI_MERGE_PARTITION) return QUAPI_EINVAL;
+    const bool hash_store = merge == QUAPI_MERGE_HASH || merge == QUAPI_MERGE_PARTITION;
     const bool dense_ok =
         contiguous && !batch && M == 2 && L >= quapi_dev::kDenseMinL && L <= quapi_dev::kDenseMaxL;
     if (merge == QUAPI_MERGE_DIRECT && !dense_ok) return QUAPI_EUNSUPPORTED;
     if (merge == QUAPI_MERGE_BUCKETED && !contiguous) return QUAPI_EUNSUPPORTED;
-    if (merge == QUAPI_MERGE_HASH && batch) return QUAPI_EUNSUPPORTED;
-    if (merge == QUAPI_MERGE_HASH && contiguous) {
+    if (hash_store && batch) return QUAPI_EUNSUPPORTED;
+    if (hash_store && contiguous) {
         // the hash table takes any merge positions
         if (K * bits > 128 || L * bits > 62 || (K - L) * bits > 64) return QUAPI_EUNSUPPORTED;
         contiguous = false;
@@ -732,6 +759,7 @@ static int create_ctx(const quapi_params* p, int n_inst, const quapi_c64* eta_al
     c->sparse = !contiguous;
     c->dense = use_dense;
     c->f32 = p->precision == QUAPI_FP32_LOG;
+    c->sp_part = c->sparse && merge == QUAPI_MERGE_PARTITION;
     c->qpos = pos;
     if (c->sparse) {
         // the other positions, oldest first; the representative word packs
@@ -922,21 +950,38 @@ static int create_ctx(const quapi_params* p, int n_inst, const quapi_c64* eta_al
         long long scap = p->max_groups > 0 ? p->max_groups : std::min(ipow(P, std::min(L, 12)), 1ll << 21);
         scap = std::max((long long)c->init_pair.size(), std::min(scap, ((1ll << 31) - 1) / P));
         c->sp_cap = scap;
+        // segments: an eighth over an even share, and room for a few merge tiles
+        const unsigned long long seg_cap = ((unsigned long long)scap * 9 / 8 + quapi_dev::kSegs - 1) / quapi_dev::kSegs + 4096;
+        c->sp_seg_cap = seg_cap;
+        const size_t n_slots = (size_t)seg_cap * quapi_dev::kSegs;
         unsigned long long ts = quapi_dev::kMinTable;
         while (ts < 2ull * (unsigned long long)P * (unsigned long long)scap) ts <<= 1;
         c->sp_tsize = ts;
         for (int b = 0; b < 2 && !rc; ++b) {
-            rc = dev_alloc(c, &c->sp_h[b], (size_t)scap * c->sp_hw);
-            if (!rc && c->f32) rc = dev_alloc(c, &c->sp_wf[b], (size_t)scap);
-            if (!rc && !c->f32) rc = dev_alloc(c, &c->sp_w[b], (size_t)scap);
+            rc = dev_alloc(c, &c->sp_h[b], n_slots * c->sp_hw);
+            if (!rc && c->f32) rc = dev_alloc(c, &c->sp_wf[b], n_slots);
+            if (!rc && !c->f32) rc = dev_alloc(c, &c->sp_w[b], n_slots);
         }
-        if (!rc) rc = dev_alloc(c, &c->sp_count, 2);
+        if (!rc) rc = dev_alloc(c, &c->sp_count, (size_t)quapi_dev::seg_counter(2, 0));
+        if (c->sp_part) {
+            // partitions for the children of a full store, one per kPartLoad
+            unsigned long long np = 1;
+            while (np * quapi_dev::kPartLoad < (unsigned long long)P * (unsigned long long)scap) np <<= 1;
+            c->sp_n_part = (unsigned int)np;
+            const size_t ne = (size_t)np * quapi_dev::kPartCap;
+            if (!rc) rc = dev_alloc(c, &c->sp_pcount, (size_t)np);
+            if (!rc) rc = dev_alloc(c, &c->sp_pkey, ne);
+            if (!rc) rc = dev_alloc(c, &c->sp_pbest, ne);
+            if (!rc && !c->sp_packed) rc = dev_alloc(c, &c->sp_pother, ne);
+            if (!rc) rc = dev_alloc(c, &c->sp_pw, ne);
+        } else {
         if (!rc) rc = dev_alloc(c, &c->sp_slot, (size_t)ts);
         if (!c->sp_packed) {
             if (!rc) rc = dev_alloc(c, &c->sp_tN, (size_t)ts);
             if (!rc) rc = dev_alloc(c, &c->sp_cslot, (size_t)scap * P);
             if (!rc) rc = dev_alloc(c, &c->sp_cN, (size_t)scap * P);
             if (!rc) rc = dev_alloc(c, &c->sp_cq, (size_t)scap * P);
+        }
         }
     }
     c->hist_cap = p->max_steps > 0 ? p->max_steps : 1024;
@@ -996,7 +1041,9 @@ static int create_ctx(const quapi_params* p, int n_inst, const quapi_c64* eta_al
         }
     }
     if (c->sparse) {
-        c->sp_grid = 4 * std::max(ncu, 1);
+        // a multiple of kSegs, so that every segment has as many writers
+        c->sp_grid = (4 * std::max(ncu, 1) + quapi_dev::kSegs - 1) / quapi_dev::kSegs * quapi_dev::kSegs;
+        c->sp_grid_merge = quapi_dev::sparse_merge_grid(P, c->sp_hw, c->f32, ncu);
         if (dev_alloc(c, &c->sp_partials, (size_t)c->sp_grid * quapi_dev::partial_stride(P)) != QUAPI_OK) {
             quapi_destroy(c);
             return QUAPI_ENOMEM;
@@ -1278,27 +1325,40 @@ int quapi_batch_groups(quapi_ctx* c, int inst, long long cap, unsigned char* his
     const int rc = sync_ctx(c);
     if (rc == QUAPI_EDEVICE) return rc;
     if (c->sparse) {
-        unsigned int cnt2[2] = {0u, 0u};
-        hipError_t e = hipMemcpy(cnt2, c->sp_count, sizeof cnt2, hipMemcpyDeviceToHost);
+        std::vector<unsigned int> cnt((size_t)quapi_dev::seg_counter(2, 0));
+        hipError_t e = hipMemcpy(cnt.data(), c->sp_count, cnt.size() * sizeof(unsigned int), hipMemcpyDeviceToHost);
         if (e != hipSuccess) return hip_to_code(e);
-        const long long n = cnt2[c->t & 1];
+        // the segments' groups, one after the other
+        unsigned long long seg_n[quapi_dev::kSegs];
+        long long n = 0;
+        for (int s = 0; s < quapi_dev::kSegs; ++s) {
+            seg_n[s] = std::min<unsigned long long>(cnt[quapi_dev::seg_counter(c->t & 1, s)], c->sp_seg_cap);
+            n += (long long)seg_n[s];
+        }
         *n_out = n;
         if (cap == 0 || n == 0) return QUAPI_OK;
         const int hw = c->sp_hw;
         std::vector<uint64_t> hh((size_t)n * hw);
         std::vector<double2> ww((size_t)n);
-        e = hipMemcpy(hh.data(), c->sp_h[c->cur], hh.size() * 8, hipMemcpyDeviceToHost);
-        if (e == hipSuccess && c->f32) {
-            std::vector<float2> wl((size_t)n);
-            e = hipMemcpy(wl.data(), c->sp_wf[c->cur], (size_t)n * sizeof(float2), hipMemcpyDeviceToHost);
-            for (long long r = 0; r < n; ++r) {
-                const double m = std::exp((double)wl[r].x);
-                ww[r] = make_double2(m * std::cos((double)wl[r].y), m * std::sin((double)wl[r].y));
-            }
-        } else if (e == hipSuccess) {
-            e = hipMemcpy(ww.data(), c->sp_w[c->cur], (size_t)n * 16, hipMemcpyDeviceToHost);
+        std::vector<float2> wl(c->f32 ? (size_t)n : 0);
+        size_t r0 = 0;
+        for (int s = 0; s < quapi_dev::kSegs && e == hipSuccess; ++s) {
+            if (!seg_n[s]) continue;
+            const size_t src = (size_t)s * c->sp_seg_cap;
+            e = hipMemcpy(hh.data() + r0 * hw, c->sp_h[c->cur] + src * hw, (size_t)seg_n[s] * hw * 8,
+                          hipMemcpyDeviceToHost);
+            if (e == hipSuccess && c->f32)
+                e = hipMemcpy(wl.data() + r0, c->sp_wf[c->cur] + src, (size_t)seg_n[s] * sizeof(float2),
+                              hipMemcpyDeviceToHost);
+            else if (e == hipSuccess)
+                e = hipMemcpy(ww.data() + r0, c->sp_w[c->cur] + src, (size_t)seg_n[s] * 16, hipMemcpyDeviceToHost);
+            r0 += (size_t)seg_n[s];
         }
         if (e != hipSuccess) return hip_to_code(e);
+        for (size_t r = 0; r < wl.size(); ++r) {
+            const double m = std::exp((double)wl[r].x);
+            ww[r] = make_double2(m * std::cos((double)wl[r].y), m * std::sin((double)wl[r].y));
+        }
         const unsigned long long dm = (1ull << c->bits) - 1;
         for (long long r = 0; r < n && r < cap; ++r) {
             unsigned char* row = hist + (size_t)r * c->K;
@@ -1398,7 +1458,8 @@ int quapi_info(quapi_ctx* c, quapi_info_t* out) {
     out->device_bytes = c->device_bytes;
     out->precision = c->f32 ? QUAPI_FP32_LOG : QUAPI_FP64;
     out->hash_merge = c->sparse ? 1 : 0;
-    out->store = c->sparse ? QUAPI_MERGE_HASH : c->dense ? QUAPI_MERGE_DIRECT : QUAPI_MERGE_BUCKETED;
+    out->store = c->sparse ? (c->sp_part ? QUAPI_MERGE_PARTITION : QUAPI_MERGE_HASH)
+                           : c->dense ? QUAPI_MERGE_DIRECT : QUAPI_MERGE_BUCKETED;
     out->n_instances = c->n_inst;
     return QUAPI_OK;
 }

@@ -76,10 +76,17 @@ __device__ inline unsigned long long home_slot(unsigned long long key, unsigned 
     return ((mix64(key & cmask) << kWinBits) | (mix64(key) & ((1ull << kWinBits) - 1ull))) & tm;
 }
 
+// groups a segment holds at parity par, bounded by its size
+__device__ inline unsigned long long seg_groups(const SparseArgs& a, int par, int s) {
+    const unsigned long long c = a.count[seg_counter(par, s)];
+    return c < a.seg_cap ? c : a.seg_cap;
+}
+
 // groups stored at t-1 (the step's input), bounded by the capacity
 __device__ inline unsigned long long groups_in(const SparseArgs& a) {
-    const unsigned long long stored = a.count[(a.t - 1) & 1];
-    return stored < (unsigned long long)a.cap ? stored : (unsigned long long)a.cap;
+    unsigned long long n = 0ull;
+    for (int s = 0; s < kSegs; ++s) n += seg_groups(a, (a.t - 1) & 1, s);
+    return n < (unsigned long long)a.cap ? n : (unsigned long long)a.cap;
 }
 
 // slots in use this step, minus one: the next power of two at or above twice
@@ -89,6 +96,21 @@ __device__ inline unsigned long long table_mask(const SparseArgs& a, unsigned lo
     unsigned long long ts = kMinTable;
     if (need > ts) ts = 1ull << (64 - __clzll(need - 1ull));
     return (ts < a.tsize ? ts : a.tsize) - 1ull;
+}
+
+// partitions in use this step: about one per kPartLoad children of the input,
+// a power of two, at most the allocation
+__device__ inline unsigned int n_partitions(const SparseArgs& a, unsigned long long n_in) {
+    const unsigned long long need = ((unsigned long long)a.P * n_in + kPartLoad - 1) / kPartLoad;
+    unsigned long long np = 1;
+    while (np < need) np <<= 1;
+    return (unsigned int)(np < a.n_part_max ? np : a.n_part_max);
+}
+
+// partition of a merge key: high bits of its hash (the LDS table of the
+// partition merge takes the low ones)
+__device__ inline unsigned int partition_of(unsigned long long key, unsigned int np) {
+    return (unsigned int)(mix64(key) >> 32) & (np - 1u);
 }
 
 // low bits of the packed representative word: the complement of the points
@@ -119,6 +141,69 @@ __device__ inline Hist<W> load_hist(const uint64_t* p, unsigned long long g) {
 #pragma unroll
     for (int k = 0; k < W; ++k) h.w[k] = p[g * W + k];
     return h;
+}
+
+// A merged group's history from its key and its representative's other points:
+// both are read in 4-bit slices (two points of a two-level system, one of a
+// larger one), and a table in the LDS gives each slice value's points at their
+// history positions.  Table 0 covers the key (point k of the merge positions
+// at key bit BP*(nq-1-k)), table 1 the other word (point k at BP*(nn-1-k)).
+constexpr int kSliceBits = 4;
+constexpr int kSlices = 64 / kSliceBits;
+using HistTab = ulonglong2[2][kSlices][1 << kSliceBits];
+
+template <int BP>
+__device__ inline void build_hist_tab(const SparseArgs& a, HistTab& tab) {
+    constexpr unsigned int DM = (1u << BP) - 1;
+    for (int e = threadIdx.x; e < 2 * kSlices * (1 << kSliceBits); e += blockDim.x) {
+        const int side = e / (kSlices << kSliceBits);
+        const int sl = (e / (1 << kSliceBits)) % kSlices;
+        const unsigned int v = (unsigned int)e & ((1u << kSliceBits) - 1);
+        const int n = side ? a.nn : a.nq;
+        unsigned long long w0 = 0ull, w1 = 0ull;
+        for (int b = 0; b < kSliceBits; b += BP) {
+            const int kbit = sl * kSliceBits + b;                 // bit of the key (other word)
+            const int k = n - 1 - kbit / BP;                       // its point
+            if (k < 0) break;
+            const unsigned long long pt = (v >> b) & DM;
+            const int bit = BP * (side ? a.npos[k] : a.qpos[k]);   // its history position
+            if (bit < 64) w0 |= pt << bit;
+            else w1 |= pt << (bit - 64);
+        }
+        tab[side][sl][v] = make_ulonglong2(w0, w1);
+    }
+}
+
+// Slices are read four at a time from both tables, up to ns (the larger of the
+// two slice counts): the slices above the key's or the other word's points read
+// value 0, whose entry is zero.
+constexpr int kSliceGroup = 4;
+
+template <int BP, int W>
+__device__ inline Hist<W> hist_from(const HistTab& tab, unsigned long long key, unsigned long long nk, int ns) {
+    Hist<W> h;
+#pragma unroll
+    for (int w = 0; w < W; ++w) h.w[w] = 0ull;
+    for (int s0 = 0; s0 < ns; s0 += kSliceGroup) {
+#pragma unroll
+        for (int j = 0; j < kSliceGroup; ++j) {
+            const int sl = s0 + j;
+            const ulonglong2 t = tab[0][sl][(key >> (kSliceBits * sl)) & ((1u << kSliceBits) - 1)];
+            const ulonglong2 u = tab[1][sl][(nk >> (kSliceBits * sl)) & ((1u << kSliceBits) - 1)];
+            h.w[0] |= t.x | u.x;
+            if (W == 2) h.w[W - 1] |= t.y | u.y;
+        }
+    }
+    return h;
+}
+
+// slices a history rebuild reads: the larger of the key's and the other word's
+// slice counts, rounded up to whole groups of kSliceGroup (at most kSlices)
+template <int BP>
+__device__ inline int hist_slices(const SparseArgs& a) {
+    const int bits = BP * (a.nq > a.nn ? a.nq : a.nn);
+    const int ns = (bits + kSliceBits - 1) / kSliceBits;
+    return (ns + kSliceGroup - 1) / kSliceGroup * kSliceGroup;
 }
 
 // History chunks of kChunkBits bits (two points of a two-level system, one of
@@ -193,6 +278,7 @@ __global__ __launch_bounds__(kSparseThreads) void sparse_expand(const SparseArgs
     __shared__ double lwr[kLds], lwi[kLds];
     __shared__ unsigned int loff[kLdsRows][kSpWaves];
     __shared__ unsigned int lovf[2], lused;
+    __shared__ unsigned long long seg_pre[kSegs + 1];       // the input's segments: first group of each
     const int i = threadIdx.x;
     const int wave = i >> 6;
     const unsigned int lane = lane_id();
@@ -287,6 +373,14 @@ __global__ __launch_bounds__(kSparseThreads) void sparse_expand(const SparseArgs
         itab[c][v][1] = abc;
         gtab[c][v] = make_ulonglong2(kp, np);
     }
+    if (i == 0) {
+        unsigned long long n = 0ull;
+        for (int s = 0; s < kSegs; ++s) {
+            seg_pre[s] = n;
+            n += seg_groups(a, (t - 1) & 1, s);
+        }
+        seg_pre[kSegs] = n;
+    }
     __syncthreads();
 
     double acc[S];
@@ -294,6 +388,15 @@ __global__ __launch_bounds__(kSparseThreads) void sparse_expand(const SparseArgs
     for (int k = 0; k < S; ++k) acc[k] = 0.0;
     const bool failed = error_word(a.error) != 0u;
     const unsigned long long n_in = groups_in(a);
+    // place of input group g: the last segment starting at or before g (empty
+    // segments start where the next one does)
+    auto at = [&](unsigned long long g) {
+        int s = 0;
+#pragma unroll
+        for (int step = kSegs / 2; step > 0; step >>= 1)
+            if (seg_pre[s + step] <= g) s += step;
+        return (unsigned long long)s * a.seg_cap + (g - seg_pre[s]);
+    };
     const unsigned long long N = failed ? 0ull : n_in;
     const unsigned long long tm = table_mask(a, n_in);
     const bool packed = a.packed != 0;
@@ -321,6 +424,24 @@ __global__ __launch_bounds__(kSparseThreads) void sparse_expand(const SparseArgs
         raise_error(a.error, t, kErrOverflow);
         if (!packed) a.cslot[entry] = ~0u;
     };
+    // partition merge: a merged slot (or a child that found the LDS table full)
+    // becomes one entry of its key's partition
+    const bool parted = a.part != 0;
+    const unsigned int n_part = parted ? n_partitions(a, n_in) : 1u;
+    auto append = [&](unsigned long long key, unsigned long long best, unsigned long long other, double wr,
+                      double wi) {
+        const unsigned int pp = partition_of(key, n_part);
+        const unsigned int pos = atomicAdd(a.pcount + pp, 1u);
+        if (pos < kPartCap) {
+            const size_t e = (size_t)pp * kPartCap + pos;
+            a.pkey[e] = key;
+            a.pbest[e] = best;
+            if (!packed) a.pother[e] = other;
+            a.pw[e] = make_double2(wr, wi);
+        } else {
+            raise_error(a.error, t, kErrOverflow);
+        }
+    };
 
     unsigned int pass = 0u;
     for (unsigned long long base = (unsigned long long)blockIdx.x * kSparseThreads; base < N; base += stride, ++pass) {
@@ -339,11 +460,12 @@ __global__ __launch_bounds__(kSparseThreads) void sparse_expand(const SparseArgs
 
         const unsigned long long g = base + i;
         if (g < N) {
-            const Hist<W> h = load_hist<W>(a.h_in, g);
+            const unsigned long long gp = at(g);
+            const Hist<W> h = load_hist<W>(a.h_in, gp);
             double2 Wt = make_double2(0.0, 0.0);
             float2 Wl = make_float2(0.0f, 0.0f);
-            if (F32) Wl = a.wf_in[g];
-            else Wt = a.w_in[g];
+            if (F32) Wl = a.wf_in[gp];
+            else Wt = a.w_in[gp];
             // influence sums over lags 1..dmax, and the children's key and other
             // points but for the new point
             Real A = 0, B = 0, Ac = 0, Bc = 0;
@@ -457,6 +579,9 @@ __global__ __launch_bounds__(kSparseThreads) void sparse_expand(const SparseArgs
                     unsafeAtomicAdd(&lwr[ls], wr);
                     unsafeAtomicAdd(&lwi[ls], wi);
                     if (!packed) { mls[p] = ls; mq[p] = word; mnk[p] = nk; }
+                } else if (parted) {
+                    // no room in the LDS: an entry of its own
+                    append(key, word, nk, wr, wi);
                 } else {
                     // no room in the LDS: straight to the table
                     const unsigned long long entry = packed ? 0ull : ebase + n_ent - 1u - atomicAdd(ovf, 1u);
@@ -509,9 +634,21 @@ __global__ __launch_bounds__(kSparseThreads) void sparse_expand(const SparseArgs
             __syncthreads();
         }
 
+        if (parted) {
+            // each used LDS slot is one entry of its key's partition
+#pragma unroll
+            for (int r = 0; r < kLdsRows; ++r) {
+                const int ls = r * kSparseThreads + i;
+                const unsigned long long kk = lkey[ls];
+                if (kk) append(kk - 1ull, packed ? lbest[ls] : savedq[r], packed ? 0ull : lbest[ls], lwr[ls], lwi[ls]);
+                lkey[ls] = 0ull;
+                lbest[ls] = 0ull;
+                lwr[ls] = 0.0;
+                lwi[ls] = 0.0;
+            }
+        } else {
         // each used LDS slot is one insertion into the table; the first probes
         // of a thread's slots are in flight together
-        {
             unsigned long long fkk[kLdsRows], fsl[kLdsRows], fprev[kLdsRows];
 #pragma unroll
             for (int r = 0; r < kLdsRows; ++r) {
@@ -545,7 +682,7 @@ __global__ __launch_bounds__(kSparseThreads) void sparse_expand(const SparseArgs
                 lwi[ls] = 0.0;
             }
         }
-        if (!packed) {
+        if (!packed && !parted) {
             // entries of this pass that no child took
             const unsigned int lo = lused, hi = n_ent - *ovf;
             for (unsigned int j = lo + (unsigned int)i; j < hi; j += kSparseThreads) a.cslot[ebase + j] = ~0u;
@@ -595,20 +732,24 @@ __global__ __launch_bounds__(kSparseThreads) void sparse_resolve(const SparseArg
 // for twice the children, and children merge).
 template <int BP, int W, bool F32>
 __global__ __launch_bounds__(kSparseThreads) void sparse_compact(const SparseArgs a) {
-    constexpr unsigned long long DM = (1ull << BP) - 1;
     __shared__ unsigned int wcnt[kRows][kSpWaves];
     __shared__ unsigned int tile_base, tile_used;
     __shared__ unsigned short lpos[kTile];                  // used slots of the tile, in slot order
     __shared__ unsigned long long lkey[kTile];              // and their stored keys
+    __shared__ HistTab htab;
+    build_hist_tab<BP>(a, htab);
+    const int ns = hist_slices<BP>(a);
     const int i = threadIdx.x;
     const int wave = i >> 6;
     const bool failed = error_word(a.error) != 0u;
-    unsigned int* const out_count = a.count + (a.t & 1);
+    // this workgroup's output segment
+    const unsigned int seg = blockIdx.x % (unsigned int)kSegs;
+    unsigned int* const out_count = a.count + seg_counter(a.t & 1, (int)seg);
+    const unsigned long long seg_base = (unsigned long long)seg * a.seg_cap;
     const unsigned long long tm = table_mask(a, groups_in(a));
     const unsigned long long n_tiles = (tm + kTile) / kTile;
     const bool packed = a.packed != 0;
     const unsigned long long omask = packed ? other_mask(a) : 0ull;
-    const int nq = a.nq, nn = a.nn;
     for (unsigned long long tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         const unsigned long long s0 = tile * kTile;
         unsigned long long kk[kRows], bal[kRows];
@@ -652,30 +793,17 @@ __global__ __launch_bounds__(kSparseThreads) void sparse_compact(const SparseArg
                 nk = a.tN[sl];
                 a.tN[sl] = ~0ull;
             }
-            if (!failed && idx < (unsigned long long)a.cap) {
+            if (!failed && idx < a.seg_cap) {
                 // the key's points at the merge positions, the representative's elsewhere
                 const unsigned long long key = lkey[j] - 1ull;
-                Hist<W> hist;
+                const Hist<W> hist = hist_from<BP, W>(htab, key, nk, ns);
+                const unsigned long long o = seg_base + idx;
 #pragma unroll
-                for (int w = 0; w < W; ++w) hist.w[w] = 0ull;
-                for (int k = 0; k < nq; ++k) {
-                    const int bit = BP * a.qpos[k];
-                    const unsigned long long pt = (key >> (BP * (nq - 1 - k))) & DM;
-                    if (W == 1 || bit < 64) hist.w[0] |= pt << (bit & 63);
-                    else hist.w[W - 1] |= pt << (bit & 63);
-                }
-                for (int k = 0; k < nn; ++k) {
-                    const int bit = BP * a.npos[k];
-                    const unsigned long long pt = (nk >> (BP * (nn - 1 - k))) & DM;
-                    if (W == 1 || bit < 64) hist.w[0] |= pt << (bit & 63);
-                    else hist.w[W - 1] |= pt << (bit & 63);
-                }
-#pragma unroll
-                for (int w = 0; w < W; ++w) a.h_out[idx * W + w] = hist.w[w];
+                for (int w = 0; w < W; ++w) a.h_out[o * W + w] = hist.w[w];
                 if (F32) {
-                    a.wf_out[idx] = to_log_domain(e->wr, e->wi);
+                    a.wf_out[o] = to_log_domain(e->wr, e->wi);
                 } else {
-                    a.w_out[idx] = make_double2(e->wr, e->wi);
+                    a.w_out[o] = make_double2(e->wr, e->wi);
                 }
             } else if (!failed) {
                 raise_error(a.error, a.t, kErrOverflow);
@@ -689,16 +817,170 @@ __global__ __launch_bounds__(kSparseThreads) void sparse_compact(const SparseArg
     }
 }
 
+// Partition merge: workgroups take the step's partitions in turn.  A
+// partition's entries merge in an LDS table (key, representative word, weight
+// sums; unpacked form: then the smallest other points at the largest quantised
+// |w|^2), and its groups are written at one counter update, their histories
+// rebuilt from the key and the representative's other points.  The partition's
+// counter is cleared for the next step.  The rounds are pipelined: a round's
+// entries are loaded while the round before takes its place in the output, and
+// the count of the round after is loaded with them.
+template <int BP, int W, bool F32>
+__global__ __launch_bounds__(kSparseThreads) void sparse_pmerge(const SparseArgs a) {
+    constexpr int kRowsP = kPartLds / kSparseThreads;
+    constexpr int kPer = (kPartCap + kSparseThreads - 1) / kSparseThreads;   // entries per thread
+    __shared__ unsigned long long lk[kPartLds], lb[kPartLds], lo[kPartLds];
+    __shared__ double lwr[kPartLds], lwi[kPartLds];
+    __shared__ unsigned int wcnt[kRowsP][kSpWaves];
+    __shared__ unsigned int base_s;
+    __shared__ HistTab htab;
+    build_hist_tab<BP>(a, htab);
+    const int ns = hist_slices<BP>(a);
+    const int i = threadIdx.x;
+    const int wave = i >> 6;
+    const unsigned int lane = lane_id();
+    const bool failed = error_word(a.error) != 0u;
+    // this workgroup's output segment
+    const unsigned int seg = blockIdx.x % (unsigned int)kSegs;
+    unsigned int* const out_count = a.count + seg_counter(a.t & 1, (int)seg);
+    const unsigned long long seg_base = (unsigned long long)seg * a.seg_cap;
+    const unsigned int n_part = n_partitions(a, groups_in(a));
+    const unsigned int G = gridDim.x;
+    const bool packed = a.packed != 0;
+    const unsigned long long omask = packed ? other_mask(a) : 0ull;
+    for (int k = i; k < kPartLds; k += kSparseThreads) {
+        lk[k] = 0ull;
+        lb[k] = 0ull;
+        lo[k] = ~0ull;
+        lwr[k] = 0.0;
+        lwi[k] = 0.0;
+    }
+
+    // the entries of one partition, kPer per thread (beyond kPartCap: reported by
+    // expand).  The loads take no branch, so that they are all in flight at once:
+    // a thread past the count reads the partition's last entry again (its line is
+    // read anyway), a round past the last partition reads partition 0; those
+    // values are not used.
+    unsigned long long ek[kPer], eb[kPer], eo[kPer];
+    double2 ew[kPer];
+    auto load = [&](unsigned int pp, unsigned int n) {
+        const size_t p0 = (size_t)(pp < n_part ? pp : 0u) * kPartCap;
+        const unsigned int last = n ? n - 1u : 0u;
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const unsigned int e = (unsigned int)i + (unsigned int)q * kSparseThreads;
+            const size_t ge = p0 + (e < last ? e : last);
+            ek[q] = a.pkey[ge];
+            ew[q] = a.pw[ge];
+            eb[q] = a.pbest[ge];
+            eo[q] = packed ? 0ull : a.pother[ge];
+        }
+    };
+    // a partition's count as stored (clamped where it is used, so that the
+    // load of the next round's count is not waited for at once)
+    auto count_of = [&](unsigned int pp) { return pp < n_part ? a.pcount[pp] : 0u; };
+    auto clamp = [](unsigned int c) { return c < kPartCap ? c : kPartCap; };
+    unsigned int pp = blockIdx.x;
+    unsigned int n_cur = clamp(count_of(pp));
+    load(pp, n_cur);
+    unsigned int n_next = count_of(pp + G);
+    __syncthreads();
+
+    for (; pp < n_part; pp += G) {
+        // this round's entries into the table: at most kPartCap keys in
+        // kPartLds slots, so a free slot is always found
+        unsigned int ms[kPer];
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const unsigned int e = (unsigned int)i + (unsigned int)q * kSparseThreads;
+            ms[q] = ~0u;
+            if (e < n_cur) {
+                const unsigned long long kk = ek[q] + 1ull;
+                unsigned int sl = (unsigned int)mix64(ek[q]) & (unsigned int)(kPartLds - 1);
+                for (int probe = 0; probe < kPartLds; ++probe) {
+                    const unsigned long long prev = atomicCAS(&lk[sl], 0ull, kk);
+                    if (prev == 0ull || prev == kk) break;
+                    sl = (sl + 1u) & (unsigned int)(kPartLds - 1);
+                }
+                ms[q] = sl;
+                atomicMax(&lb[sl], eb[q]);
+                unsafeAtomicAdd(&lwr[sl], ew[q].x);
+                unsafeAtomicAdd(&lwi[sl], ew[q].y);
+            }
+        }
+        __syncthreads();
+        if (!packed) {
+#pragma unroll
+            for (int q = 0; q < kPer; ++q)
+                if (ms[q] != ~0u && eb[q] == lb[ms[q]]) atomicMin(&lo[ms[q]], eo[q]);
+            __syncthreads();
+        }
+        // the used slots' places: per row and wave, then one counter update
+        unsigned long long bal[kRowsP];
+#pragma unroll
+        for (int r = 0; r < kRowsP; ++r) {
+            bal[r] = __ballot(lk[r * kSparseThreads + i] != 0ull);
+            if (lane == 0u) wcnt[r][wave] = (unsigned int)__popcll(bal[r]);
+        }
+        __syncthreads();
+        // the next round's entries, and the count of the round after, are in
+        // flight while the place is taken
+        const unsigned int pn = pp + G;
+        n_cur = clamp(n_next);
+        load(pn, n_cur);
+        n_next = count_of(pn + G);
+        if (i == 0) {
+            unsigned int tot = 0u;
+            for (int r = 0; r < kRowsP; ++r)
+                for (int w = 0; w < kSpWaves; ++w) {
+                    const unsigned int c = wcnt[r][w];
+                    wcnt[r][w] = tot;
+                    tot += c;
+                }
+            base_s = tot ? atomicAdd(out_count, tot) : 0u;
+            a.pcount[pp] = 0u;                                // the next step's appends start at zero
+        }
+        __syncthreads();
+        const unsigned int base = base_s;
+        // write the groups, and free the slots for the next round
+#pragma unroll
+        for (int r = 0; r < kRowsP; ++r) {
+            const int sl = r * kSparseThreads + i;
+            const unsigned long long kk = lk[sl];
+            if (kk == 0ull) continue;
+            const unsigned long long idx = (unsigned long long)base + wcnt[r][wave] + rank_below(bal[r]);
+            if (!failed && idx < a.seg_cap) {
+                const unsigned long long key = kk - 1ull;
+                const unsigned long long nk = packed ? ((lb[sl] & omask) ^ omask) : lo[sl];
+                // the key's points at the merge positions, the representative's elsewhere
+                const Hist<W> hist = hist_from<BP, W>(htab, key, nk, ns);
+                const unsigned long long o = seg_base + idx;
+#pragma unroll
+                for (int w = 0; w < W; ++w) a.h_out[o * W + w] = hist.w[w];
+                if (F32) a.wf_out[o] = to_log_domain(lwr[sl], lwi[sl]);
+                else a.w_out[o] = make_double2(lwr[sl], lwi[sl]);
+            } else if (!failed) {
+                raise_error(a.error, a.t, kErrOverflow);
+            }
+            lk[sl] = 0ull;
+            lb[sl] = 0ull;
+            lo[sl] = ~0ull;
+            lwr[sl] = 0.0;
+            lwi[sl] = 0.0;
+        }
+        __syncthreads();   // the table is free for the next round
+    }
+}
+
 template <int P>
 __global__ __launch_bounds__(kSparseThreads) void sparse_reduce(const SparseArgs a) {
     constexpr int S = partial_stride(P);
     __shared__ double wred[kSpWaves][S];
+    __shared__ int keep_s;
     const int i = threadIdx.x;
     const int wave = i >> 6;
     const unsigned int lane = lane_id();
     const int t = a.t;
-    const unsigned int err = error_word(a.error);
-    const bool keep = err == 0u || (int)(err >> 4) > t;
     double acc[S];
 #pragma unroll
     for (int k = 0; k < S; ++k) acc[k] = 0.0;
@@ -712,7 +994,14 @@ __global__ __launch_bounds__(kSparseThreads) void sparse_reduce(const SparseArgs
     }
     __syncthreads();
     if (i == 0) {
-        const unsigned int n_in = a.count[(t - 1) & 1];
+        // the groups stored: over the capacity, the step fails
+        unsigned long long n_stored = 0ull;
+        for (int s = 0; s < kSegs; ++s) n_stored += a.count[seg_counter(t & 1, s)];
+        if (n_stored > (unsigned long long)a.cap) raise_error(a.error, t, kErrOverflow);
+        const unsigned int err = error_word(a.error);
+        const bool keep = err == 0u || (int)(err >> 4) > t;
+        keep_s = keep ? 1 : 0;
+        const unsigned long long n_in = groups_in(a);
         if (keep) {
             double sum[S];
 #pragma unroll
@@ -724,16 +1013,17 @@ __global__ __launch_bounds__(kSparseThreads) void sparse_reduce(const SparseArgs
             for (int p = 0; p < P; ++p) a.rho_hist[(size_t)t * P + p] = make_double2(sum[2 * p], sum[2 * p + 1]);
             StepStatsDev st;
             st.n_groups = n_in;
-            st.n_children = (unsigned long long)n_in * P;
+            st.n_children = n_in * P;
             st.n_survivors = (unsigned long long)sum[2 * P + 1];
-            st.n_stored = a.count[t & 1];
+            st.n_stored = n_stored;
             st.dropped_abs = sum[2 * P];
             st.pad = 0.0;
             a.stats_hist[t] = st;
-            // the counter step t+1 writes: it held this step's input count
-            a.count[(t + 1) & 1] = 0u;
         }
     }
+    __syncthreads();
+    // the counters step t+1 writes: they held this step's input counts
+    if (keep_s && i < kSegs) a.count[seg_counter((t + 1) & 1, i)] = 0u;
 }
 
 }  // namespace
@@ -745,8 +1035,12 @@ void launch_sparse(const SparseArgs& a, hipStream_t st, hipEvent_t after_expand)
     const size_t chunk_bytes = std::max(sparse_chunk_lds<F32>((a.K + ppc - 1) / ppc), kExpandLdsFloor);
     hipLaunchKernelGGL((sparse_expand<P, BP, W, F32>), dim3(g), dim3(kSparseThreads), chunk_bytes, st, a);
     if (after_expand) (void)hipEventRecord(after_expand, st);
-    if (!a.packed) hipLaunchKernelGGL((sparse_resolve<P>), dim3(g), dim3(kSparseThreads), 0, st, a);
-    hipLaunchKernelGGL((sparse_compact<BP, W, F32>), dim3(g), dim3(kSparseThreads), 0, st, a);
+    if (a.part) {
+        hipLaunchKernelGGL((sparse_pmerge<BP, W, F32>), dim3(a.grid_merge), dim3(kSparseThreads), 0, st, a);
+    } else {
+        if (!a.packed) hipLaunchKernelGGL((sparse_resolve<P>), dim3(g), dim3(kSparseThreads), 0, st, a);
+        hipLaunchKernelGGL((sparse_compact<BP, W, F32>), dim3(g), dim3(kSparseThreads), 0, st, a);
+    }
     hipLaunchKernelGGL((sparse_reduce<P>), dim3(1), dim3(kSparseThreads), 0, st, a);
 }
 
@@ -760,6 +1054,25 @@ int launch_sparse_form(const SparseArgs& a, hipStream_t st, hipEvent_t ev) {
     else if (a.P == 16 && a.hw == 2) launch_sparse<16, 4, 2, F32>(a, st, ev);
     else return (int)hipErrorInvalidValue;
     return (int)hipGetLastError();
+}
+
+template <int BP, int W, bool F32>
+int merge_blocks_per_cu() {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sparse_pmerge<BP, W, F32>, kSparseThreads, 0) != hipSuccess)
+        return 0;
+    return n;
+}
+
+int sparse_merge_grid(int P, int hw, bool f32, int n_cu) {
+    const int bp = P == 4 ? 2 : 4;
+    int per_cu = 0;
+    if (bp == 2 && hw == 1) per_cu = f32 ? merge_blocks_per_cu<2, 1, true>() : merge_blocks_per_cu<2, 1, false>();
+    else if (bp == 2) per_cu = f32 ? merge_blocks_per_cu<2, 2, true>() : merge_blocks_per_cu<2, 2, false>();
+    else if (hw == 1) per_cu = f32 ? merge_blocks_per_cu<4, 1, true>() : merge_blocks_per_cu<4, 1, false>();
+    else per_cu = f32 ? merge_blocks_per_cu<4, 2, true>() : merge_blocks_per_cu<4, 2, false>();
+    const int g = std::max(per_cu, 1) * std::max(n_cu, 1) / kSegs * kSegs;
+    return std::max(g, kSegs);
 }
 
 int launch_sparse_step(const SparseArgs& a, void* stream, void* after_expand) {

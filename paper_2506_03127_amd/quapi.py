@@ -31,6 +31,7 @@ QUAPI_MERGE_AUTO = 0
 QUAPI_MERGE_DIRECT = 1
 QUAPI_MERGE_BUCKETED = 2
 QUAPI_MERGE_HASH = 3
+QUAPI_MERGE_PARTITION = 4
 
 
 class c64(ctypes.Structure):

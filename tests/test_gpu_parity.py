@@ -37,13 +37,24 @@ def _mode_q(Q, mode):
     return Q.QUAPI_PRE if mode == "pre" else Q.QUAPI_POST
 
 
+# the last oracle run, reused when the next case differs only in the store
+_last_oracle = [None, None]
+
+
 def run_both(Q, H, q, dt, K, eta, rho0, n, mode="pre", mask=None, theta=0.0, qbits=32, **kw):
-    print(f"[parity] M={np.asarray(H).shape[0]} K={K} mode={mode} mask={mask} theta={theta} n={n}",
-          flush=True)
-    o = oracle.Oracle(H, q, dt, K, eta, rho0, mask=mask, theta=theta, mode=_mode_o(mode), qbits=qbits)
+    print(f"[parity] M={np.asarray(H).shape[0]} K={K} mode={mode} mask={mask} theta={theta} n={n} "
+          f"merge={kw.get('merge', 0)}", flush=True)
+    key = (np.asarray(H).tobytes(), tuple(q), dt, K, np.asarray(eta).tobytes(), np.asarray(rho0).tobytes(), n,
+           mode, None if mask is None else tuple(mask), theta, qbits)
+    if _last_oracle[0] == key:
+        o = _last_oracle[1]
+    else:
+        _last_oracle[0] = _last_oracle[1] = None
+        o = oracle.Oracle(H, q, dt, K, eta, rho0, mask=mask, theta=theta, mode=_mode_o(mode), qbits=qbits)
+        o.step(n)
+        _last_oracle[0], _last_oracle[1] = key, o
     g = Q.Propagator(H, q, dt, K, eta, rho0, mask=mask, theta=theta, mode=_mode_q(Q, mode),
                      qbits=qbits, **kw)
-    o.step(n)
     g.step(n)
     return o, g
 
@@ -166,18 +177,21 @@ def test_three_level_system(Q, eta_cache):
     assert_groups(o, g)
 
 
+@pytest.mark.parametrize("store", ["HASH", "PARTITION"])
 @pytest.mark.parametrize("mode,K,mask,theta,n", [
     ("post", 3, None, 0.0, 12),            # exact iQUAPI: 16^3 groups
     ("pre", 5, (0, 1, 2), 1e-7, 24),       # MACGIC pre-merging on lags 0..2
     ("pre", 6, (0, 1, 2, 4), 1e-7, 20),    # a mask with a distant lag
 ], ids=["post-K3-full", "pre-K5-lags-0-2", "pre-K6-sparse"])
-def test_four_level_system(Q, eta_cache, mode, K, mask, theta, n):
-    """Four levels (16 pairs of 4-bit points) on the hash-table merge, against
-    the oracle: rho(t), counters and groups."""
+def test_four_level_system(Q, eta_cache, store, mode, K, mask, theta, n):
+    """Four levels (16 pairs of 4-bit points) on the hash-table store, merged
+    through the table and through partitions, against the oracle: rho(t),
+    counters and groups."""
     wl = W.four_level(K=K)
     eta = eta_cache(wl, K)
-    o, g = run_both(Q, wl.H, wl.q, wl.dt, K, eta, wl.rho0, n, mode=mode, mask=mask, theta=theta)
-    assert Q.quapi_info(g.ctx)["store"] == Q.QUAPI_MERGE_HASH
+    merge = getattr(Q, f"QUAPI_MERGE_{store}")
+    o, g = run_both(Q, wl.H, wl.q, wl.dt, K, eta, wl.rho0, n, mode=mode, mask=mask, theta=theta, merge=merge)
+    assert Q.quapi_info(g.ctx)["store"] == merge
     assert ambiguous(o, n) == 0
     assert_rho(o, g, n)
     assert_stats(o, g, n)
@@ -202,6 +216,7 @@ def test_other_shapes(Q, eta_cache, make, mode, K, mask, theta, n):
 
 
 # ------------------------------------------------------------------ sparse MACGIC masks (hash-table merge)
+@pytest.mark.parametrize("store", ["AUTO", "PARTITION"])
 @pytest.mark.parametrize("make,mode,K,mask,theta,n", [
     (W.structured_bath, "pre", 12, (0, 1, 2, 3, 4, 5, 8, 11), 1e-7, 30),
     (W.structured_bath, "pre", 16, (0, 1, 2, 3, 4, 5, 6, 7, 11, 15), 1e-7, 25),
@@ -219,18 +234,23 @@ def test_other_shapes(Q, eta_cache, make, mode, K, mask, theta, n):
     (W.three_level, "pre", 12, (0, 1, 2, 3), 1e-7, 25),
 ], ids=["K12-pre", "K16-pre", "K8-post", "K6-newest-only", "three-level-K8", "K24-tail-15-19-23",
         "K24-packed-32bit", "K24-unpacked-34bit", "K20-unpacked-first4", "three-level-K12-unpacked"])
-def test_sparse_masks(Q, eta_cache, make, mode, K, mask, theta, n):
+def test_sparse_masks(Q, eta_cache, store, make, mode, K, mask, theta, n):
     """Masks whose merge positions are not a contiguous run from 0: the children a
-    group receives are not neighbours in key order and merge through a hash table."""
+    group receives are not neighbours in key order and merge through a hash table
+    (the default) or through partitions by key hash."""
     wl = make(K=K)
     eta = eta_cache(wl, K)
-    o, g = run_both(Q, wl.H, wl.q, wl.dt, K, eta, wl.rho0, n, mode=mode, mask=mask, theta=theta)
+    merge = getattr(Q, f"QUAPI_MERGE_{store}")
+    o, g = run_both(Q, wl.H, wl.q, wl.dt, K, eta, wl.rho0, n, mode=mode, mask=mask, theta=theta, merge=merge)
+    if store != "AUTO":
+        assert Q.quapi_info(g.ctx)["store"] == merge
     assert ambiguous(o, n) == 0
     assert_rho(o, g, n)
     assert_stats(o, g, n)
     assert_groups(o, g)
 
 
+@pytest.mark.parametrize("store", ["AUTO", "PARTITION"])
 @pytest.mark.parametrize("make,K,mask,theta,n", [
     # the long-memory mask: lags 0..11 exact, 16, 24 and 32 kept (80-bit
     # histories, 26 other points: the representative in a second pass)
@@ -243,11 +263,13 @@ def test_sparse_masks(Q, eta_cache, make, mode, K, mask, theta, n):
     (W.three_level, 24, (0, 1, 2, 3, 4, 5, 6, 7, 12, 23), 1e-7, 13),
     (W.three_level, 20, tuple(range(13)) + (19,), 1e-5, 16),
 ], ids=["K40-lags-16-24-32", "K40-other-64bit", "K40-packed", "three-level-K24", "three-level-K20-packed"])
-def test_sparse_long_histories(Q, eta_cache, make, K, mask, theta, n):
-    """Hash-table merge with histories longer than one 64-bit word."""
+def test_sparse_long_histories(Q, eta_cache, store, make, K, mask, theta, n):
+    """Hash-table store with histories longer than one 64-bit word, merged
+    through the table and through partitions."""
     wl = make(K=K)
     eta = eta_cache(wl, K)
-    o, g = run_both(Q, wl.H, wl.q, wl.dt, K, eta, wl.rho0, n, mode="pre", mask=mask, theta=theta)
+    merge = getattr(Q, f"QUAPI_MERGE_{store}")
+    o, g = run_both(Q, wl.H, wl.q, wl.dt, K, eta, wl.rho0, n, mode="pre", mask=mask, theta=theta, merge=merge)
     assert Q.quapi_info(g.ctx)["record_bytes"] == 32
     assert ambiguous(o, n) == 0
     assert_rho(o, g, n)
@@ -255,10 +277,12 @@ def test_sparse_long_histories(Q, eta_cache, make, K, mask, theta, n):
     assert_groups(o, g)
 
 
-def test_sparse_mask_capacity_overflow(Q, eta_cache):
+@pytest.mark.parametrize("store", ["AUTO", "PARTITION"])
+def test_sparse_mask_capacity_overflow(Q, eta_cache, store):
     wl = W.structured_bath(K=10)
     eta = eta_cache(wl, 10)
-    g = Q.Propagator(wl.H, wl.q, wl.dt, 10, eta, wl.rho0, mask=(0, 1, 2, 5), mode=Q.QUAPI_POST, max_groups=50)
+    g = Q.Propagator(wl.H, wl.q, wl.dt, 10, eta, wl.rho0, mask=(0, 1, 2, 5), mode=Q.QUAPI_POST, max_groups=50,
+                     merge=getattr(Q, f"QUAPI_MERGE_{store}"))
     g.step(12)
     with pytest.raises(Q.QuapiError) as e:
         g.sync()
@@ -388,21 +412,24 @@ def test_structured_bath_full_run(Q, store):
     check_stats(g.stats(1, n), gold)
 
 
-def test_long_memory_full_run(Q, eta_cache):
+@pytest.mark.parametrize("store", ["AUTO", "PARTITION"])
+def test_long_memory_full_run(Q, eta_cache, store):
     """The long-memory workload (dk_max 40, lags 0..11, 16, 24 and 32 exact,
-    theta 1e-9: 80-bit histories on the hash-table merge, ~1.6e7 groups) for
-    1000 steps at the full size, launched as the benchmark launches it: the
-    stored oracle steps (past K + 1 = 41) element by element -- rho(t),
-    counters, group-set fingerprints -- and the counters of every step against
-    the bookkeeping of the method."""
+    theta 1e-9: 80-bit histories on the hash-table store, ~1.6e7 groups) for
+    1000 steps at the full size, launched as the benchmark launches it, merged
+    through the table and through partitions: the stored oracle steps (past
+    K + 1 = 41) element by element -- rho(t), counters, group-set fingerprints
+    -- and the counters of every step against the bookkeeping of the method."""
     gold = GoldenRun("long_memory")
     wl = W.long_memory()
     n0 = gold.steps
     assert n0 >= wl.K + 1 and gold.ambiguous(n0) == 0
+    merge = getattr(Q, f"QUAPI_MERGE_{store}")
     g = Q.Propagator(wl.H, wl.q, wl.dt, wl.K, gold.eta, wl.rho0, mask=wl.mask, theta=wl.theta,
-                     max_steps=wl.n_steps, max_groups=48 << 20)
+                     max_steps=wl.n_steps, max_groups=48 << 20, merge=merge)
     assert Q.quapi_info(g.ctx)["hash_merge"] == 1
-    print(f"[parity] long memory, {n0} stored steps then to {wl.n_steps}", flush=True)
+    assert Q.quapi_info(g.ctx)["store"] == (Q.QUAPI_MERGE_HASH if store == "AUTO" else merge)
+    print(f"[parity] long memory ({store}), {n0} stored steps then to {wl.n_steps}", flush=True)
     _run_against_golden(Q, g, gold, n0, g.groups)
     r0 = g.rho_history()
     err = np.abs(r0 - gold.rho).max()
@@ -496,14 +523,15 @@ def test_contexts_on_caller_streams_step_side_by_side(Q, eta_cache):
 
 
 # ------------------------------------------------------------------ the three stores
-@pytest.mark.parametrize("store", ["DIRECT", "BUCKETED", "HASH"])
+@pytest.mark.parametrize("store", ["DIRECT", "BUCKETED", "HASH", "PARTITION"])
 @pytest.mark.parametrize("mode,K,mask,theta,n", [
     ("pre", 12, (0, 1, 2, 3, 4, 5, 6), 1e-7, 60),     # L = 6
     ("post", 10, (0, 1, 2, 3, 4, 5), 1e-8, 40),       # L = 6
 ])
 def test_every_store_matches_the_oracle(Q, eta_cache, store, mode, K, mask, theta, n):
-    """The direct-mapped store, the bucketed store and the hash table on the
-    same contiguous masks: each against the oracle (rho, counters, groups)."""
+    """The direct-mapped store, the bucketed store and the hash-table store
+    (merged through the table and through partitions) on the same contiguous
+    masks: each against the oracle (rho, counters, groups)."""
     wl = W.structured_bath(K=K)
     eta = eta_cache(wl, K)
     merge = getattr(Q, f"QUAPI_MERGE_{store}")
@@ -543,4 +571,7 @@ def test_store_requests_that_do_not_apply(Q, eta_cache):
     assert e.value.code == Q.QUAPI_EUNSUPPORTED
     with pytest.raises(Q.QuapiError) as e:
         Q.Propagator(wl.H, wl.q, wl.dt, 12, eta, wl.rho0, mask=(0, 1, 2, 5), merge=7)
+    assert e.value.code == Q.QUAPI_EINVAL
+    with pytest.raises(Q.QuapiError) as e:
+        Q.Propagator(wl.H, wl.q, wl.dt, 12, eta, wl.rho0, mask=(0, 1, 2, 5), merge=5)
     assert e.value.code == Q.QUAPI_EINVAL

@@ -87,6 +87,7 @@ def test_create_rejects_invalid_input_without_device(Q):
     assert _create_code(Q, mask=[0, 1, 1]) == Q.QUAPI_EINVAL          # not strictly sorted
     assert _create_code(Q, mask=[0, 1, 8]) == Q.QUAPI_EINVAL          # lag beyond dk_max - 1
     assert _create_code(Q, mode=7) == Q.QUAPI_EINVAL
+    assert _create_code(Q, merge=5) == Q.QUAPI_EINVAL                 # no such store
     eta_nan = np.zeros((3, 9), dtype=complex)
     eta_nan[0, 3] = np.nan
     assert _create_code(Q, eta=eta_nan) == Q.QUAPI_EINVAL
@@ -126,6 +127,8 @@ def test_create_batch_rejects_invalid_input_without_device(Q):
     etas[2, 1, 4] = np.inf                              # the last instance's table
     assert _create_batch_code(Q, n_inst=3, etas=etas) == Q.QUAPI_EINVAL
     assert _create_batch_code(Q, mask=[0, 1, 3]) == Q.QUAPI_EUNSUPPORTED   # hash-table merge
+    for merge in (Q.QUAPI_MERGE_HASH, Q.QUAPI_MERGE_PARTITION):
+        assert _create_batch_code(Q, merge=merge) == Q.QUAPI_EUNSUPPORTED
     assert _create_batch_code(Q, mode=9) == Q.QUAPI_EINVAL
     Hb = np.stack([W.tls_hamiltonian(0.5, 1.0), np.array([[0, 1], [2, 0]], dtype=complex)])
     assert _create_batch_code(Q, H_batch=Hb) == Q.QUAPI_EINVAL          # second H not Hermitian
