@@ -35,9 +35,10 @@ time steps: 4^8 = 65536 groups per step at steady state.
 
 --workload long-memory measures the long-memory configuration instead: the
 same structured bath with dk_max = 40, theta = 1e-9, the mask keeping lags
-0..11 exact and lags 16, 24 and 32 of the tail (80-bit histories, hash-table
-merge), 1000 time steps.  Its roofline object covers the expand kernel, the
-largest share of that step, with the same algorithmic bytes per step.
+0..11 exact and lags 16, 24 and 32 of the tail (80-bit histories, the
+hash-table store merged through partitions; --merge hash takes the table),
+1000 time steps.  Its roofline object covers the expand kernel, the largest
+share of that step, with the same algorithmic bytes per step.
 --precision fp32 runs the FP32 log-domain form on either workload.
 """
 from __future__ import annotations
@@ -111,11 +112,12 @@ def workload_spec(name: str, precision: str, store: str = "bucketed") -> dict:
         tag = "_partition" if store == "partition" else ""
         spec["traffic"] = f"{spec['kernel']}{tag}_{name.replace('-', '_')}_traffic.json"
     if precision == "fp32":
-        # the FP32 form runs every mask on the hash-table merge
-        spec.update({"kernel": "sparse_expand", "kernel_label": "sparse_expand (FP32 form)",
+        # the FP32 form runs every mask on the hash-table store
+        tag = "_partition" if store == "partition" else ""
+        spec.update({"kernel": "sparse_expand",
+                     "kernel_label": "sparse_expand (FP32 form" + (", partition merge)" if tag else ")"),
                      "sources": WORKLOADS["long-memory"]["sources"],
-                     "traffic": spec["traffic"].replace(".json", "_fp32.json").replace(
-                         "step_kernel", "sparse_expand_structured_bath")})
+                     "traffic": f"sparse_expand{tag}_{name.replace('-', '_')}_traffic_fp32.json"})
         if name == "structured-bath":
             spec["max_groups"] = 8 << 20
     return spec

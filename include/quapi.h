@@ -61,7 +61,8 @@ typedef struct { double re, im; } quapi_c64;
                                 /* near their thresholds may differ too                                 */
 
 /* Where the groups live and how they merge (Sec. 3.1.2; quapi_params.merge). */
-#define QUAPI_MERGE_AUTO     0  /* DIRECT where it applies, else BUCKETED where it applies, else HASH     */
+#define QUAPI_MERGE_AUTO     0  /* DIRECT where it applies, else BUCKETED where it applies, else the      */
+                                /* hash-table store merged through partitions (PARTITION)                  */
 #define QUAPI_MERGE_DIRECT   1  /* a slot per key of the merge positions 0..L-1 (two-level systems,       */
                                 /* 6 <= L <= 12, FP64, lone contexts): the parents that merge are the      */
                                 /* occupied slots of an aligned segment of four, every merged group has a  */
@@ -69,11 +70,13 @@ typedef struct { double re, im; } quapi_c64;
                                 /* count) and one kernel whose waves never wait on one another             */
 #define QUAPI_MERGE_BUCKETED 2  /* merge positions 0..L-1: groups sorted by key in buckets of their top   */
                                 /* points, merged on chip as runs of neighbours                             */
-#define QUAPI_MERGE_HASH     3  /* any merge positions: an open-addressing hash table in device memory     */
-#define QUAPI_MERGE_PARTITION 4 /* the hash table's store, merged without a table: each pass's merged      */
-                                /* children go to partitions by the hash of their key, and each partition  */
-                                /* merges in on-chip memory (no device-memory atomics but one counter     */
-                                /* per entry, no table scan)                                               */
+#define QUAPI_MERGE_HASH     3  /* any merge positions: histories in one or two words, merged through an   */
+                                /* open-addressing hash table in device memory                             */
+#define QUAPI_MERGE_PARTITION 4 /* the same store and the same groups as HASH, merged without a table:     */
+                                /* each expand pass's merged children are appended (one counter increment  */
+                                /* each, 32-byte entries) to partitions chosen by the hash of their key,   */
+                                /* and a second kernel merges each partition in an LDS table and writes   */
+                                /* its groups (no table scan, no second pass for the representative)      */
 
 typedef struct quapi_ctx quapi_ctx;
 
@@ -81,7 +84,7 @@ typedef struct quapi_ctx quapi_ctx;
  * every pointer and may free it after the call). */
 typedef struct {
     int M;                    /* number of system (DVR) states, 2..4 (M > 4: QUAPI_EUNSUPPORTED; M = 4, */
-                              /* 16 pairs, runs on the hash-table merge only)                           */
+                              /* 16 pairs, runs on the hash-table store only: HASH or PARTITION)       */
     const quapi_c64* H;       /* M*M Hermitian system Hamiltonian H_S (eq. tot_ham), used as given;     */
                               /* rejected if |H_ij - conj(H_ji)| > 1e-12 max(1, max|H|)                  */
     const double* q;          /* M coupling eigenvalues q_i of the DVR states (eq. tot_ham)             */
@@ -96,7 +99,7 @@ typedef struct {
     const int* mask;          /* MACGIC mask (Sec. 2.1): n_mask sorted lags, mask[0]=0, mask[1]=1,      */
                               /* mask[n_mask-1] <= K-1; NULL: every lag 0..K-1.  Merge positions       */
                               /* 0..L-1 (L >= 2, M <= 3) run on the direct-mapped or bucketed store    */
-                              /* (see merge); any other set merges through a hash table and needs the  */
+                              /* (see merge); any other set takes the hash-table store and needs the   */
                               /* history in 128 bits, the merge positions in 62 and the other          */
                               /* positions in 64 (M = 2: K <= 63, at most 31 merge and 32 other        */
                               /* positions; M = 3 and 4: half of each)                                 */
@@ -108,10 +111,12 @@ typedef struct {
                               /* multiply-add) with its low qbits mantissa bits cleared; equal values    */
                               /* go to the history that is smaller read from the oldest point.          */
                               /* < 0: default 32, or 40 in the FP32 precision form (whose rounding of    */
-                              /* |w|^2, ~1e-6 relative, must stay well below the compared quantum)      */
+                              /* |w|^2, ~1e-6 relative, must stay well below the compared quantum).     */
+                              /* Parity with the oracle is tested at the defaults; at qbits 8 and 20 a  */
+                              /* few representatives differ from the oracle's (alike on every store)   */
     long long max_groups;     /* stored groups to allocate for, spread evenly over the key buckets     */
                               /* (at least one each; an uneven fill reports ENOMEM first); 0: room   */
-                              /* for every key of the merge positions (hash-table merge: up to 2^21). */
+                              /* for every key of the merge positions (hash-table store: up to 2^21). */
                               /* The direct-mapped store always holds every key: AUTO takes it only   */
                               /* when max_groups is 0 or at least P^L                                 */
     int max_steps;            /* initial capacity of the rho(t) history; grows on demand; <= 0: 1024    */
@@ -121,9 +126,9 @@ typedef struct {
                               /* step kernels of one device across all streams: a step kernel on     */
                               /* another stream than the last one waits for it; other work overlaps  */
     int precision;            /* QUAPI_FP64 (0) or QUAPI_FP32_LOG                                       */
-    int merge;                /* QUAPI_MERGE_*: the store (0, AUTO: DIRECT, else BUCKETED, else HASH,   */
-                              /* the first that applies); a store that does not apply returns          */
-                              /* QUAPI_EUNSUPPORTED                                                     */
+    int merge;                /* QUAPI_MERGE_*: the store (0, AUTO: DIRECT, else BUCKETED, else         */
+                              /* PARTITION, the first that applies); a store that does not apply       */
+                              /* returns QUAPI_EUNSUPPORTED; HASH and PARTITION take any mask           */
 } quapi_params;
 
 /* Per-step counters, available for every step t >= 1 that has completed. */
@@ -147,9 +152,9 @@ typedef struct {
     long long capacity;       /* maximum number of stored groups (of one instance)                      */
     size_t device_bytes;      /* device memory held by the context                                      */
     int precision;            /* QUAPI_FP64 or QUAPI_FP32_LOG                                           */
-    int hash_merge;           /* 1: the hash-table merge, 0: a store sorted by key                      */
+    int hash_merge;           /* 1: the hash-table store (HASH or PARTITION), 0: a store sorted by key  */
     int n_instances;          /* instances of a batched context, else 1                                 */
-    int store;                /* QUAPI_MERGE_DIRECT, QUAPI_MERGE_BUCKETED or QUAPI_MERGE_HASH           */
+    int store;                /* QUAPI_MERGE_DIRECT, _BUCKETED, _HASH or _PARTITION                      */
 } quapi_info_t;
 
 /* Create a context and its initial state t = 0 (one path per nonzero
@@ -175,7 +180,7 @@ int quapi_create(const quapi_params* p, quapi_ctx** out);
  * one instance.  The functions without "batch" in their name address
  * instance 0.  Merge positions 0..L-1 (the bucketed store), FP64 only.
  * Errors: as quapi_create; EINVAL (n_inst < 1 or > 1024, eta_batch NULL or not
- * finite, an H_batch matrix not Hermitian), EUNSUPPORTED (the hash-table merge
+ * finite, an H_batch matrix not Hermitian), EUNSUPPORTED (the hash-table store
  * or the FP32 form). */
 int quapi_create_batch(const quapi_params* p, int n_inst, const quapi_c64* eta_batch, const quapi_c64* H_batch,
                        quapi_ctx** out);
@@ -196,7 +201,7 @@ int quapi_step(quapi_ctx* c, int n_steps);
  * Recording captures the context's stream: nothing else may be enqueued on it
  * meanwhile (e.g. by another thread's context on the shared library stream). 
  * Errors: EINVAL (n_steps < 1), ESTATE (a previous step failed), ENOMEM
- * (history growth), EUNSUPPORTED (the hash-table merge), EDEVICE (capture,
+ * (history growth), EUNSUPPORTED (the hash-table store), EDEVICE (capture,
  * instantiation or launch failed). */
 int quapi_step_graph(quapi_ctx* c, int n_steps);
 
@@ -215,7 +220,8 @@ int quapi_rho_history(quapi_ctx* c, int t0, int n, quapi_c64* out);
 /* Counters of steps t0 .. t0+n-1 (t0 >= 1) into caller-owned out[n] (synchronises). */
 int quapi_step_stats(quapi_ctx* c, int t0, int n, quapi_stepstat_t* out);
 
-/* The stored groups (the groups the next step extends), sorted by merge key:
+/* The stored groups (the groups the next step extends), in store order (sorted
+ * by merge key on the direct-mapped and bucketed stores):
  * hist[i*K + j] = pair index of group i at lag j (0 for lags the paths do not
  * yet hold), w[i] = group amplitude.  Writes min(n, cap) groups; *n_out = n.
  * hist or w may be NULL with cap = 0 to query n (synchronises). */
@@ -262,14 +268,14 @@ const char* quapi_strerror(int code);
  * makes the next quapi_step calls record HIP events on the context's stream
  * around each of the next max_launches steps: one before the step kernel, one
  * between it and the planner that follows it, one after the planner.  On the
- * hash-table merge: one before the expand kernel, one after it, one after the
+ * hash-table store: one before the expand kernel, one after it, one after the
  * rest of the step.
  * Errors: EINVAL (max_launches < 1), ENOMEM, EDEVICE. */
 int quapi_profile_begin(quapi_ctx* c, int max_launches);
 
 /* Durations in milliseconds of the recorded steps, oldest first: step_ms[k] of
  * the step kernel, plan_ms[k] of the planner after it (either array may be NULL);
- * on the hash-table merge, of the expand kernel and of the rest of the step.
+ * on the hash-table store, of the expand kernel and of the rest of the step.
  * Writes min(cap, n) entries, *n_out = n; synchronises and stops recording.
  * Errors: EINVAL, ESTATE (no recording began), EDEVICE. */
 int quapi_profile_end(quapi_ctx* c, int cap, double* step_ms, double* plan_ms, int* n_out);

@@ -57,10 +57,9 @@ struct quapi_ctx {
     bool sp_part = false;                         // partition merge in place of the table
     unsigned int sp_n_part = 0;                   // partitions allocated
     unsigned int* sp_pcount = nullptr;            // [sp_n_part]
-    unsigned long long* sp_pkey = nullptr;        // [sp_n_part * kPartCap] entries ...
-    unsigned long long* sp_pbest = nullptr;
-    unsigned long long* sp_pother = nullptr;      // (unpacked form only)
-    double2* sp_pw = nullptr;
+    quapi_dev::PartRec* sp_prec = nullptr;        // [sp_n_part * kPartCap] entries
+    unsigned long long* sp_pother = nullptr;      // (unpacked form whose entry does not fit 128 bits)
+    bool sp_pfit = false;
     unsigned long long* sp_tN = nullptr;         // unpacked form only
     unsigned int* sp_cslot = nullptr;
     unsigned long long* sp_cN = nullptr;
@@ -396,10 +395,9 @@ int step_sparse(quapi_ctx* c, int n_steps) {
     a.grid_merge = c->sp_grid_merge;
     a.n_part_max = c->sp_n_part;
     a.pcount = c->sp_pcount;
-    a.pkey = c->sp_pkey;
-    a.pbest = c->sp_pbest;
+    a.prec = c->sp_prec;
     a.pother = c->sp_pother;
-    a.pw = c->sp_pw;
+    a.pfit = c->sp_pfit ? 1 : 0;
     a.cap = c->sp_cap;
     a.seg_cap = c->sp_seg_cap;
     a.P = c->P;
@@ -759,7 +757,8 @@ static int create_ctx(const quapi_params* p, int n_inst, const quapi_c64* eta_al
     c->sparse = !contiguous;
     c->dense = use_dense;
     c->f32 = p->precision == QUAPI_FP32_LOG;
-    c->sp_part = c->sparse && merge == QUAPI_MERGE_PARTITION;
+    // the hash-table store merges through partitions unless the table is asked for
+    c->sp_part = c->sparse && merge != QUAPI_MERGE_HASH;
     c->qpos = pos;
     if (c->sparse) {
         // the other positions, oldest first; the representative word packs
@@ -970,10 +969,10 @@ static int create_ctx(const quapi_params* p, int n_inst, const quapi_c64* eta_al
             c->sp_n_part = (unsigned int)np;
             const size_t ne = (size_t)np * quapi_dev::kPartCap;
             if (!rc) rc = dev_alloc(c, &c->sp_pcount, (size_t)np);
-            if (!rc) rc = dev_alloc(c, &c->sp_pkey, ne);
-            if (!rc) rc = dev_alloc(c, &c->sp_pbest, ne);
-            if (!rc && !c->sp_packed) rc = dev_alloc(c, &c->sp_pother, ne);
-            if (!rc) rc = dev_alloc(c, &c->sp_pw, ne);
+            // unpacked form: key, other points and quantised |w|^2 in one 128-bit number where they fit
+            c->sp_pfit = !c->sp_packed && bits * K + (63 - c->qbits) <= 128;
+            if (!rc) rc = dev_alloc(c, &c->sp_prec, ne);
+            if (!rc && !c->sp_packed && !c->sp_pfit) rc = dev_alloc(c, &c->sp_pother, ne);
         } else {
         if (!rc) rc = dev_alloc(c, &c->sp_slot, (size_t)ts);
         if (!c->sp_packed) {

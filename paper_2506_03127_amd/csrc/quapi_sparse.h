@@ -45,6 +45,16 @@ struct __align__(32) SpSlot {
     double wr, wi;                  // sum of the key's child weights
 };
 
+// One entry of a partition: the merge key and the representative word (packed
+// form: the word itself; unpacked form: the key, the other points and the
+// quantised |w|^2 >> qbits side by side as one 128-bit number where they fit,
+// else the key and the quantised |w|^2, the other points in an array of their
+// own), and the weight sum.
+struct __align__(32) PartRec {
+    unsigned long long x, y;
+    double wr, wi;
+};
+
 struct SparseArgs {
     const uint64_t* h_in;           // [kSegs * seg_cap * hw] stored groups (state at t-1)
     const double2* w_in;            // FP64 form: amplitudes
@@ -76,10 +86,9 @@ struct SparseArgs {
     int part;                       // 1: partition merge in place of the table
     unsigned int n_part_max;        // partitions allocated (a power of two)
     unsigned int* pcount;           // [n_part_max] entries appended this step, zero between steps
-    unsigned long long* pkey;       // [n_part_max * kPartCap] merge key of each entry
-    unsigned long long* pbest;      // ... representative word (unpacked form: quantised |w|^2)
-    unsigned long long* pother;     // ... unpacked form: smallest other points at that |w|^2
-    double2* pw;                    // ... weight sum
+    PartRec* prec;                  // [n_part_max * kPartCap] the entries
+    unsigned long long* pother;     // ... unpacked form, when pfit is 0: smallest other points at the best |w|^2
+    int pfit;                       // unpacked form: key, other points and quantised |w|^2 fill one 128-bit number
     double* partials;               // [partial_stride(P)][grid] per expand workgroup
     int grid;
     int grid_merge;                 // workgroups of the partition merge (resident at once)

@@ -113,6 +113,22 @@ __device__ inline unsigned int partition_of(unsigned long long key, unsigned int
     return (unsigned int)(mix64(key) >> 32) & (np - 1u);
 }
 
+// w bits (at most 64) of the 128-bit number hi:lo from bit s
+__device__ inline unsigned long long bits_at(unsigned long long lo, unsigned long long hi, int s, int w) {
+    const unsigned long long v = s >= 64 ? hi >> (s - 64) : (s == 0 ? lo : (lo >> s) | (hi << (64 - s)));
+    return w >= 64 ? v : v & ((1ull << w) - 1ull);
+}
+
+// v (below 2^(128-s)) into the 128-bit number hi:lo at bit s
+__device__ inline void put_bits(unsigned long long& lo, unsigned long long& hi, unsigned long long v, int s) {
+    if (s >= 64) {
+        hi |= v << (s - 64);
+    } else {
+        lo |= v << s;
+        if (s > 0) hi |= v >> (64 - s);
+    }
+}
+
 // low bits of the packed representative word: the complement of the points
 // at the other positions
 __device__ inline unsigned long long other_mask(const SparseArgs& a) {
@@ -434,10 +450,20 @@ __global__ __launch_bounds__(kSparseThreads) void sparse_expand(const SparseArgs
         const unsigned int pos = atomicAdd(a.pcount + pp, 1u);
         if (pos < kPartCap) {
             const size_t e = (size_t)pp * kPartCap + pos;
-            a.pkey[e] = key;
-            a.pbest[e] = best;
-            if (!packed) a.pother[e] = other;
-            a.pw[e] = make_double2(wr, wi);
+            PartRec r;
+            r.x = key;
+            r.y = best;
+            if (!packed && a.pfit) {
+                const int kb = BP * a.nq;
+                r.y = 0ull;
+                put_bits(r.x, r.y, other, kb);
+                put_bits(r.x, r.y, best >> a.qbits, kb + BP * a.nn);
+            } else if (!packed) {
+                a.pother[e] = other;
+            }
+            r.wr = wr;
+            r.wi = wi;
+            a.prec[e] = r;
         } else {
             raise_error(a.error, t, kErrOverflow);
         }
@@ -832,7 +858,8 @@ __global__ __launch_bounds__(kSparseThreads) void sparse_pmerge(const SparseArgs
     __shared__ unsigned long long lk[kPartLds], lb[kPartLds], lo[kPartLds];
     __shared__ double lwr[kPartLds], lwi[kPartLds];
     __shared__ unsigned int wcnt[kRowsP][kSpWaves];
-    __shared__ unsigned int base_s;
+    __shared__ unsigned int base_s, used_s;
+    __shared__ unsigned short lslot[kPartLds];               // the round's used slots, in slot order
     __shared__ HistTab htab;
     build_hist_tab<BP>(a, htab);
     const int ns = hist_slices<BP>(a);
@@ -856,6 +883,9 @@ __global__ __launch_bounds__(kSparseThreads) void sparse_pmerge(const SparseArgs
         lwi[k] = 0.0;
     }
 
+    const bool fit = !packed && a.pfit != 0;
+    const int kb = BP * a.nq, ob = BP * a.nn;
+    const unsigned long long kmask = (1ull << kb) - 1ull;
     // the entries of one partition, kPer per thread (beyond kPartCap: reported by
     // expand).  The loads take no branch, so that they are all in flight at once:
     // a thread past the count reads the partition's last entry again (its line is
@@ -870,10 +900,20 @@ __global__ __launch_bounds__(kSparseThreads) void sparse_pmerge(const SparseArgs
         for (int q = 0; q < kPer; ++q) {
             const unsigned int e = (unsigned int)i + (unsigned int)q * kSparseThreads;
             const size_t ge = p0 + (e < last ? e : last);
-            ek[q] = a.pkey[ge];
-            ew[q] = a.pw[ge];
-            eb[q] = a.pbest[ge];
-            eo[q] = packed ? 0ull : a.pother[ge];
+            const PartRec r = a.prec[ge];
+            ek[q] = r.x;
+            eb[q] = r.y;
+            ew[q] = make_double2(r.wr, r.wi);
+            eo[q] = packed || fit ? 0ull : a.pother[ge];
+        }
+        if (fit) {
+#pragma unroll
+            for (int q = 0; q < kPer; ++q) {
+                const unsigned long long lo = ek[q], hi = eb[q];
+                ek[q] = lo & kmask;
+                eo[q] = bits_at(lo, hi, kb, ob);
+                eb[q] = bits_at(lo, hi, kb + ob, 63 - a.qbits) << a.qbits;
+            }
         }
     };
     // a partition's count as stored (clamped where it is used, so that the
@@ -938,17 +978,24 @@ __global__ __launch_bounds__(kSparseThreads) void sparse_pmerge(const SparseArgs
                     tot += c;
                 }
             base_s = tot ? atomicAdd(out_count, tot) : 0u;
+            used_s = tot;
             a.pcount[pp] = 0u;                                // the next step's appends start at zero
         }
         __syncthreads();
-        const unsigned int base = base_s;
-        // write the groups, and free the slots for the next round
+        const unsigned int base = base_s, used = used_s;
+        // the used slots listed in slot order, so that consecutive threads
+        // write consecutive groups
 #pragma unroll
         for (int r = 0; r < kRowsP; ++r) {
             const int sl = r * kSparseThreads + i;
+            if (lk[sl] != 0ull) lslot[wcnt[r][wave] + rank_below(bal[r])] = (unsigned short)sl;
+        }
+        __syncthreads();
+        // write the groups, and free the slots for the next round
+        for (unsigned int j = (unsigned int)i; j < used; j += kSparseThreads) {
+            const int sl = lslot[j];
             const unsigned long long kk = lk[sl];
-            if (kk == 0ull) continue;
-            const unsigned long long idx = (unsigned long long)base + wcnt[r][wave] + rank_below(bal[r]);
+            const unsigned long long idx = (unsigned long long)base + j;
             if (!failed && idx < a.seg_cap) {
                 const unsigned long long key = kk - 1ull;
                 const unsigned long long nk = packed ? ((lb[sl] & omask) ^ omask) : lo[sl];

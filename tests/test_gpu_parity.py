@@ -216,7 +216,7 @@ def test_other_shapes(Q, eta_cache, make, mode, K, mask, theta, n):
 
 
 # ------------------------------------------------------------------ sparse MACGIC masks (hash-table merge)
-@pytest.mark.parametrize("store", ["AUTO", "PARTITION"])
+@pytest.mark.parametrize("store", ["HASH", "PARTITION"])
 @pytest.mark.parametrize("make,mode,K,mask,theta,n", [
     (W.structured_bath, "pre", 12, (0, 1, 2, 3, 4, 5, 8, 11), 1e-7, 30),
     (W.structured_bath, "pre", 16, (0, 1, 2, 3, 4, 5, 6, 7, 11, 15), 1e-7, 25),
@@ -242,15 +242,14 @@ def test_sparse_masks(Q, eta_cache, store, make, mode, K, mask, theta, n):
     eta = eta_cache(wl, K)
     merge = getattr(Q, f"QUAPI_MERGE_{store}")
     o, g = run_both(Q, wl.H, wl.q, wl.dt, K, eta, wl.rho0, n, mode=mode, mask=mask, theta=theta, merge=merge)
-    if store != "AUTO":
-        assert Q.quapi_info(g.ctx)["store"] == merge
+    assert Q.quapi_info(g.ctx)["store"] == merge
     assert ambiguous(o, n) == 0
     assert_rho(o, g, n)
     assert_stats(o, g, n)
     assert_groups(o, g)
 
 
-@pytest.mark.parametrize("store", ["AUTO", "PARTITION"])
+@pytest.mark.parametrize("store", ["HASH", "PARTITION"])
 @pytest.mark.parametrize("make,K,mask,theta,n", [
     # the long-memory mask: lags 0..11 exact, 16, 24 and 32 kept (80-bit
     # histories, 26 other points: the representative in a second pass)
@@ -277,7 +276,27 @@ def test_sparse_long_histories(Q, eta_cache, store, make, K, mask, theta, n):
     assert_groups(o, g)
 
 
-@pytest.mark.parametrize("store", ["AUTO", "PARTITION"])
+@pytest.mark.parametrize("K,mask,qbits,n", [
+    (40, tuple(range(12)) + (16, 24, 32), 32, 12),    # unpacked: key, other points and |w|^2 in 128 bits
+    (50, tuple(range(16)) + (24, 36, 49), 32, 12),    # unpacked, 100 + 31 bits: the other points apart
+    (24, tuple(range(8)) + (23,), 32, 26),           # packed representative word
+])
+def test_partition_entry_forms(Q, eta_cache, K, mask, qbits, n):
+    """The partition merge's three entry forms against the oracle: the packed
+    representative word, and the unpacked form with its parts in one 128-bit
+    number or with the other points in an array of their own."""
+    wl = W.structured_bath(K=K)
+    eta = eta_cache(wl, K)
+    o, g = run_both(Q, wl.H, wl.q, wl.dt, K, eta, wl.rho0, n, mode="pre", mask=mask, theta=1e-8, qbits=qbits,
+                    merge=Q.QUAPI_MERGE_PARTITION)
+    assert Q.quapi_info(g.ctx)["store"] == Q.QUAPI_MERGE_PARTITION
+    assert ambiguous(o, n) == 0
+    assert_rho(o, g, n)
+    assert_stats(o, g, n)
+    assert_groups(o, g)
+
+
+@pytest.mark.parametrize("store", ["HASH", "PARTITION"])
 def test_sparse_mask_capacity_overflow(Q, eta_cache, store):
     wl = W.structured_bath(K=10)
     eta = eta_cache(wl, 10)
@@ -412,7 +431,7 @@ def test_structured_bath_full_run(Q, store):
     check_stats(g.stats(1, n), gold)
 
 
-@pytest.mark.parametrize("store", ["AUTO", "PARTITION"])
+@pytest.mark.parametrize("store", ["HASH", "PARTITION"])
 def test_long_memory_full_run(Q, eta_cache, store):
     """The long-memory workload (dk_max 40, lags 0..11, 16, 24 and 32 exact,
     theta 1e-9: 80-bit histories on the hash-table store, ~1.6e7 groups) for
@@ -428,7 +447,7 @@ def test_long_memory_full_run(Q, eta_cache, store):
     g = Q.Propagator(wl.H, wl.q, wl.dt, wl.K, gold.eta, wl.rho0, mask=wl.mask, theta=wl.theta,
                      max_steps=wl.n_steps, max_groups=48 << 20, merge=merge)
     assert Q.quapi_info(g.ctx)["hash_merge"] == 1
-    assert Q.quapi_info(g.ctx)["store"] == (Q.QUAPI_MERGE_HASH if store == "AUTO" else merge)
+    assert Q.quapi_info(g.ctx)["store"] == merge
     print(f"[parity] long memory ({store}), {n0} stored steps then to {wl.n_steps}", flush=True)
     _run_against_golden(Q, g, gold, n0, g.groups)
     r0 = g.rho_history()

@@ -34,6 +34,7 @@ def Q():
     return quapi
 
 
+@pytest.mark.parametrize("store", ["HASH", "PARTITION"])
 @pytest.mark.parametrize("make,mode,K,mask,theta,n", [
     # the plain method: no mask, no filter
     (lambda K: W.spin_boson_ohmic(), "pre", 8, None, 0.0, 100),
@@ -46,18 +47,19 @@ def Q():
     (W.three_level, "pre", 8, (0, 1, 2, 5, 7), 1e-7, 25),
 ], ids=["spin-boson-K8", "structured-K12-E6", "structured-K10-post", "K24-tail", "K40-lags-16-24-32",
         "three-level-K8"])
-def test_fp32_form_against_oracle(Q, eta_cache, make, mode, K, mask, theta, n):
+def test_fp32_form_against_oracle(Q, eta_cache, store, make, mode, K, mask, theta, n):
     wl = make(K=K)
     eta = eta_cache(wl, K)
     mo = oracle.PRE if mode == "pre" else oracle.POST
     mq = Q.QUAPI_PRE if mode == "pre" else Q.QUAPI_POST
-    print(f"[fp32] M={wl.H.shape[0]} K={K} mode={mode} mask={mask} theta={theta} n={n}", flush=True)
+    print(f"[fp32] M={wl.H.shape[0]} K={K} mode={mode} mask={mask} theta={theta} n={n} store={store}", flush=True)
     o = oracle.Oracle(wl.H, wl.q, wl.dt, K, eta, wl.rho0, mask=mask, theta=theta, mode=mo,
                       qbits=FP32_QBITS)
     g = Q.Propagator(wl.H, wl.q, wl.dt, K, eta, wl.rho0, mask=mask, theta=theta, mode=mq,
-                     precision=Q.QUAPI_FP32_LOG)
+                     precision=Q.QUAPI_FP32_LOG, merge=getattr(Q, f"QUAPI_MERGE_{store}"))
     info = g.info()
     assert info["precision"] == Q.QUAPI_FP32_LOG and info["hash_merge"] == 1
+    assert info["store"] == getattr(Q, f"QUAPI_MERGE_{store}")
     o.step(n)
     g.step(n)
     got = g.rho_history(0, n + 1)
