@@ -111,15 +111,20 @@ def workload_spec(name: str, precision: str, store: str = "bucketed") -> dict:
         spec.update(STORE_KERNELS[store])
         tag = "_partition" if store == "partition" else ""
         spec["traffic"] = f"{spec['kernel']}{tag}_{name.replace('-', '_')}_traffic.json"
-    if precision == "fp32":
-        # the FP32 form runs every mask on the hash-table store
+    if precision == "fp32" and store == "direct":
+        # the FP32 form on the direct-mapped store (contiguous two-level masks)
+        spec.update(STORE_KERNELS["direct"])
+        spec.update({"kernel_label": "dense_step<4,2> (FP32 form)",
+                     "traffic": f"dense_step_{name.replace('-', '_')}_traffic_fp32.json"})
+    elif precision == "fp32":
+        # the FP32 form on the hash-table store (every other mask)
         tag = "_partition" if store == "partition" else ""
         spec.update({"kernel": "sparse_expand",
                      "kernel_label": "sparse_expand (FP32 form" + (", partition merge)" if tag else ")"),
                      "sources": WORKLOADS["long-memory"]["sources"],
                      "traffic": f"sparse_expand{tag}_{name.replace('-', '_')}_traffic_fp32.json"})
-        if name == "structured-bath":
-            spec["max_groups"] = 8 << 20
+    if precision == "fp32" and name == "structured-bath":
+        spec["max_groups"] = 8 << 20
     return spec
 
 
@@ -229,7 +234,8 @@ def main():
     ap.add_argument("--graph", action="store_true",
                     help="each propagation as one HIP graph (quapi_step_graph), recorded in the warm-up")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64",
-                    help="fp32: the FP32 log-domain form (hash-table merge)")
+                    help="fp32: the FP32 log-domain form (direct-mapped store for contiguous two-level "
+                         "masks, else the hash-table merge)")
     ap.add_argument("--merge", choices=["auto", "direct", "bucketed", "hash", "partition"], default="auto",
                     help="the store (QUAPI_MERGE_*); auto: the library's choice")
     ap.add_argument("--copy-mib", type=int, default=0,

@@ -71,7 +71,8 @@ struct quapi_ctx {
     // direct-mapped store (two-level systems, merge positions 0..L-1, short keys)
     bool dense = false;
     unsigned char* dn_flag[2] = {nullptr, nullptr};        // [S] occupancy bytes by buffer
-    quapi_dev::DenseRec* dn_rec[2] = {nullptr, nullptr};   // [S] records by buffer
+    quapi_dev::DenseRec* dn_rec[2] = {nullptr, nullptr};   // [S] records by buffer (FP64 form)
+    quapi_dev::DenseRec32* dn_rec32[2] = {nullptr, nullptr}; // [S] records by buffer (FP32 form)
     double* dn_tabs = nullptr;                             // [K+1] lag-sum table sets
     unsigned long long dn_slots = 0;                       // S = P^L
     unsigned int* dn_seg = nullptr;                        // [4][S/4] the planner's segment lists
@@ -236,15 +237,26 @@ int upload_initial_dense(quapi_ctx* c) {
     const size_t S = (size_t)c->dn_slots;
     const size_t n0 = c->init_key.size();
     std::vector<quapi_dev::DenseRec> rec(n0 ? n0 : 1);
+    std::vector<quapi_dev::DenseRec32> rec32(n0 ? n0 : 1);
     const unsigned char one = 1u;
     hipError_t e = hipMemsetAsync(c->dn_flag[0], 0, S, c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(c->dn_flag[1], 0, S, c->stream);
     for (size_t k = 0; k < n0 && e == hipSuccess; ++k) {
         const unsigned long long sl = c->init_key[k];
-        rec[k].w = c->init_w[k];
-        rec[k].tail = 0ull;
-        rec[k].pad = 0ull;
-        e = hipMemcpyAsync(c->dn_rec[0] + sl, &rec[k], sizeof(quapi_dev::DenseRec), hipMemcpyHostToDevice, c->stream);
+        const double2 w = c->init_w[k];
+        if (c->f32) {
+            rec32[k].lw = (float)(0.5 * std::log(w.x * w.x + w.y * w.y));
+            rec32[k].aw = (float)std::atan2(w.y, w.x);
+            rec32[k].tail = 0ull;
+            e = hipMemcpyAsync(c->dn_rec32[0] + sl, &rec32[k], sizeof(quapi_dev::DenseRec32), hipMemcpyHostToDevice,
+                               c->stream);
+        } else {
+            rec[k].w = w;
+            rec[k].tail = 0ull;
+            rec[k].pad = 0ull;
+            e = hipMemcpyAsync(c->dn_rec[0] + sl, &rec[k], sizeof(quapi_dev::DenseRec), hipMemcpyHostToDevice,
+                               c->stream);
+        }
         if (e == hipSuccess) e = hipMemcpyAsync(c->dn_flag[0] + sl, &one, 1, hipMemcpyHostToDevice, c->stream);
     }
     // the copies read host values of this frame: complete them before returning
@@ -461,11 +473,14 @@ int step_dense(quapi_ctx* c, int n_steps) {
     a.theta2 = c->theta * c->theta;
     a.qmask = c->qbits >= 64 ? 0ull : ~((1ull << c->qbits) - 1ull);
     a.error = c->d_error;
+    a.f32 = c->f32 ? 1 : 0;
     const int n = c->K + 1;
     for (int k = 0; k < n_steps; ++k) {
         const int t = c->t + 1;
         a.rec_in = c->dn_rec[c->cur];
         a.rec_out = c->dn_rec[1 - c->cur];
+        a.rec32_in = c->dn_rec32[c->cur];
+        a.rec32_out = c->dn_rec32[1 - c->cur];
         a.flag_out = c->dn_flag[1 - c->cur];
         a.plan = c->dn_plan + (t & 1);
         a.t = t;
@@ -703,9 +718,9 @@ static int create_ctx(const quapi_params* p, int n_inst, const quapi_c64* eta_al
     // merge positions 0..L-1 (L >= 2) take the bucketed path; any other set the
     // hash-table path, which keeps each history in one or two 64-bit words, the
     // key in 62 bits and the points at the other positions in one 64-bit word
-    // (the FP32 precision form is built on the hash-table merge only)
+    // (the FP32 precision form runs on the direct-mapped store and the hash-table merge)
     // (four levels, 16 pairs of 4-bit points, run on the hash-table merge, which takes any P)
-    bool contiguous = pos.size() >= 2 && p->precision == QUAPI_FP64 && M <= 3;
+    bool contiguous = pos.size() >= 2 && M <= 3;
     for (size_t i = 0; i < pos.size(); ++i)
         if (pos[i] != (int)i) contiguous = false;
     const int L = (int)pos.size();
@@ -727,7 +742,11 @@ static int create_ctx(const quapi_params* p, int n_inst, const quapi_c64* eta_al
     const bool dense_ok =
         contiguous && !batch && M == 2 && L >= quapi_dev::kDenseMinL && L <= quapi_dev::kDenseMaxL;
     if (merge == QUAPI_MERGE_DIRECT && !dense_ok) return QUAPI_EUNSUPPORTED;
-    if (merge == QUAPI_MERGE_BUCKETED && !contiguous) return QUAPI_EUNSUPPORTED;
+    // the precision form has no bucketed store: its contiguous masks go to the
+    // direct-mapped store where that applies, else to the hash table
+    const bool f32_form = p->precision == QUAPI_FP32_LOG;
+    if (f32_form && batch) return QUAPI_EUNSUPPORTED;      // the batched form is FP64
+    if (merge == QUAPI_MERGE_BUCKETED && (!contiguous || f32_form)) return QUAPI_EUNSUPPORTED;
     if (hash_store && batch) return QUAPI_EUNSUPPORTED;
     if (hash_store && contiguous) {
         // the hash table takes any merge positions
@@ -739,6 +758,10 @@ static int create_ctx(const quapi_params* p, int n_inst, const quapi_c64* eta_al
     // slots, else the bucketed store for 0..L-1, else the table
     const bool auto_dense = merge == QUAPI_MERGE_AUTO && (p->max_groups <= 0 || p->max_groups >= ipow(P, L));
     const bool use_dense = dense_ok && (merge == QUAPI_MERGE_DIRECT || auto_dense);
+    if (f32_form && contiguous && !use_dense) {
+        if (K * bits > 128 || L * bits > 62 || (K - L) * bits > 64) return QUAPI_EUNSUPPORTED;
+        contiguous = false;
+    }
     const quapi_c64* const eta0 = eta_all;                // instance 0
 
     quapi_ctx* c = new (std::nothrow) quapi_ctx();
@@ -936,7 +959,8 @@ static int create_ctx(const quapi_params* p, int n_inst, const quapi_c64* eta_al
         c->dn_slots = (unsigned long long)ipow(P, L);
         for (int b = 0; b < 2 && !rc; ++b) {
             rc = dev_alloc(c, &c->dn_flag[b], (size_t)c->dn_slots);
-            if (!rc) rc = dev_alloc(c, &c->dn_rec[b], (size_t)c->dn_slots);
+            if (!rc && !c->f32) rc = dev_alloc(c, &c->dn_rec[b], (size_t)c->dn_slots);
+            if (!rc && c->f32) rc = dev_alloc(c, &c->dn_rec32[b], (size_t)c->dn_slots);
         }
         if (!rc) rc = dev_alloc(c, &c->dn_seg, (size_t)c->dn_slots);   // four lists of S/4
         if (!rc) rc = dev_alloc(c, &c->dn_plan, 2);
@@ -1028,8 +1052,8 @@ static int create_ctx(const quapi_params* p, int n_inst, const quapi_c64* eta_al
     }
     if (c->dense) {
         // persistent workgroups, as many as are resident (their chunks never wait on one another)
-        c->dn_lds = quapi_dev::dense_lds_bytes(L, K);
-        c->dn_grid = quapi_dev::dense_step_grid(std::max(ncu, 1), c->dn_lds);
+        c->dn_lds = quapi_dev::dense_lds_bytes(L, K, c->f32);
+        c->dn_grid = quapi_dev::dense_step_grid(std::max(ncu, 1), c->dn_lds, c->f32);
         if (per_cu > 0) c->dn_grid = std::min(c->dn_grid, per_cu * std::max(ncu, 1));
         if (c->dn_grid < 1 ||
             dev_alloc(c, &c->dn_partials, (size_t)c->dn_grid * quapi_dev::partial_stride(4)) != QUAPI_OK ||
@@ -1380,7 +1404,18 @@ int quapi_batch_groups(quapi_ctx* c, int inst, long long cap, unsigned char* his
         *n_out = n;
         if (cap == 0 || n == 0) return QUAPI_OK;
         std::vector<quapi_dev::DenseRec> rec(S);
-        e = hipMemcpy(rec.data(), c->dn_rec[c->cur], S * sizeof(quapi_dev::DenseRec), hipMemcpyDeviceToHost);
+        if (c->f32) {
+            std::vector<quapi_dev::DenseRec32> r32(S);
+            e = hipMemcpy(r32.data(), c->dn_rec32[c->cur], S * sizeof(quapi_dev::DenseRec32), hipMemcpyDeviceToHost);
+            for (size_t o = 0; e == hipSuccess && o < S; ++o) {
+                if (!flag[o]) continue;
+                const double m = std::exp((double)r32[o].lw);
+                rec[o].w = make_double2(m * std::cos((double)r32[o].aw), m * std::sin((double)r32[o].aw));
+                rec[o].tail = r32[o].tail;
+            }
+        } else {
+            e = hipMemcpy(rec.data(), c->dn_rec[c->cur], S * sizeof(quapi_dev::DenseRec), hipMemcpyDeviceToHost);
+        }
         if (e != hipSuccess) return hip_to_code(e);
         const unsigned long long dm = (1ull << c->bits) - 1;
         long long written = 0;
@@ -1452,7 +1487,7 @@ int quapi_info(quapi_ctx* c, quapi_info_t* out) {
     out->K = c->K;
     out->L = c->L;
     out->bits_per_point = c->bits;
-    out->record_bytes = c->sparse ? (c->f32 ? 8 : 16) + 8 * c->sp_hw : c->dense ? 24 : 32;
+    out->record_bytes = c->sparse ? (c->f32 ? 8 : 16) + 8 * c->sp_hw : c->dense ? (c->f32 ? 16 : 24) : 32;
     out->capacity = c->sparse ? c->sp_cap : c->dense ? (long long)c->dn_slots : c->inst_buckets * c->cap;
     out->device_bytes = c->device_bytes;
     out->precision = c->f32 ? QUAPI_FP32_LOG : QUAPI_FP64;

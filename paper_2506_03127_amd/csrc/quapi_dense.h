@@ -35,6 +35,12 @@ struct alignas(32) DenseRec {
     unsigned long long pad;
 };
 
+// the FP32 precision form's record: the amplitude as FP32 (ln|w|, arg w)
+struct alignas(16) DenseRec32 {
+    float lw, aw;
+    unsigned long long tail;
+};
+
 // Lag-sum tables of one coefficient set: per table 64 entries of (A, B, Ac, Bc),
 // the sums over the table's points of (cre ds, cim ss, dre ds, dim ss), then
 // exp(-D^2 Re c_0) and exp(-D^2 Re delta_0); tables 0.. cover the segment's
@@ -52,8 +58,11 @@ struct DensePlan {
 
 struct DenseArgs {
     const unsigned int* seg;             // [4][S/4] the planner's lists
-    const DenseRec* rec_in;              // [S] the stored groups
-    DenseRec* rec_out;                   // [S] the step's merged children
+    const DenseRec* rec_in;              // [S] the stored groups (FP64 form)
+    DenseRec* rec_out;                   // [S] the step's merged children (FP64 form)
+    const DenseRec32* rec32_in;          // the same in the FP32 precision form
+    DenseRec32* rec32_out;
+    int f32;                             // 1: the FP32 precision form
     unsigned char* flag_out;             // [S] set here (all zero before the step)
     const DensePlan* plan;
     double* partials;                    // [partial_stride(4)][grid] each workgroup's sums
@@ -84,14 +93,14 @@ struct DensePlanArgs {
     unsigned int* error;
 };
 
-int dense_lds_bytes(int L, int K);        // dynamic LDS of the step kernel (lag-sum tables)
+int dense_lds_bytes(int L, int K, bool f32);   // dynamic LDS of the step kernel (lag-sum tables)
 // the lag-sum table sets of coefficient sets 0..n_sets-1 (coef: [n_sets][4][K+1],
 // tables: TableLayout) into out [n_sets][dense_tabset_doubles]
 int launch_dense_tables(const double* coef, const double* tables, int L, int K, int n_sets, double* out,
                         void* stream);
 int launch_dense_step(const DenseArgs& a, int grid, int lds_bytes, void* stream);
 int launch_dense_plan(const DensePlanArgs& a, void* stream);
-int dense_step_grid(int n_cu, int lds_bytes);   // persistent workgroups resident at once
+int dense_step_grid(int n_cu, int lds_bytes, bool f32);   // persistent workgroups resident at once
 int dense_max_chunks(long long n_segs);
 
 }  // namespace quapi_dev

@@ -239,6 +239,8 @@ struct DLds {
     double2 k4[16];                              // K4[p * 4 + h]
     double ds[4], ss[4];
     double e0, f0;                               // exp(-D^2 Re c_0), exp(-D^2 Re delta_0)
+    float2 k4f[16];                              // the FP32 form's copies
+    float dsf[4], ssf[4];
     double acc[2 * P4][kDenseThreads];           // each lane's rho by pair, re/im, over its segments
     double red[kWavesD][partial_stride(P4)];
 };
@@ -298,6 +300,35 @@ __device__ inline void tab_add(const double* tab, unsigned int q, unsigned int e
     Bc += v.w;
 }
 
+__device__ inline void tab_add(const float* tab, unsigned int q, unsigned int e, float& A, float& B, float& Ac,
+                               float& Bc) {
+    const float4 v = *reinterpret_cast<const float4*>(tab + 4 * ((size_t)q * kTabEntries + e));
+    A += v.x;
+    B += v.y;
+    Ac += v.z;
+    Bc += v.w;
+}
+
+// (ln|w|, arg w) of w = (re, im) in FP32 for the precision form's store: FP32
+// log and atan2, then one Newton step each in FP64 (ln|w| = l0 + ln(1 + u) / 2
+// with u = |w|^2 e^(-2 l0) - 1; arg w = a0 + atan of w turned by -a0), rounded
+// once.  Out of line: its temporaries do not add to the step kernel's registers.
+__device__ __noinline__ float2 to_log_domain32(double re, double im) {
+    const double n2 = norm2_nocontract(re, im);
+    const float l0 = 0.5f * logf((float)n2);
+    const double u = __builtin_fma(n2, exp_fast(-2.0 * (double)l0), -1.0);
+    const float a0 = atan2f((float)im, (float)re);
+    double sa, ca;
+    sincos_fast((double)a0, &sa, &ca);
+    const double num = im * ca - re * sa, den = re * ca + im * sa;
+    return make_float2((float)((double)l0 + __builtin_fma(-0.25 * u, u, 0.5 * u)),
+                       (float)((double)a0 + num * recip(den)));
+}
+
+__device__ inline float uniform_f(float v) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
 __device__ inline double uniform_d(double v) {
     return __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(v)),
                             __builtin_amdgcn_readfirstlane(__double2loint(v)));
@@ -316,14 +347,31 @@ __device__ inline void chunk_of(const unsigned int (&n_seg)[4], unsigned int c, 
 }
 
 // Q32: the quantised |w|^2 keeps no bit of the low word (qbits >= 32), so the
-// representative's key is the high word alone
-template <bool Q32>
+// representative's key is the high word alone.
+// F32: the precision form.  A parent's amplitude is read as FP32 (ln|w|, arg w)
+// and leaves the log domain with FP32 exp and sin/cos; the lag sums, the
+// influence exponents and each child's product are FP32; the filter test, the
+// merge sums and rho(t) are FP64, and each merged sum returns to the log domain
+// through FP32 log and atan2 refined by one FP64 Newton step, rounded once.
+template <bool Q32, bool F32>
 __global__ __launch_bounds__(kDenseThreads, 4) void dense_step(const DenseArgs a) {
     constexpr int P = P4;
     constexpr int S = partial_stride(P);
     using QT = typename std::conditional<Q32, unsigned int, unsigned long long>::type;
-    extern __shared__ double tab[];                // [n_tabs][kTabEntries][4]
+    using Real = typename std::conditional<F32, float, double>::type;
+    using Rec = typename std::conditional<F32, DenseRec32, DenseRec>::type;
+    extern __shared__ double tab_raw[];
+    Real* tab = reinterpret_cast<Real*>(tab_raw);  // [n_tabs][kTabEntries][4]
     __shared__ DLds s;
+    const Rec* rec_in;
+    Rec* rec_out;
+    if constexpr (F32) {
+        rec_in = a.rec32_in;
+        rec_out = a.rec32_out;
+    } else {
+        rec_in = a.rec_in;
+        rec_out = a.rec_out;
+    }
     const int i = threadIdx.x;
     const int wave = i >> 6;
     const unsigned int lane = lane_id();
@@ -350,16 +398,26 @@ __global__ __launch_bounds__(kDenseThreads, 4) void dense_step(const DenseArgs a
     }
 
     // ---- this step's lag-sum tables (built once per coefficient set) and K4
-    if (i < P * P) s.k4[i] = make_double2(a.tables[2 * i], a.tables[2 * i + 1]);
+    if (i < P * P) {
+        s.k4[i] = make_double2(a.tables[2 * i], a.tables[2 * i + 1]);
+        s.k4f[i] = make_float2((float)a.tables[2 * i], (float)a.tables[2 * i + 1]);
+    }
     if (i < P) {
         s.ds[i] = a.tables[TableLayout::ds(P) + i];
         s.ss[i] = a.tables[TableLayout::ss(P) + i];
+        s.dsf[i] = (float)s.ds[i];
+        s.ssf[i] = (float)s.ss[i];
     }
     {
-        const unsigned int n4 = (nsh + ntl) * kTabEntries;             // 32-byte entries
+        const unsigned int n4 = (nsh + ntl) * kTabEntries;             // entries of four sums
         const double4* src = reinterpret_cast<const double4*>(a.tabset);
-        double4* dst = reinterpret_cast<double4*>(tab);
-        for (unsigned int k = i; k < n4; k += kDenseThreads) dst[k] = src[k];
+        for (unsigned int k = i; k < n4; k += kDenseThreads) {
+            const double4 v = src[k];
+            if constexpr (F32)
+                reinterpret_cast<float4*>(tab)[k] = make_float4((float)v.x, (float)v.y, (float)v.z, (float)v.w);
+            else
+                reinterpret_cast<double4*>(tab)[k] = v;
+        }
         if (i == 0) {
             s.e0 = a.tabset[4 * n4];
             s.f0 = a.tabset[4 * n4 + 1];
@@ -375,10 +433,12 @@ __global__ __launch_bounds__(kDenseThreads, 4) void dense_step(const DenseArgs a
     const int q_shift = 2 * (L - 1);                        // output slot = (p << q_shift) | j
     // wave-uniform constants (scalar registers)
     const int n1 = K + 1;
-    const double D = a.tables[TableLayout::ds(P) + 1], Sg = a.tables[TableLayout::ss(P) + 1];
-    const double cim0 = a.coef[n1], dim0 = a.coef[3 * n1];
-    const double creL = a.coef[L], cimL = a.coef[n1 + L], dreL = a.coef[2 * n1 + L], dimL = a.coef[3 * n1 + L];
-    const double e0 = uniform_d(s.e0), f0 = uniform_d(s.f0), theta2 = a.theta2;
+    const Real D = (Real)a.tables[TableLayout::ds(P) + 1], Sg = (Real)a.tables[TableLayout::ss(P) + 1];
+    const Real cim0 = (Real)a.coef[n1], dim0 = (Real)a.coef[3 * n1];
+    const Real creL = (Real)a.coef[L], cimL = (Real)a.coef[n1 + L], dreL = (Real)a.coef[2 * n1 + L],
+               dimL = (Real)a.coef[3 * n1 + L];
+    const double e0d = uniform_d(s.e0), f0d = uniform_d(s.f0), theta2 = a.theta2;
+    const Real e0 = (Real)e0d, f0 = (Real)f0d;
     const unsigned long long qmask = a.qmask;
 
     double dropped = 0.0;
@@ -390,10 +450,10 @@ __global__ __launch_bounds__(kDenseThreads, 4) void dense_step(const DenseArgs a
             unsigned int nib = ent & 15u;
             int mn = __builtin_ctz(nib);
             nib &= nib - 1u;
-            DenseRec Rn = a.rec_in[4ull * j + mn];
+            Rec Rn = rec_in[4ull * j + mn];
 
             // lag sums over the shared points 0..L-2
-            double As = 0.0, Bs = 0.0, Acs = 0.0, Bcs = 0.0;
+            Real As = 0, Bs = 0, Acs = 0, Bcs = 0;
             for (unsigned int q = 0; q < nsh; ++q) {
                 const int st = kTabPts * (int)q, len = min(kTabPts, L - 1 - st);
                 const unsigned int v = (j >> (2 * (L - 1 - st - len))) & ((1u << (2 * len)) - 1u);
@@ -418,11 +478,25 @@ __global__ __launch_bounds__(kDenseThreads, 4) void dense_step(const DenseArgs a
                 // this parent, and the next one's record in flight
                 const int mc = mn;
                 const unsigned long long Tc = Rn.tail;
-                const double2 Wc = Rn.w;
+                Real Wcx, Wcy;                         // the parent's amplitude (FP32 form: ln|w|, arg w)
+                if constexpr (F32) {
+                    Wcx = Rn.lw;
+                    Wcy = Rn.aw;
+                } else {
+                    Wcx = Rn.w.x;
+                    Wcy = Rn.w.y;
+                }
                 if (r < b) {
                     mn = __builtin_ctz(nib);
                     nib &= nib - 1u;
-                    Rn = a.rec_in[4ull * j + mn];
+                    Rn = rec_in[4ull * j + mn];
+                }
+                if constexpr (F32) {
+                    const float m = expf(Wcx);
+                    float sa, ca;
+                    sincos_f32(Wcy, sa, ca);
+                    Wcx = m * ca;
+                    Wcy = m * sa;
                 }
                 // the propagator row of point 0, read again each parent (held across the
                 // loop it would take 16 registers)
@@ -430,9 +504,16 @@ __global__ __launch_bounds__(kDenseThreads, 4) void dense_step(const DenseArgs a
                 asm volatile("" : "+v"(k4row));
 
                 // ---- influence sums of the parent over lags 1..K
-                const double dsm = s.ds[mc], ssm = s.ss[mc];   // point L-1 of the parent (lag L)
-                double A = __builtin_fma(creL, dsm, As), B = __builtin_fma(cimL, ssm, Bs);
-                double Ac = __builtin_fma(dreL, dsm, Acs), Bc = __builtin_fma(dimL, ssm, Bcs);
+                Real dsm, ssm;                         // point L-1 of the parent (lag L)
+                if constexpr (F32) {
+                    dsm = s.dsf[mc];
+                    ssm = s.ssf[mc];
+                } else {
+                    dsm = s.ds[mc];
+                    ssm = s.ss[mc];
+                }
+                Real A = __builtin_fma(creL, dsm, As), B = __builtin_fma(cimL, ssm, Bs);
+                Real Ac = __builtin_fma(dreL, dsm, Acs), Bc = __builtin_fma(dimL, ssm, Bcs);
                 for (unsigned int q = 0; q < ntl; ++q) {
                     const int len = min(kTabPts, tail_pts - kTabPts * (int)q);
                     const unsigned int v = (unsigned int)(Tc >> (2 * kTabPts * q)) & ((1u << (2 * len)) - 1u);
@@ -441,38 +522,58 @@ __global__ __launch_bounds__(kDenseThreads, 4) void dense_step(const DenseArgs a
                 const unsigned long long ctail = ((Tc << 2) | (unsigned long long)mc) & tail_mask;
                 // pairs (0,1) and (1,0) have ds = +D, -D and equal ss: their exponents are
                 // mirror images and share one exp and one sincos; pairs (0,0), (1,1) have ds = 0
-                const double x = D * A, y = D * __builtin_fma(cim0, Sg, B);
-                const double xc = D * Ac, yc = D * __builtin_fma(dim0, Sg, Bc);
-                const double ex = exp_fast(x), exc = exp_fast(xc);
-                const double iex = recip(ex), iexc = recip(exc);
-                double sy, cy, syc, cyc;
-                sincos_fast(y, &sy, &cy);
-                sincos_fast(yc, &syc, &cyc);
-                double er[P], ei[P], fr[P], fi[P];
+                const Real x = D * A, y = D * __builtin_fma(cim0, Sg, B);
+                const Real xc = D * Ac, yc = D * __builtin_fma(dim0, Sg, Bc);
+                Real ex, exc, iex, iexc, sy, cy, syc, cyc;
+                if constexpr (F32) {
+                    ex = expf(x);
+                    exc = expf(xc);
+                    iex = 1.0f / ex;
+                    iexc = 1.0f / exc;
+                    sincos_f32(y, sy, cy);
+                    sincos_f32(yc, syc, cyc);
+                } else {
+                    ex = exp_fast(x);
+                    exc = exp_fast(xc);
+                    iex = recip(ex);
+                    iexc = recip(exc);
+                    sincos_fast(y, &sy, &cy);
+                    sincos_fast(yc, &syc, &cyc);
+                }
+                Real er[P], ei[P], fr[P], fi[P];
                 er[1] = e0 * iex * cy;  ei[1] = -(e0 * iex * sy);
                 er[2] = e0 * ex * cy;   ei[2] = e0 * ex * sy;
                 fr[1] = f0 * iexc * cyc; fi[1] = -(f0 * iexc * syc);
                 fr[2] = f0 * exc * cyc;  fi[2] = f0 * exc * syc;
 #pragma unroll
                 for (int p = 0; p < P; ++p) {
-                    const double2 k4 = s.k4[p * P + k4row];
-                    const double br = Wc.x * k4.x - Wc.y * k4.y;
-                    const double bi = Wc.x * k4.y + Wc.y * k4.x;
-                    double wr2 = br, wi2 = bi;              // pairs 0 and 3: factor 1
-                    if (p == 1 || p == 2) {
-                        wr2 = br * er[p] - bi * ei[p];
-                        wi2 = br * ei[p] + bi * er[p];
+                    Real k4x, k4y;
+                    if constexpr (F32) {
+                        k4x = s.k4f[p * P + k4row].x;
+                        k4y = s.k4f[p * P + k4row].y;
+                    } else {
+                        k4x = s.k4[p * P + k4row].x;
+                        k4y = s.k4[p * P + k4row].y;
                     }
+                    const Real br = Wcx * k4x - Wcy * k4y;
+                    const Real bi = Wcx * k4y + Wcy * k4x;
+                    Real cr = br, ci = bi;                  // pairs 0 and 3: factor 1
+                    if (p == 1 || p == 2) {
+                        cr = br * er[p] - bi * ei[p];
+                        ci = br * ei[p] + bi * er[p];
+                    }
+                    const double wr2 = (double)cr, wi2 = (double)ci;
                     const double n2 = norm2_nocontract(wr2, wi2);
                     const bool keep = (theta2 == 0.0) || !(n2 < theta2);
                     n_surv += keep ? 1u : 0u;
                     if (keep) {
+                        // rho(t) terms: the product in the form's precision, summed in FP64
                         if (p == 1) {
-                            r1r += wr2 * fr[1] - wi2 * fi[1];
-                            r1i += wr2 * fi[1] + wi2 * fr[1];
+                            r1r += (double)(cr * fr[1] - ci * fi[1]);
+                            r1i += (double)(cr * fi[1] + ci * fr[1]);
                         } else if (p == 2) {
-                            r2r += wr2 * fr[2] - wi2 * fi[2];
-                            r2i += wr2 * fi[2] + wi2 * fr[2];
+                            r2r += (double)(cr * fr[2] - ci * fi[2]);
+                            r2i += (double)(cr * fi[2] + ci * fr[2]);
                         }
                         const unsigned long long q64 = (unsigned long long)__double_as_longlong(n2) & qmask;
                         const QT q = Q32 ? (QT)(q64 >> 32) : (QT)q64;
@@ -488,18 +589,7 @@ __global__ __launch_bounds__(kDenseThreads, 4) void dense_step(const DenseArgs a
                     }
                 }
             }
-            // ---- the merged children at their slots; rho of the segment
-#pragma unroll
-            for (int p = 0; p < P; ++p) {
-                if (!any[p]) continue;
-                const unsigned long long so = ((unsigned long long)p << q_shift) | j;
-                DenseRec o;
-                o.w = make_double2(sr[p], si[p]);
-                o.tail = bt[p];
-                o.pad = 0ull;
-                a.rec_out[so] = o;
-                a.flag_out[so] = 1u;
-            }
+            // ---- rho of the segment; the merged children at their slots
             s.acc[0][i] += sr[0];          // pairs 0 and 3: the end-point factor is 1
             s.acc[1][i] += si[0];
             s.acc[2][i] += r1r;
@@ -508,6 +598,42 @@ __global__ __launch_bounds__(kDenseThreads, 4) void dense_step(const DenseArgs a
             s.acc[5][i] += r2i;
             s.acc[6][i] += sr[3];
             s.acc[7][i] += si[3];
+            if constexpr (F32) {
+                // one pair at a time, its state rotated into index 0 (one set of the
+                // conversion's temporaries live at once)
+#pragma unroll 1
+                for (int p = 0; p < P; ++p) {
+                    if (any[0]) {
+                        const float2 la = to_log_domain32(sr[0], si[0]);
+                        Rec o;
+                        o.lw = la.x;
+                        o.aw = la.y;
+                        o.tail = bt[0];
+                        const unsigned long long so = ((unsigned long long)p << q_shift) | j;
+                        rec_out[so] = o;
+                        a.flag_out[so] = 1u;
+                    }
+#pragma unroll
+                    for (int k = 0; k + 1 < P; ++k) {
+                        any[k] = any[k + 1];
+                        sr[k] = sr[k + 1];
+                        si[k] = si[k + 1];
+                        bt[k] = bt[k + 1];
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    if (!any[p]) continue;
+                    const unsigned long long so = ((unsigned long long)p << q_shift) | j;
+                    Rec o;
+                    o.w = make_double2(sr[p], si[p]);
+                    o.tail = bt[p];
+                    o.pad = 0ull;
+                    rec_out[so] = o;
+                    a.flag_out[so] = 1u;
+                }
+            }
         }
         // ---- the next chunk of this wave
         const unsigned int cn = c + stride;
@@ -549,7 +675,9 @@ int dense_tab_count(int L, int K) {
 
 size_t dense_tabset_doubles(int L, int K) { return (size_t)dense_tab_count(L, K) * kTabEntries * 4 + 4; }
 
-int dense_lds_bytes(int L, int K) { return dense_tab_count(L, K) * kTabEntries * 4 * (int)sizeof(double); }
+int dense_lds_bytes(int L, int K, bool f32) {
+    return dense_tab_count(L, K) * kTabEntries * 4 * (f32 ? (int)sizeof(float) : (int)sizeof(double));
+}
 
 int launch_dense_tables(const double* coef, const double* tables, int L, int K, int n_sets, double* out,
                         void* stream) {
@@ -560,20 +688,30 @@ int launch_dense_tables(const double* coef, const double* tables, int L, int K, 
 
 int dense_max_chunks(long long n_segs) { return (int)((n_segs + kDenseChunk - 1) / kDenseChunk) + 4; }
 
-int dense_step_grid(int n_cu, int lds_bytes) {
+int dense_step_grid(int n_cu, int lds_bytes, bool f32) {
     int n32 = 0, n64 = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n32, dense_step<true>, kDenseThreads, lds_bytes) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&n64, dense_step<false>, kDenseThreads, lds_bytes) != hipSuccess)
-        return 0;
+    const hipError_t e1 =
+        f32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n32, dense_step<true, true>, kDenseThreads, lds_bytes)
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n32, dense_step<true, false>, kDenseThreads, lds_bytes);
+    const hipError_t e2 =
+        f32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n64, dense_step<false, true>, kDenseThreads, lds_bytes)
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n64, dense_step<false, false>, kDenseThreads, lds_bytes);
+    if (e1 != hipSuccess || e2 != hipSuccess) return 0;
     const int nb = std::min(n32, n64);                       // one grid serves either form
     return nb < 1 ? 0 : nb * n_cu;
 }
 
 int launch_dense_step(const DenseArgs& a, int grid, int lds_bytes, void* stream) {
-    if ((a.qmask & 0xffffffffull) == 0ull)
-        hipLaunchKernelGGL(dense_step<true>, dim3(grid), dim3(kDenseThreads), lds_bytes, (hipStream_t)stream, a);
+    const bool q32 = (a.qmask & 0xffffffffull) == 0ull;
+    const hipStream_t st = (hipStream_t)stream;
+    if (a.f32 && q32)
+        hipLaunchKernelGGL((dense_step<true, true>), dim3(grid), dim3(kDenseThreads), lds_bytes, st, a);
+    else if (a.f32)
+        hipLaunchKernelGGL((dense_step<false, true>), dim3(grid), dim3(kDenseThreads), lds_bytes, st, a);
+    else if (q32)
+        hipLaunchKernelGGL((dense_step<true, false>), dim3(grid), dim3(kDenseThreads), lds_bytes, st, a);
     else
-        hipLaunchKernelGGL(dense_step<false>, dim3(grid), dim3(kDenseThreads), lds_bytes, (hipStream_t)stream, a);
+        hipLaunchKernelGGL((dense_step<false, false>), dim3(grid), dim3(kDenseThreads), lds_bytes, st, a);
     return (int)hipGetLastError();
 }
 

@@ -185,6 +185,34 @@ __host__ __device__ inline void sincos_reduced(double y, double& sn, double& cs)
 // |y| < kTrigArgMax (checked on the host for every phase of a run)
 __device__ inline void sincos_fast(double y, double* sn, double* cs) { sincos_reduced(y, *sn, *cs); }
 
+// FP32 sin and cos for the precision form, |y| < kTrigArgMax: the quadrant and
+// the reduced argument r = y - k pi/2 in FP64 (as above; exact to FP32
+// rounding), then Taylor series in FP32 through r^9 and r^10 on |r| <= pi/4
+// (the next terms are below 3e-9 there), coefficients 1/n!.
+__host__ __device__ inline void sincos_f32(float y, float& sn, float& cs) {
+    const double yd = (double)y;
+    const double k = __builtin_rint(yd * kTwoOverPi);
+    double rd = __builtin_fma(-k, kPio2A, yd);
+    rd = __builtin_fma(-k, kPio2B, rd);
+    const float r = (float)rd, z = r * r;
+    float ps = 1.0f / 362880.0f;                          //  1/9!
+    ps = __builtin_fmaf(ps, z, -1.0f / 5040.0f);         // -1/7!
+    ps = __builtin_fmaf(ps, z, 1.0f / 120.0f);           //  1/5!
+    ps = __builtin_fmaf(ps, z, -1.0f / 6.0f);            // -1/3!
+    const float s0 = __builtin_fmaf(ps * z, r, r);
+    float pc = -1.0f / 3628800.0f;                        // -1/10!
+    pc = __builtin_fmaf(pc, z, 1.0f / 40320.0f);         //  1/8!
+    pc = __builtin_fmaf(pc, z, -1.0f / 720.0f);          // -1/6!
+    pc = __builtin_fmaf(pc, z, 1.0f / 24.0f);            //  1/4!
+    pc = __builtin_fmaf(pc, z, -0.5f);                   // -1/2!
+    const float c0 = __builtin_fmaf(pc, z, 1.0f);
+    const int q = (int)k & 3;
+    const float a = (q & 1) ? c0 : s0;
+    const float b = (q & 1) ? s0 : c0;
+    sn = (q & 2) ? -a : a;
+    cs = ((q + 1) & 2) ? -b : b;
+}
+
 // The error word holds (failing step << 4) | code; the first error wins.
 __device__ inline void raise_error(unsigned int* err, int t, unsigned int code) {
     atomicCAS(err, 0u, ((unsigned int)t << 4) | code);

@@ -53,7 +53,7 @@ int device_scratch(unsigned char** ptr, int* grid) {
         int ncu = 0;
         if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return QUAPI_EDEVICE;
         // resident step workgroups with the largest lag-sum tables a run here can need
-        const int grid = quapi_dev::dense_step_grid(std::max(ncu, 1), quapi_dev::dense_lds_bytes(kStaticMaxL, kStaticMaxK));
+        const int grid = quapi_dev::dense_step_grid(std::max(ncu, 1), quapi_dev::dense_lds_bytes(kStaticMaxL, kStaticMaxK, false), false);
         if (grid < 1) return QUAPI_EDEVICE;
         g_scratch[dev] = (unsigned char*)p;
         g_grid[dev] = grid;
@@ -286,7 +286,7 @@ extern "C" int quapi_run_static(const quapi_params* p, int n_steps, quapi_c64* r
     // ---- t = 0 planned, then each step: the step kernel and the next planner
     unsigned char* flag[2] = {(unsigned char*)su.flag0, (unsigned char*)su.flag1};
     quapi_dev::DenseRec* rec[2] = {su.rec0, (quapi_dev::DenseRec*)(base + o_rec1)};
-    const int lds = quapi_dev::dense_lds_bytes(L, K);
+    const int lds = quapi_dev::dense_lds_bytes(L, K, false);
     quapi_dev::DensePlanArgs pa;
     pa.seg = (unsigned int*)(base + o_seg);
     pa.n_segs = (long long)ns;
@@ -307,6 +307,9 @@ extern "C" int quapi_run_static(const quapi_params* p, int n_steps, quapi_c64* r
     const int qbits = p->qbits < 0 ? 32 : std::min(p->qbits, 63);
     sa.qmask = qbits >= 64 ? 0ull : ~((1ull << qbits) - 1ull);
     sa.error = su.error;
+    sa.f32 = 0;
+    sa.rec32_in = nullptr;
+    sa.rec32_out = nullptr;
     int cur = 0;
     for (int t = 0; t <= n_steps; ++t) {
         if (t > 0) {

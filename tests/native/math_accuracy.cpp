@@ -1,5 +1,6 @@
-// Accuracy of the library's reduced-argument FP64 exp and sincos (the host
-// build of the same inline functions the kernels use) against the C library,
+// Accuracy of the library's reduced-argument FP64 exp and sincos, and of the
+// FP32 sincos of the precision form (the host build of the same inline
+// functions the kernels use) against the C library,
 // which is within one ulp of the correctly rounded value: the largest error in
 // ulps over seeded random arguments spanning the reduced range, and the
 // quadrant signs.  Prints the maxima; exits non-zero above the bound.
@@ -65,5 +66,19 @@ int main() {
     if (std::fabs(quapi_dev::exp_fast(-707.0) / std::exp(-707.0) - 1.0) > 1e-15) ++bad;
     std::printf("max ulp: exp %.2f  sin %.2f  cos %.2f\n", e_exp, e_sin, e_cos);
     if (e_exp > 4.0 || e_sin > 4.0 || e_cos > 4.0) ++bad;
+    // the precision form's FP32 sincos: error in units of 2^-24 times the larger of
+    // |value| and 1e-3, against the FP64 value of the same FP32 argument
+    double f_sin = 0, f_cos = 0;
+    for (int i = 0; i < 2000000; ++i) {
+        const double span = (i % 3 == 0) ? 3.2 : (i % 3 == 1) ? 100.0 : 0.99e5;
+        const float x = (float)uniform(-span, span);
+        float s, c;
+        quapi_dev::sincos_f32(x, s, c);
+        const double rs = std::sin((double)x), rc = std::cos((double)x);
+        f_sin = std::fmax(f_sin, std::fabs((double)s - rs) / std::fmax(std::fabs(rs), 1e-3) * 0x1.0p24);
+        f_cos = std::fmax(f_cos, std::fabs((double)c - rc) / std::fmax(std::fabs(rc), 1e-3) * 0x1.0p24);
+    }
+    std::printf("FP32 sincos, max error in 2^-24 relative units: sin %.2f  cos %.2f\n", f_sin, f_cos);
+    if (f_sin > 8.0 || f_cos > 8.0) ++bad;
     return bad ? 1 : 0;
 }

@@ -588,6 +588,11 @@ def test_store_requests_that_do_not_apply(Q, eta_cache):
     with pytest.raises(Q.QuapiError) as e:
         Q.Propagator(wl.H, wl.q, wl.dt, 12, eta, wl.rho0, mask=(0, 1, 2, 5), merge=Q.QUAPI_MERGE_BUCKETED)
     assert e.value.code == Q.QUAPI_EUNSUPPORTED
+    # the precision form has no bucketed store
+    with pytest.raises(Q.QuapiError) as e:
+        Q.Propagator(wl.H, wl.q, wl.dt, 12, eta, wl.rho0, mask=tuple(range(8)), merge=Q.QUAPI_MERGE_BUCKETED,
+                     precision=Q.QUAPI_FP32_LOG)
+    assert e.value.code == Q.QUAPI_EUNSUPPORTED
     with pytest.raises(Q.QuapiError) as e:
         Q.Propagator(wl.H, wl.q, wl.dt, 12, eta, wl.rho0, mask=(0, 1, 2, 5), merge=7)
     assert e.value.code == Q.QUAPI_EINVAL

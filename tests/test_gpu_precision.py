@@ -48,6 +48,22 @@ def Q():
 ], ids=["spin-boson-K8", "structured-K12-E6", "structured-K10-post", "K24-tail", "K40-lags-16-24-32",
         "three-level-K8"])
 def test_fp32_form_against_oracle(Q, eta_cache, store, make, mode, K, mask, theta, n):
+    check_fp32_against_oracle(Q, eta_cache, store, make, mode, K, mask, theta, n)
+
+
+# two-level masks whose merge positions are 0..L-1 with 6 <= L <= 12: the
+# precision form runs them on the direct-mapped store
+@pytest.mark.parametrize("make,mode,K,mask,theta,n", [
+    (lambda K: W.spin_boson_ohmic(), "pre", 8, None, 0.0, 100),
+    (W.structured_bath, "pre", 12, tuple(range(8)), 1e-7, 60),
+    (W.structured_bath, "post", 10, tuple(range(6)), 1e-7, 40),
+    (W.structured_bath, "pre", 12, tuple(range(9)), 1e-8, 40),
+], ids=["spin-boson-K8", "structured-K12-E8", "structured-K10-post-E6", "structured-K12-E9"])
+def test_fp32_direct_store_against_oracle(Q, eta_cache, make, mode, K, mask, theta, n):
+    check_fp32_against_oracle(Q, eta_cache, "DIRECT", make, mode, K, mask, theta, n)
+
+
+def check_fp32_against_oracle(Q, eta_cache, store, make, mode, K, mask, theta, n):
     wl = make(K=K)
     eta = eta_cache(wl, K)
     mo = oracle.PRE if mode == "pre" else oracle.POST
@@ -58,7 +74,7 @@ def test_fp32_form_against_oracle(Q, eta_cache, store, make, mode, K, mask, thet
     g = Q.Propagator(wl.H, wl.q, wl.dt, K, eta, wl.rho0, mask=mask, theta=theta, mode=mq,
                      precision=Q.QUAPI_FP32_LOG, merge=getattr(Q, f"QUAPI_MERGE_{store}"))
     info = g.info()
-    assert info["precision"] == Q.QUAPI_FP32_LOG and info["hash_merge"] == 1
+    assert info["precision"] == Q.QUAPI_FP32_LOG and info["hash_merge"] == (0 if store == "DIRECT" else 1)
     assert info["store"] == getattr(Q, f"QUAPI_MERGE_{store}")
     o.step(n)
     g.step(n)
@@ -83,24 +99,27 @@ def test_fp32_form_against_oracle(Q, eta_cache, store, make, mode, K, mask, thet
     assert np.median(d) < 1e-5
 
 
-def test_fp32_form_against_fp64_form(Q, eta_cache):
+@pytest.mark.parametrize("store,n", [("DIRECT", 1000), ("PARTITION", 200)])
+def test_fp32_form_against_fp64_form(Q, eta_cache, store, n):
     """Both forms on the same GPU, on the structured bath at dk_max = 24 with lags
-    0..11 kept (the FP64 form on the direct-mapped store), 200 steps, both comparing
-    12 mantissa bits for the representative."""
+    0..11 kept (the FP64 form on the direct-mapped store), both comparing 12
+    mantissa bits for the representative: the FP32 form on the direct-mapped
+    store over the whole 1000-step run, and on the hash-table store (partition
+    merge) over 200 steps."""
     wl = W.structured_bath()
     eta = eta_cache(wl, wl.K)
-    n = 200
     kw = dict(mask=wl.mask, theta=wl.theta, max_steps=n)
     g64 = Q.Propagator(wl.H, wl.q, wl.dt, wl.K, eta, wl.rho0, qbits=FP32_QBITS, **kw)
     g32 = Q.Propagator(wl.H, wl.q, wl.dt, wl.K, eta, wl.rho0, precision=Q.QUAPI_FP32_LOG,
-                       max_groups=4 << 20, **kw)
-    assert g64.info()["hash_merge"] == 0 and g32.info()["hash_merge"] == 1
+                       max_groups=4 << 20, merge=getattr(Q, f"QUAPI_MERGE_{store}"), **kw)
+    assert g64.info()["store"] == Q.QUAPI_MERGE_DIRECT
+    assert g32.info()["store"] == getattr(Q, f"QUAPI_MERGE_{store}")
     g64.step(n)
     g32.step(n)
     r64 = g64.rho_history(0, n + 1)
     r32 = g32.rho_history(0, n + 1)
     err = np.abs(r32 - r64).max()
-    print(f"[fp32] 200 steps, max |drho| FP32 form vs FP64 form = {err:.3e}", flush=True)
+    print(f"[fp32] {store}, {n} steps, max |drho| FP32 form vs FP64 form = {err:.3e}", flush=True)
     assert err < FP32_RHO_TOL
     s64, s32 = g64.stats(1, n), g32.stats(1, n)
     assert all(abs(a["n_groups"] - b["n_groups"]) <= max(2, 1e-3 * a["n_groups"]) for a, b in zip(s64, s32))
