@@ -55,19 +55,21 @@ typedef struct { double re, im; } quapi_c64;
 #define QUAPI_FP32_LOG  1       /* precision form: stored amplitudes as FP32 (ln|w|, arg w); each       */
                                 /* child's influence exponent (eq. inf_fun) and amplitude formed in     */
                                 /* FP32 in that log domain; the merge sums (Sec. 3.1.2), the eta table  */
-                                /* and the rho(t) sums stay FP64.  Every mask takes the hash-table      */
-                                /* merge in this form.  Results differ from the FP64 form by the FP32   */
-                                /* rounding of each child, and the filter and representative decisions */
+                                /* and the rho(t) sums stay FP64.  This form has no bucketed store:    */
+                                /* DIRECT where it applies, else the hash-table merge.  Results differ  */
+                                /* from the FP64 form by the FP32 rounding of each child, and the      */
+                                /* filter and representative decisions                                  */
                                 /* near their thresholds may differ too                                 */
 
 /* Where the groups live and how they merge (Sec. 3.1.2; quapi_params.merge). */
 #define QUAPI_MERGE_AUTO     0  /* DIRECT where it applies, else BUCKETED where it applies, else the      */
                                 /* hash-table store merged through partitions (PARTITION)                  */
 #define QUAPI_MERGE_DIRECT   1  /* a slot per key of the merge positions 0..L-1 (two-level systems,       */
-                                /* 6 <= L <= 12, FP64, lone contexts): the parents that merge are the      */
-                                /* occupied slots of an aligned segment of four, every merged group has a  */
-                                /* fixed slot; a step is a planner (the occupied segments listed by group  */
-                                /* count) and one kernel whose waves never wait on one another             */
+                                /* 6 <= L <= 12, FP64 or FP32_LOG, lone contexts): the parents that merge  */
+                                /* are the occupied slots of an aligned segment of four, every merged      */
+                                /* group has a fixed slot; a step is a planner (the occupied segments     */
+                                /* listed by group count) and one kernel whose waves never wait on one    */
+                                /* another                                                                  */
 #define QUAPI_MERGE_BUCKETED 2  /* merge positions 0..L-1: groups sorted by key in buckets of their top   */
                                 /* points, merged on chip as runs of neighbours                             */
 #define QUAPI_MERGE_HASH     3  /* any merge positions: histories in one or two words, merged through an   */
@@ -148,7 +150,8 @@ typedef struct {
     int record_bytes;         /* bytes of one stored group: 8 key + 8 history tail + 16 weight (32),    */
                               /* 8 history tail + 16 weight (24) on the direct-mapped store, whose slot  */
                               /* is the key, or 8 or 16 history + 16 weight (24 or 32) on the hash-table */
-                              /* merge, with an 8-byte weight in the FP32 precision form                 */
+                              /* merge; the FP32 precision form stores an 8-byte weight (16 B records on */
+                              /* the direct-mapped store)                                                 */
     long long capacity;       /* maximum number of stored groups (of one instance)                      */
     size_t device_bytes;      /* device memory held by the context                                      */
     int precision;            /* QUAPI_FP64 or QUAPI_FP32_LOG                                           */
