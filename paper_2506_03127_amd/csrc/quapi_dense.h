@@ -44,8 +44,8 @@ struct alignas(16) DenseRec32 {
 // Lag-sum tables of one coefficient set: per table 64 entries of (A, B, Ac, Bc),
 // the sums over the table's points of (cre ds, cim ss, dre ds, dim ss), then
 // exp(-D^2 Re c_0) and exp(-D^2 Re delta_0); tables 0.. cover the segment's
-// key points 0..L-2 three at a time (the first point the high digit), the
-// rest the tail points L..K-1 three at a time (the first point the low digit).
+// key points 0..L-2 two at a time (the first point the high digit), the
+// rest the tail points L..K-1 two at a time (the first point the low digit).
 int dense_tab_count(int L, int K);
 size_t dense_tabset_doubles(int L, int K);   // one set, padded to 32 bytes
 

@@ -46,7 +46,7 @@ namespace {
 constexpr int P4 = 4;
 constexpr int kWavesD = kDenseThreads / 64;
 constexpr int kPlanWavesD = kDensePlanThreads / 64;
-constexpr int kTabPts = 3;                                   // points per lag-sum table
+constexpr int kTabPts = 2;                                   // points per lag-sum table
 constexpr int kTabEntries = 1 << (2 * kTabPts);
 constexpr int kCountBits = 13;                               // a region's count of one list (<= 4096)
 constexpr int kTagShift = 4 * kCountBits;                    // epoch tag: bits 52..63
