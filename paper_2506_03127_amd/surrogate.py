@@ -5,10 +5,12 @@ peak's frequency, width and reorganisation energy, the Ohmic coupling, the
 bias of H_S = (eps/2) sigma_z + (Delta/2) sigma_x, and the time -- to the four
 real components of rho(t) (rho_00, Re rho_01, Im rho_01, rho_11).  It is
 trained on trajectories of the batched propagation (one instance per
-parameter point) with the library's network kernels, validated on held-out
-points, and answers a query only inside the box and in a cell of the
-(w0, gamma) plane whose held-out error is within the tolerance; every other
-query is propagated by the method itself, which also judges the error.
+parameter point) with the library's network kernels, and validated on
+held-out points per cell of the (w0, gamma) plane and per time window.  A
+query asks for rho(t) up to a horizon; the network answers it only inside the
+box and where every window up to that horizon was within the tolerance in the
+query's cell; every other query is propagated by the method itself, which
+also judges the error.
 
 The paper contains no such network; it serves parameter scans.
 """
@@ -61,12 +63,14 @@ class Solver:
     batch: int = 64
     threads: int = 8                         # eta quadratures in parallel (host)
 
-    def solve(self, pts: np.ndarray, progress: bool = False) -> np.ndarray:
-        """rho(t), t = 0..n_steps, of every point: [n_points][n_steps + 1][2][2],
-        by the batched propagation, `batch` points per launch."""
+    def solve(self, pts: np.ndarray, progress: bool = False, n_steps: Optional[int] = None) -> np.ndarray:
+        """rho(t), t = 0..n_steps (default: the solver's), of every point:
+        [n_points][n_steps + 1][2][2], by the batched propagation, `batch` points
+        per launch."""
         from concurrent.futures import ThreadPoolExecutor
-        base = workloads.structured_bath(n_steps=self.n_steps, K=self.K, n_exact=self.n_exact, theta=self.theta)
-        out = np.zeros((len(pts), self.n_steps + 1, 2, 2), dtype=np.complex128)
+        n_t = self.n_steps if n_steps is None else n_steps
+        base = workloads.structured_bath(n_steps=n_t, K=self.K, n_exact=self.n_exact, theta=self.theta)
+        out = np.zeros((len(pts), n_t + 1, 2, 2), dtype=np.complex128)
 
         def eta(pt):
             w0, g, lam, a, _ = pt
@@ -79,9 +83,9 @@ class Solver:
             etas = np.stack(etas_all[s:s + self.batch])
             Hs = np.stack([workloads.tls_hamiltonian(e, 1.0) for e in chunk[:, 4]])
             prop = quapi.BatchPropagator(base.H, base.q, base.dt, self.K, etas, base.rho0, mask=base.mask,
-                                         theta=self.theta, max_steps=self.n_steps, H_batch=Hs)
-            prop.step(self.n_steps)
-            out[s:s + len(chunk)] = np.transpose(prop.rho_all(0, self.n_steps + 1), (1, 0, 2, 3))
+                                         theta=self.theta, max_steps=n_t, H_batch=Hs)
+            prop.step(n_t)
+            out[s:s + len(chunk)] = np.transpose(prop.rho_all(0, n_t + 1), (1, 0, 2, 3))
             prop.close()
             if progress:
                 print(f"[solver] points {s + len(chunk)} of {len(pts)}", flush=True)
@@ -119,10 +123,11 @@ class Surrogate:
     depth: int = 4
     tol: float = 1e-3
     cells: Tuple[int, int] = (4, 3)          # bins of w0 and gamma for the validation
+    windows: int = 5                         # equal time windows of 0..n_steps for the validation
     seed: int = 1
     net: Optional[quapi.MLP] = None
-    accepted: Optional[np.ndarray] = None    # [cells w0][cells gamma] bool
-    cell_error: Optional[np.ndarray] = None  # held-out error per cell (nan: no point)
+    accepted: Optional[np.ndarray] = None    # [cells w0][cells gamma][windows] bool
+    cell_error: Optional[np.ndarray] = None  # held-out error per cell and window (nan: no point)
     history: Dict[str, list] = field(default_factory=dict)
     stream: object = None                    # torch stream of the network and of its batches
     residual: bool = True                    # learn rho(t) minus the system's own evolution
@@ -232,37 +237,52 @@ class Surrogate:
         rho[..., 1, 1] = c[..., 3]
         return rho + self._baseline(pts, n_t)
 
+    def _window(self, t: np.ndarray) -> np.ndarray:
+        """Time window of step t (0..n_steps): equal spans, the last one closed."""
+        n = max(self.solver.n_steps, 1)
+        return np.minimum((np.asarray(t) * self.windows) // n, self.windows - 1)
+
     def validate(self, pts: np.ndarray, rho: np.ndarray) -> np.ndarray:
         """Held-out error of every point (max over t and elements of |rho_net -
-        rho_method|); a cell is accepted when its held-out points are all within
-        the tolerance."""
-        err = np.abs(self.predict(pts, rho.shape[1]) - rho).max(axis=(1, 2, 3))
+        rho_method|); a (cell, window) is accepted when its held-out points are
+        all within the tolerance over the window's steps."""
+        e_t = np.abs(self.predict(pts, rho.shape[1]) - rho).max(axis=(2, 3))      # [points][t]
+        win = self._window(np.arange(rho.shape[1]))
+        e_w = np.stack([e_t[:, win == w].max(axis=1) for w in range(self.windows)], axis=1)
         cw, cg = self._cell(pts)
-        self.cell_error = np.full(self.cells, np.nan)
+        self.cell_error = np.full(self.cells + (self.windows,), np.nan)
         for a in range(self.cells[0]):
             for b in range(self.cells[1]):
                 sel = (cw == a) & (cg == b)
                 if sel.any():
-                    self.cell_error[a, b] = err[sel].max()
+                    self.cell_error[a, b] = e_w[sel].max(axis=0)
         self.accepted = np.nan_to_num(self.cell_error, nan=np.inf) <= self.tol
-        return err
+        return e_t.max(axis=1)
 
-    # ---- queries
-    def query(self, pts: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
-        """rho(t), t = 0..n_steps, of every point, and which were answered by the
-        network (the rest by the method)."""
-        pts = np.asarray(pts, dtype=np.float64).reshape(-1, len(PARAMS))
+    def answers(self, pts: np.ndarray, t_max: int) -> np.ndarray:
+        """Which points the network answers up to step t_max: inside the box,
+        and every window through t_max's accepted in the point's cell."""
         use = self.box.contains(pts)
         if self.accepted is None:
-            use[:] = False
-        else:
-            cw, cg = self._cell(pts)
-            use &= self.accepted[cw, cg]
-        out = np.empty((len(pts), self.solver.n_steps + 1, 2, 2), dtype=np.complex128)
+            return np.zeros(len(pts), dtype=bool)
+        cw, cg = self._cell(pts)
+        last = int(self._window(np.array([t_max]))[0])
+        return use & self.accepted[cw, cg, :last + 1].all(axis=1)
+
+    # ---- queries
+    def query(self, pts: np.ndarray, t_max: Optional[int] = None) -> Tuple[np.ndarray, np.ndarray]:
+        """rho(t), t = 0..t_max (default n_steps), of every point, and which were
+        answered by the network (the rest by the method, propagated to t_max)."""
+        pts = np.asarray(pts, dtype=np.float64).reshape(-1, len(PARAMS))
+        t_max = self.solver.n_steps if t_max is None else int(t_max)
+        if not 0 <= t_max <= self.solver.n_steps:
+            raise ValueError(f"t_max {t_max} outside 0..{self.solver.n_steps}")
+        use = self.answers(pts, t_max)
+        out = np.empty((len(pts), t_max + 1, 2, 2), dtype=np.complex128)
         if use.any():
-            out[use] = self.predict(pts[use])
+            out[use] = self.predict(pts[use], t_max + 1)
         if (~use).any():
-            out[~use] = self.solver.solve(pts[~use])
+            out[~use] = self.solver.solve(pts[~use], n_steps=t_max)
         return out, use
 
 
@@ -316,7 +336,10 @@ def main(argv=None):
         "solve_s": t_solve, "fit_s": t_fit, "loss_final": sur.history["loss"][-1][1],
         "held_out_error_median": float(np.median(err)), "held_out_error_p90": float(np.percentile(err, 90)),
         "held_out_error_max": float(err.max()), "tol": args.tol,
-        "cells_accepted": int(sur.accepted.sum()), "cells": int(sur.accepted.size),
+        "cells_accepted": int(sur.accepted.all(axis=2).sum()), "cells": int(sur.accepted[..., 0].size),
+        "windows": sur.windows,
+        "cell_windows_accepted_from_t0": [int(sur.accepted[..., :w + 1].all(axis=2).sum())
+                                          for w in range(sur.windows)],
         "query_64_points_network_ms": 1e3 * t_net, "query_64_points_method_ms": 1e3 * t_method,
     }
     print(json.dumps(out), flush=True)

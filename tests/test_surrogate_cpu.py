@@ -53,10 +53,42 @@ def test_box_and_cells():
     assert f[0, 0, 5] == -1 and f[0, -1, 5] == 1
 
 
+class _Stub(S.Solver):
+    def solve(self, pts, progress=False, n_steps=None):
+        n = self.n_steps if n_steps is None else n_steps
+        return np.full((len(pts), n + 1, 2, 2), 7.0 + 0j)
+
+
 def test_untrained_surrogate_sends_everything_to_the_method():
-    class Stub(S.Solver):
-        def solve(self, pts):
-            return np.full((len(pts), self.n_steps + 1, 2, 2), 7.0 + 0j)
-    sur = S.Surrogate(solver=Stub(n_steps=4))
+    sur = S.Surrogate(solver=_Stub(n_steps=4))
     got, used = sur.query(sur.box.sample(3, seed=2))
     assert not used.any() and np.all(got == 7.0)
+    got, used = sur.query(sur.box.sample(3, seed=2), t_max=2)
+    assert not used.any() and got.shape == (3, 3, 2, 2)
+
+
+def test_time_windows_and_horizons():
+    sur = S.Surrogate(solver=_Stub(n_steps=50), windows=5)
+    # equal spans of ten steps, the last one closed at step 50
+    assert list(sur._window(np.array([0, 9, 10, 39, 40, 49, 50]))) == [0, 0, 1, 3, 4, 4, 4]
+    pts = sur.box.sample(400, seed=3)
+    cw, cg = sur._cell(pts)
+    # accept windows 0 and 1 of cell (0, 0), and every window of cell (1, 1)
+    sur.accepted = np.zeros(sur.cells + (sur.windows,), dtype=bool)
+    sur.accepted[0, 0, :2] = True
+    sur.accepted[1, 1, :] = True
+    for t_max, want in ((5, ((0, 0), (1, 1))), (19, ((0, 0), (1, 1))), (20, ((1, 1),)), (50, ((1, 1),))):
+        use = sur.answers(pts, t_max)
+        expect = np.zeros(len(pts), dtype=bool)
+        for a, b in want:
+            expect |= (cw == a) & (cg == b)
+        assert np.array_equal(use, expect), t_max
+    # outside the box: never the network
+    out = pts[:1].copy()
+    out[0, 1] = 1.0
+    assert not sur.answers(out, 5).any()
+    try:
+        sur.query(pts[:1], t_max=51)
+        assert False
+    except ValueError:
+        pass
