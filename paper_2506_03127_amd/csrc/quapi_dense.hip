@@ -309,22 +309,6 @@ __device__ inline void tab_add(const float* tab, unsigned int q, unsigned int e,
     Bc += v.w;
 }
 
-// (ln|w|, arg w) of w = (re, im) in FP32 for the precision form's store: FP32
-// log and atan2, then one Newton step each in FP64 (ln|w| = l0 + ln(1 + u) / 2
-// with u = |w|^2 e^(-2 l0) - 1; arg w = a0 + atan of w turned by -a0), rounded
-// once.  Out of line: its temporaries do not add to the step kernel's registers.
-__device__ __noinline__ float2 to_log_domain32(double re, double im) {
-    const double n2 = norm2_nocontract(re, im);
-    const float l0 = 0.5f * logf((float)n2);
-    const double u = __builtin_fma(n2, exp_fast(-2.0 * (double)l0), -1.0);
-    const float a0 = atan2f((float)im, (float)re);
-    double sa, ca;
-    sincos_fast((double)a0, &sa, &ca);
-    const double num = im * ca - re * sa, den = re * ca + im * sa;
-    return make_float2((float)((double)l0 + __builtin_fma(-0.25 * u, u, 0.5 * u)),
-                       (float)((double)a0 + num * recip(den)));
-}
-
 __device__ inline float uniform_f(float v) {
     return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
 }

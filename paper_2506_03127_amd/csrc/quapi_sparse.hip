@@ -259,7 +259,8 @@ __host__ __device__ constexpr size_t sparse_chunk_lds(int n_chunks) {
 // F32: the precision form.  A group's amplitude is read as (ln|w|, arg w) in
 // FP32; each child adds ln K4 and its influence exponent in FP32, leaves the
 // log domain with FP32 exp and sin/cos, and enters the filter, the merge sums
-// and rho(t) in FP64.
+// and rho(t) in FP64.  (Two levels: the parent leaves the log domain once and
+// the mirrored pairs share one FP32 exp and sin/cos, as in FP64.)
 //
 // A workgroup takes kSparseThreads parents per pass.  Their children merge
 // first in a table in the LDS (key, best word, weight sums; unpacked form:
@@ -276,7 +277,7 @@ __global__ __launch_bounds__(kSparseThreads) void sparse_expand(const SparseArgs
     constexpr unsigned long long DM = (1ull << BP) - 1;
     __shared__ double k4re[P * P], k4im[P * P], ds[P], ss[P];
     __shared__ double cre[kMaxK + 1], cim[kMaxK + 1], dre[kMaxK + 1], dim[kMaxK + 1];
-    __shared__ double e0f0[2];                               // two-level FP64: exp(-D^2 Re c_0), exp(-D^2 Re delta_0)
+    __shared__ double e0f0[2];                               // two levels: exp(-D^2 Re c_0), exp(-D^2 Re delta_0)
     // FP32 precision form: ln|K4|, arg K4 and the exponent tables in FP32
     __shared__ float lk4[F32 ? P * P : 1], ak4[F32 ? P * P : 1], dsf[F32 ? P : 1], ssf[F32 ? P : 1];
     __shared__ float cref[F32 ? kMaxK + 1 : 1], cimf[F32 ? kMaxK + 1 : 1];
@@ -345,7 +346,7 @@ __global__ __launch_bounds__(kSparseThreads) void sparse_expand(const SparseArgs
         }
     }
     __syncthreads();
-    if (P == 4 && !F32 && i == 0) {
+    if (P == 4 && i == 0) {
         const double D = ds[1];
         e0f0[0] = exp(-D * (cre[0] * D));
         e0f0[1] = exp(-D * (dre[0] * D));
@@ -526,10 +527,46 @@ __global__ __launch_bounds__(kSparseThreads) void sparse_expand(const SparseArgs
                 fr1 = f0 * iexc * cyc; fi1 = -(f0 * iexc * syc);
                 fr2 = f0 * exc * cyc;  fi2 = f0 * exc * syc;
             }
+            // two levels, FP32: the same mirror, in FP32; the parent leaves the log
+            // domain once and each child is its product with K4 and the factor
+            float pwr = 0.f, pwi = 0.f;
+            float ger1 = 1.f, gei1 = 0.f, ger2 = 1.f, gei2 = 0.f, gfr1 = 1.f, gfi1 = 0.f, gfr2 = 1.f, gfi2 = 0.f;
+            if constexpr (P == 4 && F32) {
+                const float m = expf(Wl.x);
+                float sa, ca;
+                sincos_f32(Wl.y, sa, ca);
+                pwr = m * ca;
+                pwi = m * sa;
+                const float D = dsf[1], Sg = ssf[1];
+                const float x = D * (float)A, y = D * __builtin_fmaf(cimf[0], Sg, (float)B);
+                const float xc = D * (float)Ac, yc = D * __builtin_fmaf(dimf[0], Sg, (float)Bc);
+                const float ex = expf(x), exc = expf(xc);
+                const float iex = 1.0f / ex, iexc = 1.0f / exc;
+                float sy, cy, syc, cyc;
+                sincos_f32(y, sy, cy);
+                sincos_f32(yc, syc, cyc);
+                const float e0 = (float)e0f0[0], f0 = (float)e0f0[1];
+                ger1 = e0 * iex * cy;  gei1 = -(e0 * iex * sy);
+                ger2 = e0 * ex * cy;   gei2 = e0 * ex * sy;
+                gfr1 = f0 * iexc * cyc; gfi1 = -(f0 * iexc * syc);
+                gfr2 = f0 * exc * cyc;  gfi2 = f0 * exc * syc;
+            }
 #pragma unroll
             for (int p = 0; p < P; ++p) {
                 double wr, wi, rr, ri;   // the child's amplitude; its rho(t) term
-                if constexpr (F32) {
+                if constexpr (P == 4 && F32) {
+                    const float k4r = (float)k4re[p * P + h0], k4i = (float)k4im[p * P + h0];
+                    const float br = pwr * k4r - pwi * k4i;
+                    const float bi = pwr * k4i + pwi * k4r;
+                    float er = 1.f, ei = 0.f, fr = 1.f, fi = 0.f;
+                    if (p == 1) { er = ger1; ei = gei1; fr = gfr1; fi = gfi1; }
+                    if (p == 2) { er = ger2; ei = gei2; fr = gfr2; fi = gfi2; }
+                    const float cr = br * er - bi * ei, ci = br * ei + bi * er;
+                    wr = (double)cr;
+                    wi = (double)ci;
+                    rr = (double)(cr * fr - ci * fi);
+                    ri = (double)(cr * fi + ci * fr);
+                } else if constexpr (F32) {
                     float lr = Wl.x + lk4[p * P + h0], ph = Wl.y + ak4[p * P + h0];
                     float lc = lr, pc = ph;
                     const float dsp = dsf[p], ssp = ssf[p];
@@ -733,9 +770,6 @@ __global__ __launch_bounds__(kSparseThreads) void sparse_expand(const SparseArgs
 // The FP64 sum w of a group back to FP32 (ln|w|, arg w): FP64 log and atan2,
 // rounded once.  Not inlined, so that the unrolled rows of the compact loop do
 // not each hold the registers of the two functions.
-__device__ __noinline__ float2 to_log_domain(double wr, double wi) {
-    return make_float2((float)(0.5 * log(norm2_nocontract(wr, wi))), (float)atan2(wi, wr));
-}
 
 // unpacked form: among the children with the key's largest quantised |w|^2,
 // the smallest points at the other positions (oldest first)
@@ -827,7 +861,7 @@ __global__ __launch_bounds__(kSparseThreads) void sparse_compact(const SparseArg
 #pragma unroll
                 for (int w = 0; w < W; ++w) a.h_out[o * W + w] = hist.w[w];
                 if (F32) {
-                    a.wf_out[o] = to_log_domain(e->wr, e->wi);
+                    a.wf_out[o] = to_log_domain32(e->wr, e->wi);
                 } else {
                     a.w_out[o] = make_double2(e->wr, e->wi);
                 }
@@ -1004,7 +1038,7 @@ __global__ __launch_bounds__(kSparseThreads) void sparse_pmerge(const SparseArgs
                 const unsigned long long o = seg_base + idx;
 #pragma unroll
                 for (int w = 0; w < W; ++w) a.h_out[o * W + w] = hist.w[w];
-                if (F32) a.wf_out[o] = to_log_domain(lwr[sl], lwi[sl]);
+                if (F32) a.wf_out[o] = to_log_domain32(lwr[sl], lwi[sl]);
                 else a.w_out[o] = make_double2(lwr[sl], lwi[sl]);
             } else if (!failed) {
                 raise_error(a.error, a.t, kErrOverflow);
