@@ -309,9 +309,9 @@ __device__ inline void tab_add(const float* tab, unsigned int q, unsigned int e,
     Bc += v.w;
 }
 
-__device__ inline float uniform_f(float v) {
-    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
-}
+// fused multiply-add in the precision of its operands
+__device__ inline float fma_r(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ inline double fma_r(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 __device__ inline double uniform_d(double v) {
     return __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(v)),
@@ -496,8 +496,8 @@ __global__ __launch_bounds__(kDenseThreads, 4) void dense_step(const DenseArgs a
                     dsm = s.ds[mc];
                     ssm = s.ss[mc];
                 }
-                Real A = __builtin_fma(creL, dsm, As), B = __builtin_fma(cimL, ssm, Bs);
-                Real Ac = __builtin_fma(dreL, dsm, Acs), Bc = __builtin_fma(dimL, ssm, Bcs);
+                Real A = fma_r(creL, dsm, As), B = fma_r(cimL, ssm, Bs);
+                Real Ac = fma_r(dreL, dsm, Acs), Bc = fma_r(dimL, ssm, Bcs);
                 for (unsigned int q = 0; q < ntl; ++q) {
                     const int len = min(kTabPts, tail_pts - kTabPts * (int)q);
                     const unsigned int v = (unsigned int)(Tc >> (2 * kTabPts * q)) & ((1u << (2 * len)) - 1u);
@@ -506,8 +506,8 @@ __global__ __launch_bounds__(kDenseThreads, 4) void dense_step(const DenseArgs a
                 const unsigned long long ctail = ((Tc << 2) | (unsigned long long)mc) & tail_mask;
                 // pairs (0,1) and (1,0) have ds = +D, -D and equal ss: their exponents are
                 // mirror images and share one exp and one sincos; pairs (0,0), (1,1) have ds = 0
-                const Real x = D * A, y = D * __builtin_fma(cim0, Sg, B);
-                const Real xc = D * Ac, yc = D * __builtin_fma(dim0, Sg, Bc);
+                const Real x = D * A, y = D * fma_r(cim0, Sg, B);
+                const Real xc = D * Ac, yc = D * fma_r(dim0, Sg, Bc);
                 Real ex, exc, iex, iexc, sy, cy, syc, cyc;
                 if constexpr (F32) {
                     ex = expf(x);
