@@ -200,7 +200,8 @@ int quapi_step(quapi_ctx* c, int n_steps);
  * by later calls that start at the same step with the same buffers (after
  * quapi_reset, for instance).  A call that does not match the recorded run
  * records anew.  Results equal quapi_step's bit for bit.  Launch timing
- * (quapi_profile_*) skips graph steps.  Bucketed store only (lone or batched).
+ * (quapi_profile_*) skips graph steps.  The direct-mapped and bucketed stores
+ * (lone or batched).
  * Recording captures the context's stream: nothing else may be enqueued on it
  * meanwhile (e.g. by another thread's context on the shared library stream). 
  * Errors: EINVAL (n_steps < 1), ESTATE (a previous step failed), ENOMEM

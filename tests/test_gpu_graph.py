@@ -1,7 +1,8 @@
 """quapi_step_graph: the launches of quapi_step recorded once into a HIP graph
 and replayed.  Every replay must equal eager stepping bit for bit (rho(t),
 counters, stored groups), also with eager steps, synchronisations and other
-replays between them; the batched form likewise; the hash-table merge refuses.
+replays between them, on the direct-mapped and the bucketed store; the batched
+form likewise; the hash-table merge refuses.
 """
 import numpy as np
 import pytest
@@ -28,12 +29,16 @@ def _eta(Q, wl, bath, K):
     return Q.quapi_eta(bath.ohmic_alpha, bath.ohmic_wc, [x for pk in bath.peaks for x in pk], wl.beta, wl.dt, K)
 
 
-def test_graph_replays_equal_eager_steps(Q):
-    wl = W.structured_bath(K=12, n_exact=6, theta=1e-7)
+# lags 0..5 exact: merge positions 0..4, the bucketed store; lags 0..7: 0..6, the
+# direct-mapped store
+@pytest.mark.parametrize("n_exact,store", [(6, "BUCKETED"), (8, "DIRECT")])
+def test_graph_replays_equal_eager_steps(Q, n_exact, store):
+    wl = W.structured_bath(K=12, n_exact=n_exact, theta=1e-7)
     K, n, extra = 12, 40, 5
     eta = _eta(Q, wl, wl.bath, K)
     mk = lambda: Q.Propagator(wl.H, wl.q, wl.dt, K, eta, wl.rho0, mask=wl.mask, theta=wl.theta)
     ref = mk()
+    assert ref.info()["store"] == getattr(Q, f"QUAPI_MERGE_{store}")
     ref.step(n)
     ref_groups = ref.groups()
     ref_stats = ref.stats(1, n)
