@@ -158,3 +158,27 @@ def test_long_memory_fp64_spread_over_qbits_and_the_fp32_form(Q, eta_cache):
     # form's bar, and the FP32 form's difference is of that order, not above it
     assert spread > 100 * FP32_RHO_TOL
     assert d32 < 3.0 * spread
+
+
+def test_fp32_direct_store_is_deterministic(Q, eta_cache):
+    """The precision form on the direct-mapped store sums rho(t) and the
+    counters in a fixed order: two contexts, and one of them after a reset,
+    give the same bits."""
+    wl = W.structured_bath(K=12, n_exact=8, theta=1e-7)
+    eta = eta_cache(wl, 12)
+    n = 60
+    mk = lambda: Q.Propagator(wl.H, wl.q, wl.dt, 12, eta, wl.rho0, mask=wl.mask, theta=wl.theta,
+                              precision=Q.QUAPI_FP32_LOG)
+    a, b = mk(), mk()
+    assert a.info()["store"] == Q.QUAPI_MERGE_DIRECT
+    a.step(n)
+    b.step(n)
+    ra = a.rho_history(0, n + 1)
+    assert np.array_equal(ra, b.rho_history(0, n + 1))
+    assert a.stats(1, n) == b.stats(1, n)
+    b.reset()
+    b.step(n)
+    assert np.array_equal(ra, b.rho_history(0, n + 1))
+    ha, wa = a.groups()
+    hb, wb = b.groups()
+    assert np.array_equal(ha, hb) and np.array_equal(wa, wb)
