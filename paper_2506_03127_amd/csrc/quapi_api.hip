@@ -220,6 +220,7 @@ int launch_dense_planner(quapi_ctx* c, int t) {
     pa.plan = c->dn_plan + ((t + 1) & 1);
     pa.plan_prev = c->dn_plan + (t & 1);
     pa.reduce_t = t;
+    pa.clear_spent = quapi_dev::dense_clear_due(t);
     pa.partials = c->dn_partials;
     pa.n_parts = c->dn_grid;
     pa.rho_hist = c->d_rho;
@@ -238,7 +239,7 @@ int upload_initial_dense(quapi_ctx* c) {
     const size_t n0 = c->init_key.size();
     std::vector<quapi_dev::DenseRec> rec(n0 ? n0 : 1);
     std::vector<quapi_dev::DenseRec32> rec32(n0 ? n0 : 1);
-    const unsigned char one = 1u;
+    const unsigned char one = (unsigned char)quapi_dev::dense_tag(0);
     hipError_t e = hipMemsetAsync(c->dn_flag[0], 0, S, c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(c->dn_flag[1], 0, S, c->stream);
     for (size_t k = 0; k < n0 && e == hipSuccess; ++k) {
@@ -1400,7 +1401,8 @@ int quapi_batch_groups(quapi_ctx* c, int inst, long long cap, unsigned char* his
         hipError_t e = hipMemcpy(flag.data(), c->dn_flag[c->cur], S, hipMemcpyDeviceToHost);
         if (e != hipSuccess) return hip_to_code(e);
         long long n = 0;
-        for (unsigned char f : flag) n += f != 0u;
+        const unsigned char tag = (unsigned char)quapi_dev::dense_tag(c->t);
+        for (unsigned char f : flag) n += f == tag;
         *n_out = n;
         if (cap == 0 || n == 0) return QUAPI_OK;
         std::vector<quapi_dev::DenseRec> rec(S);
@@ -1408,7 +1410,7 @@ int quapi_batch_groups(quapi_ctx* c, int inst, long long cap, unsigned char* his
             std::vector<quapi_dev::DenseRec32> r32(S);
             e = hipMemcpy(r32.data(), c->dn_rec32[c->cur], S * sizeof(quapi_dev::DenseRec32), hipMemcpyDeviceToHost);
             for (size_t o = 0; e == hipSuccess && o < S; ++o) {
-                if (!flag[o]) continue;
+                if (flag[o] != tag) continue;
                 const double m = std::exp((double)r32[o].lw);
                 rec[o].w = make_double2(m * std::cos((double)r32[o].aw), m * std::sin((double)r32[o].aw));
                 rec[o].tail = r32[o].tail;
@@ -1420,7 +1422,7 @@ int quapi_batch_groups(quapi_ctx* c, int inst, long long cap, unsigned char* his
         const unsigned long long dm = (1ull << c->bits) - 1;
         long long written = 0;
         for (size_t o = 0; o < S && written < cap; ++o) {
-            if (!flag[o]) continue;
+            if (flag[o] != tag) continue;
             unsigned char* row = hist + (size_t)written * c->K;
             for (int j = 0; j < c->K; ++j) {
                 unsigned long long d;

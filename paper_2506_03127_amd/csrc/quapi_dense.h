@@ -10,7 +10,9 @@ namespace quapi_dev {
 // as a base-4 number with point 0 most significant, so slots are in key order.
 // A slot holds a 32-byte record -- the group amplitude and the rest of the
 // representative's history (points L..K-1, point L lowest) -- and an occupancy
-// byte (1: the slot holds a group) in an array of its own.
+// byte in an array of its own: the slot holds a group after step t when its
+// byte is dense_tag(t) (other values are left by earlier steps; the planner
+// clears a buffer every kDenseClearPeriod launches, so no old tag comes back).
 //
 // Segment j is the four slots [4 j, 4 j + 4): the parents whose children merge
 // (same points 0..L-2, Sec. 3.1.2).  The merged child of segment j by pair p
@@ -28,6 +30,15 @@ constexpr int kDensePlanThreads = 256;
 constexpr int kDensePlanIters = 2;             // 16-byte loads (four segments) per planner thread
 constexpr int kDenseRegion = kDensePlanThreads * kDensePlanIters * 4;   // segments per planner workgroup
 constexpr int kDenseMaxRegions = (1 << (2 * (kDenseMaxL - 1))) / kDenseRegion;
+
+// Occupancy tag of the groups after step t.  A buffer holds the tags of every
+// other step since its last clear; tags repeat after 255 steps, so a stale byte
+// could match only 510 steps on.  The planner clears the buffer the planned step
+// writes when that step is 0 or 1 modulo kDenseClearPeriod: each buffer at least
+// every kDenseClearPeriod steps.
+constexpr int kDenseClearPeriod = 128;
+__host__ __device__ inline unsigned int dense_tag(int t) { return 1u + (unsigned int)(t % 255); }
+inline int dense_clear_due(int t_done) { return (t_done + 1) % kDenseClearPeriod < 2 ? 1 : 0; }
 
 struct alignas(32) DenseRec {
     double2 w;                   // group amplitude
@@ -63,14 +74,14 @@ struct DenseArgs {
     const DenseRec32* rec32_in;          // the same in the FP32 precision form
     DenseRec32* rec32_out;
     int f32;                             // 1: the FP32 precision form
-    unsigned char* flag_out;             // [S] set here (all zero before the step)
+    unsigned char* flag_out;             // [S] set to dense_tag(t) at the step's merged children
     const DensePlan* plan;
     double* partials;                    // [partial_stride(4)][grid] each workgroup's sums
     const double* tables;                // TableLayout
     const double* coef;                  // this step's coefficients: cre, cim, dre, dim [4][K+1]
     const double* tabset;                // this step's lag-sum tables (dense_tabset_doubles)
     long long n_segs;                    // S/4
-    int L, K, t;
+    int L, K, t;                         // (the kernel takes its tag from t)
     double theta2;
     unsigned long long qmask;
     unsigned int* error;
@@ -78,7 +89,8 @@ struct DenseArgs {
 
 struct DensePlanArgs {
     const unsigned int* flags;           // [S/4] occupancy of the stored groups, a byte per slot
-    unsigned int* flags_spent;           // [S/4] occupancy of the step before, cleared here for the next
+    unsigned int* flags_spent;           // [S/4] occupancy buffer the planned step writes
+    int clear_spent;                     // 1: clear flags_spent first (dense_clear_due(reduce_t))
     unsigned int* seg;                   // [4][S/4] lists for the planned step
     long long n_segs;                    // S/4
     DensePlan* plan;                     // plan of the step to plan

@@ -58,6 +58,15 @@ __device__ inline unsigned int comp4(const uint4& v, int k) {
     return k == 0 ? v.x : k == 1 ? v.y : k == 2 ? v.z : v.w;
 }
 
+// the four occupancy bits of a segment's word of bytes (slot r: byte r): the
+// bytes equal to the tag (x = v ^ tag has a zero byte there; the sum below
+// sets bit 7 of every nonzero byte and of no zero one)
+__device__ inline unsigned int seg_nibble(unsigned int v, unsigned int tagx4) {
+    const unsigned int x = v ^ tagx4;
+    const unsigned int z = ~(((x & 0x7f7f7f7fu) + 0x7f7f7f7fu) | x) & 0x80808080u;
+    return ((z >> 7) & 1u) | ((z >> 14) & 2u) | ((z >> 21) & 4u) | ((z >> 28) & 8u);
+}
+
 __device__ inline unsigned int wave_sum_u32(unsigned int v) {
     for (int off = 32; off > 0; off >>= 1) v += (unsigned int)__shfl_xor((int)v, off, 64);
     return v;
@@ -126,21 +135,22 @@ __global__ __launch_bounds__(kDensePlanThreads) void dense_plan(const DensePlanA
 
     // ---- pass 1: this wave's segments and their counts per list
     const long long wbase = (long long)w * kDenseRegion + (long long)wave * (kDenseRegion / kPlanWavesD);
+    const unsigned int tagx4 = dense_tag(a.reduce_t) * 0x01010101u;   // the finished step's tag in each byte
     uint4 f[kDensePlanIters];
 #pragma unroll
     for (int it = 0; it < kDensePlanIters; ++it) {
         const long long s0 = wbase + 256 * it + 4 * (long long)lane;   // NS is a multiple of 4
         f[it] = s0 < NS ? *reinterpret_cast<const uint4*>(a.flags + s0) : make_uint4(0u, 0u, 0u, 0u);
-        // the occupancy the finished step read is read by no one now: cleared for the
-        // planned step's output
-        if (s0 < NS) *reinterpret_cast<uint4*>(a.flags_spent + s0) = make_uint4(0u, 0u, 0u, 0u);
+        // the buffer the planned step writes holds the tags of earlier steps, which
+        // differ from the tags of the next 508 steps; it is cleared now and then
+        if (a.clear_spent && s0 < NS) *reinterpret_cast<uint4*>(a.flags_spent + s0) = make_uint4(0u, 0u, 0u, 0u);
     }
     unsigned int cnt[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
     for (int it = 0; it < kDensePlanIters; ++it)
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const int n = __popc(comp4(f[it], k));       // occupancy bytes are 0 or 1
+            const int n = __popc(seg_nibble(comp4(f[it], k), tagx4));
 #pragma unroll
             for (int b = 0; b < 4; ++b) cnt[b] += (unsigned int)__popcll(__ballot(n == b + 1));
         }
@@ -197,8 +207,8 @@ __global__ __launch_bounds__(kDensePlanThreads) void dense_plan(const DensePlanA
     for (int it = 0; it < kDensePlanIters; ++it)
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const unsigned int v = comp4(f[it], k);
-            const int n = __popc(v);
+            const unsigned int nib = seg_nibble(comp4(f[it], k), tagx4);
+            const int n = __popc(nib);
             unsigned long long m[4];
 #pragma unroll
             for (int b = 0; b < 4; ++b) m[b] = __ballot(n == b + 1);
@@ -206,7 +216,6 @@ __global__ __launch_bounds__(kDensePlanThreads) void dense_plan(const DensePlanA
                 const int b = n - 1;
                 const unsigned long long mb = b == 0 ? m[0] : b == 1 ? m[1] : b == 2 ? m[2] : m[3];
                 const unsigned int base = b == 0 ? run[0] : b == 1 ? run[1] : b == 2 ? run[2] : run[3];
-                const unsigned int nib = (v & 1u) | ((v >> 7) & 2u) | ((v >> 14) & 4u) | ((v >> 21) & 8u);
                 const unsigned long long sj = (unsigned long long)(wbase + 256 * it + 4 * (long long)lane + k);
                 a.seg[(size_t)b * (size_t)NS + base + rank_below(mb)] = (unsigned int)(sj << 4) | nib;
             }
@@ -595,7 +604,7 @@ __global__ __launch_bounds__(kDenseThreads, 4) void dense_step(const DenseArgs a
                         o.tail = bt[0];
                         const unsigned long long so = ((unsigned long long)p << q_shift) | j;
                         rec_out[so] = o;
-                        a.flag_out[so] = 1u;
+                        a.flag_out[so] = (unsigned char)dense_tag(a.t);
                     }
 #pragma unroll
                     for (int k = 0; k + 1 < P; ++k) {
@@ -615,7 +624,7 @@ __global__ __launch_bounds__(kDenseThreads, 4) void dense_step(const DenseArgs a
                     o.tail = bt[p];
                     o.pad = 0ull;
                     rec_out[so] = o;
-                    a.flag_out[so] = 1u;
+                    a.flag_out[so] = (unsigned char)dense_tag(a.t);
                 }
             }
         }

@@ -127,7 +127,7 @@ __global__ __launch_bounds__(64) void static_initial(const StaticSetup a) {
     if (i == 0) {
         for (int k = 0; k < a.n_init; ++k) {
             const unsigned long long s = a.init_slot[k];
-            reinterpret_cast<unsigned char*>(a.flag0)[s] = 1u;
+            reinterpret_cast<unsigned char*>(a.flag0)[s] = (unsigned char)quapi_dev::dense_tag(0);
             quapi_dev::DenseRec r;
             r.w = make_double2(a.init_w[2 * k], a.init_w[2 * k + 1]);
             r.tail = 0ull;
@@ -329,6 +329,7 @@ extern "C" int quapi_run_static(const quapi_params* p, int n_steps, quapi_c64* r
         pa.plan = su.plan + ((t + 1) & 1);
         pa.plan_prev = su.plan + (t & 1);
         pa.reduce_t = t;
+        pa.clear_spent = quapi_dev::dense_clear_due(t);
         pa.epoch = (unsigned int)(t % 4095) + 1u;   // 1..4095: differs from the launch before
         if (quapi_dev::launch_dense_plan(pa, stream) != (int)hipSuccess) return QUAPI_EDEVICE;
     }
