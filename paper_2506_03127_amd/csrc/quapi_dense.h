@@ -27,7 +27,7 @@ constexpr int kDenseMinL = 6;                  // 4^L slots; short keys take the
 constexpr int kDenseMaxL = 12;
 constexpr int kDenseChunk = 64;                // segments per chunk (one wave)
 constexpr int kDensePlanThreads = 256;
-constexpr int kDensePlanIters = 2;             // 16-byte loads (four segments) per planner thread
+constexpr int kDensePlanIters = 1;             // 16-byte loads (four segments) per planner thread
 constexpr int kDenseRegion = kDensePlanThreads * kDensePlanIters * 4;   // segments per planner workgroup
 constexpr int kDenseMaxRegions = (1 << (2 * (kDenseMaxL - 1))) / kDenseRegion;
 
