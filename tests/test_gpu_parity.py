@@ -577,6 +577,31 @@ def test_direct_store_full_memory_spin_boson(Q, eta_cache):
     assert len(g.groups()[0]) == 4 ** 8
 
 
+def test_direct_store_long_run_across_occupancy_tags(Q, eta_cache):
+    """The direct-mapped store marks a slot with the step's tag, 1 + (t mod 255),
+    and clears each occupancy buffer only every 128 steps: 700 steps cross the
+    clears, the tag's wrap at 255 and 510, and the point where a stale tag
+    could first come back.  Against the oracle at every step (rho, counters)
+    and on the full group set at steps 255, 256, 510 and 700."""
+    K, mask, theta = 10, (0, 1, 2, 3, 4, 5), 1e-8           # L = 6
+    wl = W.structured_bath(K=K)
+    eta = eta_cache(wl, K)
+    o = oracle.Oracle(wl.H, wl.q, wl.dt, K, eta, wl.rho0, mask=mask, theta=theta, mode=oracle.POST, qbits=32)
+    g = Q.Propagator(wl.H, wl.q, wl.dt, K, eta, wl.rho0, mask=mask, theta=theta, mode=Q.QUAPI_POST, qbits=32,
+                     max_steps=700, merge=Q.QUAPI_MERGE_DIRECT)
+    assert Q.quapi_info(g.ctx)["store"] == Q.QUAPI_MERGE_DIRECT
+    done = 0
+    for t in (255, 256, 510, 700):
+        print(f"[parity] direct store, tagged occupancy, to step {t}", flush=True)
+        o.step(t - done)
+        g.step(t - done)
+        done = t
+        assert ambiguous(o, t) == 0
+        assert_groups(o, g)
+    assert_rho(o, g, 700)
+    assert_stats(o, g, 700)
+
+
 def test_store_requests_that_do_not_apply(Q, eta_cache):
     wl = W.structured_bath(K=12)
     eta = eta_cache(wl, 12)
