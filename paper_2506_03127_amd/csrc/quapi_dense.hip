@@ -10,12 +10,13 @@
 // (p, points 0..L-2) = p * 4^(L-1) + j: writing it needs no offset from any
 // other segment.
 //
-// Planner (between steps): reads the occupancy of every segment, lists the
-// nonempty segments by how many groups they hold (four lists, each in segment
-// order within a region; a decoupled look-back over epoch-tagged region
-// counts places the regions), clears the occupancy the finished step read (the
-// output of the step it plans), and reduces the finished step's per-workgroup
-// sums of rho(t) and counters in workgroup order (deterministic).
+// Planner (between steps): reads the occupancy of every segment (the bytes
+// holding the finished step's tag), lists the nonempty segments by how many
+// groups they hold (four lists, each in segment order within a region; a
+// decoupled look-back over epoch-tagged region counts places the regions),
+// now and then clears the occupancy buffer the planned step writes, and
+// reduces the finished step's per-workgroup sums of rho(t) and counters in
+// workgroup order (deterministic).
 //
 // Step: every wave takes chunks of 64 segments of one list (the lists of full
 // segments first), one segment per lane, so all lanes extend the same number
