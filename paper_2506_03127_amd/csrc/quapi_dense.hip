@@ -46,6 +46,7 @@ namespace {
 
 constexpr int P4 = 4;
 constexpr int kWavesD = kDenseThreads / 64;
+constexpr int kDies = 8;                                     // XCDs of an MI355X: workgroups go to them in turn
 constexpr int kPlanWavesD = kDensePlanThreads / 64;
 constexpr int kTabPts = 2;                                   // points per lag-sum table
 constexpr int kTabEntries = 1 << (2 * kTabPts);
@@ -329,15 +330,28 @@ __device__ inline double uniform_d(double v) {
 }
 
 // chunk c of the plan: list b (segments of b + 1 groups) and its first entry
-__device__ inline void chunk_of(const unsigned int (&n_seg)[4], unsigned int c, int& b, unsigned int& first) {
-    unsigned int kk = c;
-    b = 3;
-    for (; b > 0; --b) {
-        const unsigned int cb = (n_seg[b] + kDenseChunk - 1) / kDenseChunk;
-        if (kk < cb) break;
-        kk -= cb;
+// Chunks by die.  The lists are in segment order, so slice x of X of every list
+// covers about the same range of segments; the workgroups of die x (workgroup
+// x mod X: the order in which workgroups are handed to the dies) take slice x of
+// lists 3, 2, 1, 0 in turn.  The merged records and occupancy bytes of
+// neighbouring segments, which share lines, then meet in one L2.  Chunk v of
+// slice x: its list b and first entry, false past the slice's last chunk.
+__device__ inline bool slice_chunk(const unsigned int (&n_seg)[4], unsigned int x, unsigned int X, unsigned int v,
+                                   int& b, unsigned int& first) {
+    unsigned int kk = v;
+    bool found = false;
+#pragma unroll
+    for (int bb = 3; bb >= 0; --bb) {
+        const unsigned long long cb = (n_seg[bb] + kDenseChunk - 1) / kDenseChunk;
+        const unsigned int lo = (unsigned int)(cb * x / X), hi = (unsigned int)(cb * (x + 1) / X);
+        if (!found && kk < hi - lo) {
+            b = bb;
+            first = (lo + kk) * kDenseChunk;
+            found = true;
+        }
+        if (!found) kk -= hi - lo;
     }
-    first = kk * kDenseChunk;
+    return found;
 }
 
 // Q32: the quantised |w|^2 keeps no bit of the low word (qbits >= 32), so the
@@ -379,14 +393,16 @@ __global__ __launch_bounds__(kDenseThreads, 4) void dense_step(const DenseArgs a
     unsigned int n_seg[4];
 #pragma unroll
     for (int b = 0; b < 4; ++b) n_seg[b] = a.plan->n_seg[b];
-    const unsigned int n_chunks = a.plan->n_chunks;
-    const unsigned int stride = gridDim.x * kWavesD;
-    unsigned int c = blockIdx.x * kWavesD + wave;
+    const unsigned int X = min(gridDim.x, (unsigned int)kDies);
+    const unsigned int x = blockIdx.x % X;
+    const unsigned int stride = (gridDim.x - x + X - 1) / X * kWavesD;   // waves of slice x
+    // the wave's index in slice x (wave-uniform: kept in scalar registers)
+    unsigned int v = (unsigned int)__builtin_amdgcn_readfirstlane((int)(blockIdx.x / X * kWavesD + wave));
     int b = 0;
     unsigned int e = 0u, ent = 0u;
-    if (c < n_chunks) {
-        unsigned int first;
-        chunk_of(n_seg, c, b, first);
+    unsigned int first;
+    bool have = slice_chunk(n_seg, x, X, v, b, first);
+    if (have) {
         e = first + lane;
         if (e < n_seg[b]) ent = a.seg[(size_t)b * (size_t)NS + e];
     }
@@ -437,7 +453,7 @@ __global__ __launch_bounds__(kDenseThreads, 4) void dense_step(const DenseArgs a
 
     double dropped = 0.0;
     unsigned int n_surv = 0u;                               // this lane's surviving children
-    for (; c < n_chunks; c += stride) {
+    while (have) {
         if (e < n_seg[b]) {
             // ---- segment j of chunk c, its b + 1 parents in slot order
             const unsigned int j = ent >> 4;
@@ -630,10 +646,9 @@ __global__ __launch_bounds__(kDenseThreads, 4) void dense_step(const DenseArgs a
             }
         }
         // ---- the next chunk of this wave
-        const unsigned int cn = c + stride;
-        if (cn < n_chunks) {
-            unsigned int first;
-            chunk_of(n_seg, cn, b, first);
+        v += stride;
+        have = slice_chunk(n_seg, x, X, v, b, first);
+        if (have) {
             e = first + lane;
             if (e < n_seg[b]) ent = a.seg[(size_t)b * (size_t)NS + e];
         }
